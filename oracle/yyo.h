@@ -1,0 +1,89 @@
+/*
+ * yyo.h -- plain FP64 CPU oracle of the Yin-Yang artificial-compressibility
+ * direction-splitting time step (Takhirov, Frolov & Minev, "A direction
+ * splitting scheme for Navier-Stokes-Boussinesq system in spherical shell
+ * geometries", arXiv 1905.02300).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  The product
+ * path (the HIP library declared in include/yy.h) never calls, links or
+ * includes anything from this directory, and this directory includes
+ * nothing from the product.
+ *
+ * Conventions (shared with the product only through the written scheme):
+ *   - both patches are stored, patch 0 = Yin, patch 1 = Yang;
+ *   - every field array of one patch has (nr+2)*(nt+2)*(np+2) doubles,
+ *     logical indices -1..N in each direction, phi (k) fastest;
+ *     a face index f (0..N) is stored at logical index f;
+ *   - "MAC" layout = the field's unknowns plus its boundary faces, no
+ *     ghosts: centre (nr,nt,np), r-face (nr+1,nt,np), theta-face
+ *     (nr,nt+1,np), phi-face (nr,nt,np+1), per patch, patch slowest.
+ */
+#ifndef YYO_H
+#define YYO_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { YYO_T = 0, YYO_U1R, YYO_U1T, YYO_U1P, YYO_P1,
+       YYO_U2R, YYO_U2T, YYO_U2P, YYO_P2, YYO_NF };
+enum { YYO_LEV_N = 0, YYO_LEV_NM1 = 1, YYO_LEV_K = 2 };
+enum { YYO_MAC = 0, YYO_PADDED = 1 };
+/* explicit one-direction operators for yyo_apply_op */
+enum { YYO_OP_DRR = 0, YYO_OP_DTT, YYO_OP_DTT_HAT, YYO_OP_DPP, YYO_OP_DPP_HAT,
+       YYO_OP_LR, YYO_OP_LT, YYO_OP_LP };
+
+typedef struct yyo yyo;
+
+/* Create a shell.  delta <= 0 selects the one-cell overlap
+ * delta = pi / (2 (nt - 2)).  Returns NULL on bad arguments or when a
+ * donor window of the overlap interpolation would extrapolate. */
+yyo *yyo_create(int nr, int nt, int np, double r1, double r2, double delta);
+void yyo_destroy(yyo *h);
+/* pr, ra, tau (time step), chi (AC parameter), wall temperatures */
+int yyo_set_params(yyo *h, double pr, double ra, double tau, double chi,
+                   double t_inner, double t_outer);
+/* 0 = additive Schwarz (default), 1 = multiplicative (Yin then Yang) */
+int yyo_set_mode(yyo *h, int mode);
+int64_t yyo_field_count(const yyo *h, int field, int layout);
+int yyo_set_field(yyo *h, int field, int level, int layout, const double *src);
+int yyo_get_field(const yyo *h, int field, int level, int layout, double *dst);
+/* forcing of T, u_r, u_theta, u_phi (fields YYO_T, YYO_U1R, YYO_U1T,
+ * YYO_U1P; it applies to both velocity systems), MAC layout; NULL clears */
+int yyo_set_forcing(yyo *h, int field, const double *src);
+/* Advance one time step with K Schwarz iterations. */
+int yyo_step(yyo *h, int K);
+/* norms of the last step: out[k][patch][10] = per-field l2 norms of the
+ * iterate increment (T,u1r,u1t,u1p,p1,u2r,u2t,u2p,p2) and of Div_h u2^k */
+int yyo_get_norms(const yyo *h, double *out, int cap);
+
+/* ---- pieces of the step, exposed for the pin tests ---- */
+/* fill ghosts/boundary faces of every field at `level` from the other
+ * patch, then apply the wall rules */
+int yyo_fill(yyo *h, int level);
+/* one direction-split solve (I - tau/2 L_{field,dir}) y = x on every line;
+ * x, y padded arrays of both patches (only unknowns are read/written;
+ * other points of y are set to zero) */
+int yyo_sweep(yyo *h, int field, int dir, const double *x, double *y);
+/* apply an explicit operator at the field's unknowns (padded in/out) */
+int yyo_apply_op(yyo *h, int field, int op, const double *x, double *y);
+/* the residual R^k of a field (padded out, zero off the unknowns) for the
+ * current working iterate; s = velocity system (1 or 2) */
+int yyo_residual(yyo *h, int field, double *out);
+/* extrapolated levels psi* = 1.5 psi^n - 0.5 psi^{n-1} for every field */
+int yyo_extrapolate(yyo *h);
+/* plain Thomas algorithm: lo[0] and up[n-1] are ignored */
+int yyo_thomas(int n, const double *lo, const double *di, const double *up,
+               const double *rhs, double *x);
+/* coordinates of the Yang image of a Yin point (and vice versa) */
+void yyo_involution(double th, double ph, double *th2, double *ph2);
+/* 2x2 matrix taking (v_th, v_ph) of the other patch at the image point to
+ * this patch's components at (th, ph) */
+void yyo_rotation(double th, double ph, double m[4]);
+int yyo_omp_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

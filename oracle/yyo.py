@@ -1,0 +1,176 @@
+"""ctypes wrapper of the C oracle (oracle/yyo.c).
+
+TEST INFRASTRUCTURE ONLY: the product package never imports this module.
+Arrays cross the boundary as contiguous float64 numpy arrays.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+T, U1R, U1T, U1P, P1, U2R, U2T, U2P, P2 = range(9)
+NF = 9
+LEV_N, LEV_NM1, LEV_K = 0, 1, 2
+MAC, PADDED = 0, 1
+OP_DRR, OP_DTT, OP_DTT_HAT, OP_DPP, OP_DPP_HAT, OP_LR, OP_LT, OP_LP = range(8)
+FIELD_NAMES = ["T", "u1r", "u1t", "u1p", "p1", "u2r", "u2t", "u2p", "p2"]
+NORM_NAMES = FIELD_NAMES + ["div_u2"]
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        vp, d, i, dp = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
+        L.yyo_create.restype = vp
+        L.yyo_create.argtypes = [i, i, i, d, d, d]
+        L.yyo_destroy.argtypes = [vp]
+        L.yyo_set_params.argtypes = [vp, d, d, d, d, d, d]
+        L.yyo_set_mode.argtypes = [vp, i]
+        L.yyo_field_count.restype = ctypes.c_int64
+        L.yyo_field_count.argtypes = [vp, i, i]
+        L.yyo_set_field.argtypes = [vp, i, i, i, dp]
+        L.yyo_get_field.argtypes = [vp, i, i, i, dp]
+        L.yyo_set_forcing.argtypes = [vp, i, dp]
+        L.yyo_step.argtypes = [vp, i]
+        L.yyo_get_norms.argtypes = [vp, dp, i]
+        L.yyo_fill.argtypes = [vp, i]
+        L.yyo_sweep.argtypes = [vp, i, i, dp, dp]
+        L.yyo_apply_op.argtypes = [vp, i, i, dp, dp]
+        L.yyo_residual.argtypes = [vp, i, dp]
+        L.yyo_extrapolate.argtypes = [vp]
+        L.yyo_thomas.argtypes = [i, dp, dp, dp, dp, dp]
+        L.yyo_involution.argtypes = [d, d, dp, dp]
+        L.yyo_rotation.argtypes = [d, d, dp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def thomas(lo, di, up, rhs):
+    n = len(di)
+    x = np.zeros(n)
+    lo, di, up, rhs = map(_f64, (lo, di, up, rhs))
+    lib().yyo_thomas(n, _ptr(lo), _ptr(di), _ptr(up), _ptr(rhs), _ptr(x))
+    return x
+
+
+def involution(th, ph):
+    a, b = ctypes.c_double(), ctypes.c_double()
+    lib().yyo_involution(th, ph, ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def rotation(th, ph):
+    m = np.zeros(4)
+    lib().yyo_rotation(th, ph, _ptr(m))
+    return m.reshape(2, 2)
+
+
+def omp_threads():
+    return lib().yyo_omp_threads()
+
+
+class Shell:
+    """One Yin-Yang shell held by the oracle."""
+
+    def __init__(self, nr, nt, np_, r1=0.5, r2=1.0, delta=0.0):
+        self.nr, self.nt, self.np = nr, nt, np_
+        self.h = lib().yyo_create(nr, nt, np_, r1, r2, delta)
+        if not self.h:
+            raise ValueError("oracle rejected the grid (arguments or donor-window fit)")
+
+    def close(self):
+        if self.h:
+            lib().yyo_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, pr=1.0, ra=0.0, tau=1e-3, chi=1.0, t_inner=0.0, t_outer=0.0):
+        if lib().yyo_set_params(self.h, pr, ra, tau, chi, t_inner, t_outer) != 0:
+            raise ValueError("bad parameters")
+
+    def set_mode(self, mode):
+        if lib().yyo_set_mode(self.h, mode) != 0:
+            raise ValueError("bad mode")
+
+    def padded_shape(self):
+        return (2, self.nr + 2, self.nt + 2, self.np + 2)
+
+    def mac_shape(self, field):
+        n = [self.nr, self.nt, self.np]
+        loc = {U1R: 0, U2R: 0, U1T: 1, U2T: 1, U1P: 2, U2P: 2}.get(field)
+        if loc is not None:
+            n[loc] += 1
+        return (2, *n)
+
+    def set_field(self, field, level, a, layout=MAC):
+        a = _f64(a)
+        if a.size != lib().yyo_field_count(self.h, field, layout):
+            raise ValueError("size mismatch")
+        lib().yyo_set_field(self.h, field, level, layout, _ptr(a))
+
+    def get_field(self, field, level=LEV_N, layout=MAC):
+        shape = self.padded_shape() if layout == PADDED else self.mac_shape(field)
+        a = np.zeros(shape)
+        lib().yyo_get_field(self.h, field, level, layout, _ptr(a))
+        return a
+
+    def set_forcing(self, field, a):
+        if a is None:
+            lib().yyo_set_forcing(self.h, field, None)
+            return
+        a = _f64(a)
+        assert a.shape == self.mac_shape(field)
+        lib().yyo_set_forcing(self.h, field, _ptr(a))
+
+    def step(self, K):
+        if lib().yyo_step(self.h, K) != 0:
+            raise RuntimeError("step failed")
+
+    def norms(self, K):
+        out = np.zeros(K * 2 * 10)
+        lib().yyo_get_norms(self.h, _ptr(out), out.size)
+        return out.reshape(K, 2, 10)
+
+    def fill(self, level):
+        lib().yyo_fill(self.h, level)
+
+    def extrapolate(self):
+        lib().yyo_extrapolate(self.h)
+
+    def sweep(self, field, d, x):
+        x = _f64(x)
+        y = np.zeros(self.padded_shape())
+        if lib().yyo_sweep(self.h, field, d, _ptr(x), _ptr(y)) != 0:
+            raise ValueError("bad sweep")
+        return y
+
+    def apply_op(self, field, op, x):
+        x = _f64(x)
+        y = np.zeros(self.padded_shape())
+        lib().yyo_apply_op(self.h, field, op, _ptr(x), _ptr(y))
+        return y
+
+    def residual(self, field):
+        y = np.zeros(self.padded_shape())
+        lib().yyo_residual(self.h, field, _ptr(y))
+        return y
