@@ -1,0 +1,181 @@
+/*
+ * yy.h -- C-ABI of the MI355X (gfx950) library libyy.so: one time step of
+ * the second-order artificial-compressibility (AC) direction-splitting
+ * scheme for incompressible Navier-Stokes-Boussinesq flow on an overset
+ * Yin-Yang spherical shell with MAC finite differences (Takhirov, Frolov &
+ * Minev, arXiv 1905.02300).
+ *
+ * Problem statement (Sec. 1, eq. eq_ns and eq_heat_convec): in the shell
+ * R1 <= r <= R2 advance velocity u, pressure p and temperature T under
+ *   du/dt + (u.grad)u + grad p - Pr lap u = Pr Ra T e_r,  div u = 0,
+ *   dT/dt + u.grad T - lap T = 0,
+ * with u = 0 and T = T_wall on both spheres.  The domain is covered by two
+ * identical latitude-longitude patches (Sec. 2: Yin, and Yang obtained by
+ * (x,y,z) -> (-x,z,y)), each r in [R1,R2], theta in [pi/4-d, 3pi/4+d],
+ * phi in [-3pi/4-d, 3pi/4+d], coupled by Schwarz iterations with Lagrange
+ * interpolation of boundary data (Sec. 4).  Each step solves the first-order
+ * AC system (u1, p1) (eq. ac1) and the bootstrapped second-order system
+ * (u2, p2) (eq. ac2); u = u2 and p = p2 are the outputs.
+ *
+ * General conventions
+ *  - Every function returns a yy_status (0 = success).  No exception or
+ *    abort crosses the ABI.  A handle is not thread-safe; distinct handles
+ *    are independent.
+ *  - Memory: the caller allocates one device workspace (size from
+ *    yy_workspace_bytes) and owns it and every I/O buffer; the library
+ *    allocates no device memory.  The workspace must stay valid until
+ *    yy_destroy.  The handle itself is a small host object.
+ *  - Streams: all device work is enqueued on the stream passed (NULL = the
+ *    default stream) and is asynchronous unless stated.  Only
+ *    yy_get_norms synchronises (the stream it is given).
+ *  - Field I/O is in double precision whatever the compute precision.
+ *    "MAC" layout: the field's unknowns plus its boundary faces, both
+ *    patches, [patch][i][j][k], k (phi) fastest: centres (Nr,Nt,Np);
+ *    u_r on r-faces (Nr+1,Nt,Np); u_theta on theta-faces (Nr,Nt+1,Np);
+ *    u_phi on phi-faces (Nr,Nt,Np+1).  "PADDED" layout: (2,Nr+2,Nt+2,Np+2)
+ *    including one ghost layer; logical index -1..N per direction at
+ *    storage index 0..N+1, face f at logical index f.
+ */
+#ifndef YY_H
+#define YY_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    YY_OK = 0,
+    YY_ERR_ARG = -1,        /* bad argument (null pointer, size, id, value) */
+    YY_ERR_GEOMETRY = -2,   /* an overlap-interpolation window would extrapolate */
+    YY_ERR_WORKSPACE = -3,  /* workspace too small or misaligned */
+    YY_ERR_HIP = -4,        /* a HIP runtime call failed */
+    YY_ERR_NONFINITE = -5,  /* a Schwarz or divergence norm was NaN/Inf */
+    YY_ERR_STATE = -6       /* call out of order (e.g. step before params) */
+} yy_status;
+
+typedef enum { YY_FP64 = 0, YY_FP32_MIXED = 1 } yy_precision;
+typedef enum { YY_ADDITIVE = 0, YY_MULTIPLICATIVE = 1 } yy_schwarz_mode;
+typedef enum { YY_MAC = 0, YY_PADDED = 1 } yy_layout;
+typedef enum { YY_LEVEL_N = 0, YY_LEVEL_NM1 = 1, YY_LEVEL_K = 2 } yy_level;
+
+/* Fields.  T, p1, p2 at cell centres; u*r, u*t, u*p on r-, theta-, phi-faces. */
+typedef enum {
+    YY_T = 0, YY_U1R, YY_U1T, YY_U1P, YY_P1, YY_U2R, YY_U2T, YY_U2P, YY_P2,
+    YY_NFIELDS
+} yy_field;
+
+/* Norm slots of yy_get_norms: l2 (midpoint rule, weight r^2 sin(theta)
+ * dr dtheta dphi) of each field's iterate increment, and of Div_h u2^k. */
+#define YY_NNORMS 10
+
+typedef struct {
+    int32_t nr, nt, np;     /* cells per patch along r, theta, phi */
+    double r1, r2;          /* shell radii, 0 < r1 < r2 */
+    double delta;           /* overlap d; <= 0 selects d = pi/(2(nt-2)),
+                               which makes dtheta = d (one-cell overlap) */
+} yy_grid;
+
+typedef struct {
+    double pr, ra;          /* Prandtl and Rayleigh numbers (Sec. 1) */
+    double dt;              /* time step tau > 0 */
+    double chi;             /* AC parameter chi > 0 (Sec. 3.3, O(1)) */
+    double t_inner, t_outer;/* wall temperatures at r = R1, R2 */
+    int32_t mode;           /* yy_schwarz_mode */
+} yy_params;
+
+typedef struct yy_shell yy_shell;
+
+/* Bytes of device workspace a shell needs.  prec: yy_precision.
+ * Errors: YY_ERR_ARG (null, nr < 2, nt < 6, np < 6, r1 <= 0, r2 <= r1). */
+int yy_workspace_bytes(const yy_grid *g, int32_t prec, uint64_t *bytes);
+
+/* Create a shell on the current device inside the caller's workspace
+ * (256-byte aligned, at least yy_workspace_bytes).  Builds, in FP64 on the
+ * host, the metric tables (Sec. 2, 3.2) and the overlap-interpolation
+ * tables (Sec. 4: donor windows, cubic Lagrange weights, tangential vector
+ * rotation per target) and uploads them (synchronously, on the null
+ * stream).  Fields start at zero.
+ * Errors: YY_ERR_ARG, YY_ERR_GEOMETRY (a target outside its donor span),
+ * YY_ERR_WORKSPACE, YY_ERR_HIP.  On error *out is NULL. */
+int yy_create(const yy_grid *g, int32_t prec, void *dev_ws, uint64_t ws_bytes, yy_shell **out);
+
+/* Pr, Ra, tau, chi, wall temperatures, Schwarz mode.  Required before
+ * yy_step.  Errors: YY_ERR_ARG (dt, chi or pr not > 0, unknown mode). */
+int yy_set_params(yy_shell *s, const yy_params *p);
+
+/* Copy one field of one time level from / to a device buffer of doubles in
+ * the given layout.  Setting a field marks the shell for a ghost refresh
+ * of levels n and n-1 at the next step.  level: yy_level.
+ * Errors: YY_ERR_ARG. */
+int yy_set_field(yy_shell *s, int32_t field, int32_t level, int32_t layout,
+                 const double *dev_src, hipStream_t stream);
+int yy_get_field(yy_shell *s, int32_t field, int32_t level, int32_t layout,
+                 double *dev_dst, hipStream_t stream);
+
+/* Body forcing of T, u_r, u_theta, u_phi (field = YY_T, YY_U1R, YY_U1T,
+ * YY_U1P; it acts on both velocity systems), MAC layout, taken as the value
+ * at t^{n+1/2} of the next step; dev_src == NULL removes it.
+ * Errors: YY_ERR_ARG. */
+int yy_set_forcing(yy_shell *s, int32_t field, const double *dev_src, hipStream_t stream);
+
+/* Advance one time step n -> n+1 with n_schwarz Schwarz iterations
+ * (Sec. 4 Algorithm with the splitting-error reduction eq. er): per
+ * iteration, refresh every field's ghosts from the other patch, solve T,
+ * u1 (r, theta, phi), p1, u2 (r, theta, phi), p2, each velocity/T solve as
+ * a residual and three direction-split tridiagonal sweeps (Sec. 4).
+ * Asynchronous.  Errors: YY_ERR_ARG (n_schwarz < 1 or > 64), YY_ERR_STATE
+ * (params not set), YY_ERR_HIP. */
+int yy_step(yy_shell *s, int32_t n_schwarz, hipStream_t stream);
+
+/* Norms of the last step, synchronising the stream: out[k][patch][slot]
+ * for k < n_schwarz, slot order T,u1r,u1t,u1p,p1,u2r,u2t,u2p,p2,div(u2).
+ * Returns the number of values available (it writes at most cap), or
+ * YY_ERR_NONFINITE if any is NaN/Inf (the values are still written). */
+int yy_get_norms(yy_shell *s, double *host_out, int32_t cap, hipStream_t stream);
+
+/* Release the handle (the workspace stays the caller's). */
+int yy_destroy(yy_shell *s);
+
+/* Static description of a status code. */
+const char *yy_strerror(int status);
+
+/* ---- pieces of the step, for kernel-level tests and benchmarks ---- */
+
+/* Internal padded layout of compute-precision arrays: dims = {2, nr+2,
+ * nt+2, pitch}, pitch >= np+2 (elements).  elem_bytes = 8 or 4. */
+int yy_internal_dims(const yy_shell *s, int64_t dims[4], int32_t *elem_bytes);
+
+/* Refresh ghosts and boundary faces of every field at `level` from the
+ * other patch, then apply the wall rules. */
+int yy_fill(yy_shell *s, int32_t level, hipStream_t stream);
+
+/* psi* = 1.5 psi^n - 0.5 psi^{n-1} for T and both velocities. */
+int yy_extrapolate(yy_shell *s, hipStream_t stream);
+
+/* One direction-split solve (I - tau/2 L_{field,dir}) y = x along every
+ * line of direction dir (0 = r, 1 = theta, 2 = phi) on both patches, with
+ * the coefficients of field's split operator (Sec. 3.2-3.3; advection by
+ * the current extrapolated u2).  x, y: device arrays in the internal
+ * layout and compute precision; only the field's unknowns are read and
+ * written; x == y is allowed.  Errors: YY_ERR_ARG. */
+int yy_sweep(yy_shell *s, int32_t field, int32_t dir, const void *dev_x, void *dev_y,
+             hipStream_t stream);
+
+/* The same line solve with constant-in-line coefficients from the metric
+ * tables only (no advection): the factors (I - tau/2 Pr D) with D = D_rr,
+ * Dhat_thth, Dhat_phph of a cell-centred scalar (Sec. 3.2). */
+int yy_sweep_diffusion(yy_shell *s, int32_t dir, const void *dev_x, void *dev_y,
+                       hipStream_t stream);
+
+/* tau * R^k of a field for the current working iterate (internal layout,
+ * compute precision, written at the unknowns only). */
+int yy_residual(yy_shell *s, int32_t field, void *dev_out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,644 @@
+// yy_host.cpp -- host side of libyy.so: C-ABI entry points (include/yy.h),
+// metric and overlap-interpolation tables, workspace layout, and the
+// schedule of one time step (Sec. 4 Algorithm, additive Schwarz).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/yy.h"
+#include "yy_internal.h"
+
+using namespace yy;
+
+namespace {
+
+constexpr int MAXK = 64;
+constexpr int64_t ALIGN = 256;
+
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    Dims d;
+    int64_t field_elems;     // elements of one field array (both patches)
+    int prec;
+    int64_t ncc, nvt, nvp;   // interpolation targets per class
+    // byte offsets
+    int64_t off_fields, off_p, off_tab_r, off_tab_d, off_fill, off_partial, off_norms, total;
+    int64_t elem;            // bytes per compute element
+    int nR;                  // compute-precision arrays
+};
+
+int64_t ntab_r(const Dims &d) { return (d.nr + 2) + (d.nr + 3); }
+int64_t ntab_t(const Dims &d) { return 2 * (d.nt + 2) + 2 * (d.nt + 3); }
+
+// compute-precision arrays: T (3 levels) + T*, u (2x3x3) + u* (2x3),
+// forcing (4), residual, Thomas scratch
+constexpr int N_R_ARRAYS = 4 + 18 + 6 + 4 + 2;
+
+bool valid_grid(const yy_grid *g)
+{
+    return g && g->nr >= 2 && g->nt >= 6 && g->np >= 6 && g->nr <= 4096 && g->nt <= 4096 &&
+           g->np <= 8192 && g->r1 > 0.0 && g->r2 > g->r1 && std::isfinite(g->r1) &&
+           std::isfinite(g->r2);
+}
+
+Layout make_layout(const yy_grid *g, int prec)
+{
+    Layout L{};
+    L.prec = prec;
+    L.d.nr = g->nr;
+    L.d.nt = g->nt;
+    L.d.np = g->np;
+    L.d.sJ = align_up(g->np + 2, 16);
+    L.d.sI = (int64_t)(g->nt + 2) * L.d.sJ;
+    L.d.sP = (int64_t)(g->nr + 2) * L.d.sI;
+    L.field_elems = 2 * L.d.sP;
+    L.elem = prec == YY_FP64 ? 8 : 4;
+    L.ncc = 2LL * g->np + 2LL * g->nt;
+    L.nvt = 2LL * g->np + 2LL * (g->nt - 1);
+    L.nvp = 2LL * g->nt + 2LL * (g->np - 1);
+    int64_t o = 0;
+    L.off_fields = o;
+    o += align_up(N_R_ARRAYS * L.field_elems * L.elem, ALIGN);
+    L.off_p = o;
+    o += align_up(4 * L.field_elems * 8, ALIGN);
+    L.off_tab_r = o;
+    o += align_up((ntab_r(L.d) + ntab_t(L.d)) * L.elem, ALIGN);
+    L.off_tab_d = o;
+    o += align_up((ntab_r(L.d) + ntab_t(L.d)) * 8, ALIGN);
+    L.off_fill = o;
+    o += align_up(L.ncc * (int64_t)sizeof(FillScalar) + (L.nvt + L.nvp) * (int64_t)sizeof(FillVector), ALIGN);
+    L.off_partial = o;
+    o += align_up((int64_t)NSLOT * 2 * NBMAX * 8, ALIGN);
+    L.off_norms = o;
+    o += align_up((int64_t)MAXK * 2 * NSLOT * 8, ALIGN);
+    L.total = o;
+    return L;
+}
+
+// ---------------- geometry (Sec. 2) ----------------
+struct Frame {
+    double th0, ph0, dth, dph, dr, r1, r2, delta;
+};
+
+// The Yin <-> Yang map (x,y,z) -> (-x,z,y) is an involution: the same
+// formula gives the other patch's (theta, phi) of a point of either patch.
+void other_coords(double th, double ph, double &th2, double &ph2)
+{
+    const double st = std::sin(th);
+    double c = st * std::sin(ph);       // y = cos(theta')
+    c = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
+    th2 = std::acos(c);
+    ph2 = std::atan2(std::cos(th), -st * std::cos(ph));
+}
+
+// Rows of the 2x2 matrix taking the other patch's (v_theta', v_phi') at the
+// image point to this patch's (v_theta, v_phi): dot products of the local
+// unit vectors, the other patch's expressed in this patch's frame.
+void rotation(double th, double ph, double m[2][2])
+{
+    double th2, ph2;
+    other_coords(th, ph, th2, ph2);
+    const double et[3] = {std::cos(th) * std::cos(ph), std::cos(th) * std::sin(ph), -std::sin(th)};
+    const double ep[3] = {-std::sin(ph), std::cos(ph), 0.0};
+    const double eto[3] = {-std::cos(th2) * std::cos(ph2), -std::sin(th2), std::cos(th2) * std::sin(ph2)};
+    const double epo[3] = {std::sin(ph2), 0.0, std::cos(ph2)};
+    auto dot = [](const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; };
+    m[0][0] = dot(et, eto);
+    m[0][1] = dot(et, epo);
+    m[1][0] = dot(ep, eto);
+    m[1][1] = dot(ep, epo);
+}
+
+// Cubic Lagrange window on n uniform donor nodes x0 + m h: first node
+// (clamped so the four nodes exist) and weights.  false = outside the span.
+bool window(double x, double x0, double h, int n, int &m0, double w[4])
+{
+    const double s = (x - x0) / h;
+    if (!(s >= 0.0 && s <= (double)(n - 1)) || n < 4) return false;
+    int b = (int)std::floor(s) - 1;
+    if (b < 0) b = 0;
+    if (b > n - 4) b = n - 4;
+    m0 = b;
+    const double u = s - b;
+    w[0] = -(u - 1.0) * (u - 2.0) * (u - 3.0) / 6.0;
+    w[1] = u * (u - 2.0) * (u - 3.0) / 2.0;
+    w[2] = -u * (u - 1.0) * (u - 3.0) / 2.0;
+    w[3] = u * (u - 1.0) * (u - 2.0) / 6.0;
+    return true;
+}
+
+// donor grid of the other patch along theta or phi: its unknowns only
+struct Axis {
+    double x0, h;
+    int n, off;
+};
+Axis centres(double start, double h, int N) { return {start + 0.5 * h, h, N, 0}; }
+Axis faces(double start, double h, int N) { return {start + h, h, N - 1, 1}; }
+
+bool build_fill(const Frame &F, const Dims &d, std::vector<FillScalar> &cc,
+                std::vector<FillVector> &vt, std::vector<FillVector> &vp)
+{
+    const Axis tc = centres(F.th0, F.dth, d.nt), tfc = faces(F.th0, F.dth, d.nt);
+    const Axis pc = centres(F.ph0, F.dph, d.np), pfc = faces(F.ph0, F.dph, d.np);
+    auto thc = [&](int j) { return F.th0 + (j + 0.5) * F.dth; };
+    auto thf = [&](int j) { return F.th0 + j * F.dth; };
+    auto phc = [&](int k) { return F.ph0 + (k + 0.5) * F.dph; };
+    auto phf = [&](int k) { return F.ph0 + k * F.dph; };
+    bool ok = true;
+    auto add_scalar = [&](int j, int k) {
+        double a, b;
+        other_coords(thc(j), phc(k), a, b);
+        FillScalar e{};
+        int mt = 0, mp = 0;
+        ok = ok && window(a, tc.x0, tc.h, tc.n, mt, e.wt) && window(b, pc.x0, pc.h, pc.n, mp, e.wp);
+        e.tj = j; e.tk = k; e.dj = mt + tc.off; e.dk = mp + pc.off;
+        cc.push_back(e);
+    };
+    auto add_vector = [&](std::vector<FillVector> &v, double th, double ph, int j, int k, int row) {
+        double a, b, m[2][2];
+        other_coords(th, ph, a, b);
+        rotation(th, ph, m);
+        FillVector e{};
+        int m1 = 0, m2 = 0, m3 = 0, m4 = 0;
+        ok = ok && window(a, tfc.x0, tfc.h, tfc.n, m1, e.wtA) && window(b, pc.x0, pc.h, pc.n, m2, e.wpA);
+        ok = ok && window(a, tc.x0, tc.h, tc.n, m3, e.wtB) && window(b, pfc.x0, pfc.h, pfc.n, m4, e.wpB);
+        e.tj = j; e.tk = k;
+        e.tjA = m1 + tfc.off; e.tkA = m2 + pc.off;
+        e.tjB = m3 + tc.off; e.tkB = m4 + pfc.off;
+        e.ma = m[row][0];
+        e.mb = m[row][1];
+        v.push_back(e);
+    };
+    // centre-type in theta and phi: ghost rows, then ghost columns
+    for (int k = 0; k < d.np; k++) { add_scalar(-1, k); add_scalar(d.nt, k); }
+    for (int j = 0; j < d.nt; j++) { add_scalar(j, -1); add_scalar(j, d.np); }
+    // u_theta: boundary faces j = 0, Nt; phi ghosts of interior faces
+    for (int k = 0; k < d.np; k++) {
+        add_vector(vt, thf(0), phc(k), 0, k, 0);
+        add_vector(vt, thf(d.nt), phc(k), d.nt, k, 0);
+    }
+    for (int j = 1; j < d.nt; j++) {
+        add_vector(vt, thf(j), phc(-1), j, -1, 0);
+        add_vector(vt, thf(j), phc(d.np), j, d.np, 0);
+    }
+    // u_phi: boundary faces k = 0, Np; theta ghosts of interior faces
+    for (int j = 0; j < d.nt; j++) {
+        add_vector(vp, thc(j), phf(0), j, 0, 1);
+        add_vector(vp, thc(j), phf(d.np), j, d.np, 1);
+    }
+    for (int k = 1; k < d.np; k++) {
+        add_vector(vp, thc(-1), phf(k), -1, k, 1);
+        add_vector(vp, thc(d.nt), phf(k), d.nt, k, 1);
+    }
+    return ok;
+}
+
+template <typename R> void host_tables(const Frame &F, const Dims &d, std::vector<R> &v)
+{
+    v.clear();
+    for (int i = -1; i <= d.nr; i++) v.push_back((R)(F.r1 + (i + 0.5) * F.dr));
+    for (int f = -1; f <= d.nr + 1; f++) v.push_back((R)(F.r1 + f * F.dr));
+    for (int j = -1; j <= d.nt; j++) v.push_back((R)std::sin(F.th0 + (j + 0.5) * F.dth));
+    for (int j = -1; j <= d.nt; j++) v.push_back((R)std::cos(F.th0 + (j + 0.5) * F.dth));
+    for (int f = -1; f <= d.nt + 1; f++) v.push_back((R)std::sin(F.th0 + f * F.dth));
+    for (int f = -1; f <= d.nt + 1; f++) v.push_back((R)std::cos(F.th0 + f * F.dth));
+}
+
+template <typename R> void bind_geo(Geo<R> &g, const R *base, const Dims &d, const Frame &F)
+{
+    g.rc = base;
+    g.rf = g.rc + (d.nr + 2);
+    g.sc = g.rf + (d.nr + 3);
+    g.cc = g.sc + (d.nt + 2);
+    g.sf = g.cc + (d.nt + 2);
+    g.cf = g.sf + (d.nt + 3);
+    g.dr = (R)F.dr;
+    g.dth = (R)F.dth;
+    g.dph = (R)F.dph;
+    g.r1 = (R)F.r1;
+    const double th1 = M_PI / 4.0 - F.delta;
+    g.cphat = (R)(1.0 / (F.r1 * F.r1 * std::sin(th1) * std::sin(th1) * F.dph * F.dph));
+}
+
+template <typename R> void set_coefs(Geo<R> &g, const yy_params &p)
+{
+    g.ht = (R)(0.5 * p.dt);
+    g.tau = (R)p.dt;
+    g.inv_tau = (R)(1.0 / p.dt);
+    g.pr = (R)p.pr;
+    g.ic = (R)(1.0 / (2.0 * p.chi));
+    g.prra = (R)(p.pr * p.ra);
+    g.inv_chi = 1.0 / p.chi;
+}
+
+}  // namespace
+
+struct yy_shell {
+    Layout L;
+    Frame F;
+    yy_params prm;
+    bool have_params = false, need_fill = true;
+    int sticky = YY_OK;
+    int last_k = 0;
+    char *ws = nullptr;
+    Geo<double> gd, g64;
+    Geo<float> g32;
+    State<double> s64;
+    State<float> s32;
+    double *pres[2][2];
+    FillScalar *fcc = nullptr;
+    FillVector *fvt = nullptr, *fvp = nullptr;
+    double *partial = nullptr, *norms = nullptr;
+    int nblocks[NSLOT];
+    bool has_force[4] = {false, false, false, false};
+    void *force_ptr[4];
+};
+
+namespace {
+
+template <typename R> State<R> &state_of(yy_shell *s);
+template <> State<double> &state_of<double>(yy_shell *s) { return s->s64; }
+template <> State<float> &state_of<float>(yy_shell *s) { return s->s32; }
+template <typename R> Geo<R> &geo_of(yy_shell *s);
+template <> Geo<double> &geo_of<double>(yy_shell *s) { return s->g64; }
+template <> Geo<float> &geo_of<float>(yy_shell *s) { return s->g32; }
+
+template <typename R> void bind_state(yy_shell *s)
+{
+    State<R> &st = state_of<R>(s);
+    R *base = (R *)(s->ws + s->L.off_fields);
+    const int64_t n = s->L.field_elems;
+    int a = 0;
+    auto next = [&]() { return base + (a++) * n; };
+    for (int l = 0; l < 3; l++) st.T[l] = next();
+    st.Ts = next();
+    for (int y = 0; y < 2; y++)
+        for (int c = 0; c < 3; c++)
+            for (int l = 0; l < 3; l++) st.u[y][c][l] = next();
+    for (int y = 0; y < 2; y++)
+        for (int c = 0; c < 3; c++) st.us[y][c] = next();
+    for (int c = 0; c < 4; c++) {
+        s->force_ptr[c] = next();
+        st.force[c] = nullptr;
+    }
+    st.res = next();
+    st.cb = next();
+    double *pb = (double *)(s->ws + s->L.off_p);
+    for (int y = 0; y < 2; y++)
+        for (int l = 0; l < 2; l++) st.p[y][l] = pb + (y * 2 + l) * n;
+}
+
+int loc_of(int f)
+{
+    switch (f) {
+    case YY_U1R: case YY_U2R: return FR;
+    case YY_U1T: case YY_U2T: return FT;
+    case YY_U1P: case YY_U2P: return FP;
+    default: return CC;
+    }
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? YY_OK : YY_ERR_HIP; }
+
+template <typename R> R *field_ptr(yy_shell *s, int f, int lev)
+{
+    State<R> &st = state_of<R>(s);
+    if (f == YY_T) return st.T[lev];
+    const int y = f >= YY_U2R ? 1 : 0;
+    const int c = f - (y ? YY_U2R : YY_U1R);
+    return st.u[y][c][lev];
+}
+
+template <typename R> void do_fill(yy_shell *s, int lev, int pmask, hipStream_t st)
+{
+    Ops<R>::fill(s->L.d, state_of<R>(s), lev, s->fcc, (int)s->L.ncc, s->fvt, (int)s->L.nvt, s->fvp,
+                 (int)s->L.nvp, s->prm.t_inner, s->prm.t_outer, pmask, st);
+}
+
+template <typename R> void solve_field(yy_shell *s, int f, hipStream_t st)
+{
+    State<R> &S = state_of<R>(s);
+    const int loc = loc_of(f);
+    static const int order[4][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1}, {0, 1, 2}};
+    Ops<R>::residual(s->L.d, geo_of<R>(s), S, f, S.res, st);
+    Ops<R>::sweep(s->L.d, geo_of<R>(s), s->gd, S, f, order[loc][0], S.res, S.res, 0, nullptr, nullptr, 0, st);
+    Ops<R>::sweep(s->L.d, geo_of<R>(s), s->gd, S, f, order[loc][1], S.res, S.res, 0, nullptr, nullptr, 0, st);
+    Ops<R>::sweep(s->L.d, geo_of<R>(s), s->gd, S, f, order[loc][2], S.res, S.res, 1,
+                  s->partial + (int64_t)f * 2 * NBMAX, &s->nblocks[f], 0, st);
+}
+
+template <typename R> int step_impl(yy_shell *s, int K, hipStream_t st)
+{
+    State<R> &S = state_of<R>(s);
+    if (s->need_fill) {
+        do_fill<R>(s, 0, 3, st);
+        do_fill<R>(s, 1, 3, st);
+        s->need_fill = false;
+    }
+    Ops<R>::extrap(s->L.d, S, st);
+    Ops<R>::copy_levels(s->L.d, S, 0, 2, st);
+    for (int k = 0; k < K; k++) {
+        do_fill<R>(s, 2, 3, st);
+        solve_field<R>(s, YY_T, st);
+        solve_field<R>(s, YY_U1R, st);
+        solve_field<R>(s, YY_U1T, st);
+        solve_field<R>(s, YY_U1P, st);
+        Ops<R>::pressure(s->L.d, geo_of<R>(s), s->gd, S, 1, s->partial + (int64_t)YY_P1 * 2 * NBMAX,
+                         nullptr, &s->nblocks[YY_P1], st);
+        solve_field<R>(s, YY_U2R, st);
+        solve_field<R>(s, YY_U2T, st);
+        solve_field<R>(s, YY_U2P, st);
+        Ops<R>::pressure(s->L.d, geo_of<R>(s), s->gd, S, 2, s->partial + (int64_t)YY_P2 * 2 * NBMAX,
+                         s->partial + (int64_t)9 * 2 * NBMAX, &s->nblocks[YY_P2], st);
+        s->nblocks[9] = s->nblocks[YY_P2];
+        reduce_norms(s->partial, s->nblocks, s->norms + (int64_t)k * 2 * NSLOT, st);
+    }
+    do_fill<R>(s, 2, 3, st);
+    // rotate levels: n-1 <- n <- k, and the old n-1 becomes the next work level
+    R *t = S.T[1];
+    S.T[1] = S.T[0]; S.T[0] = S.T[2]; S.T[2] = t;
+    for (int y = 0; y < 2; y++)
+        for (int c = 0; c < 3; c++) {
+            R *u = S.u[y][c][1];
+            S.u[y][c][1] = S.u[y][c][0];
+            S.u[y][c][0] = S.u[y][c][2];
+            S.u[y][c][2] = u;
+        }
+    for (int y = 0; y < 2; y++) {
+        double *p = S.p[y][0];
+        S.p[y][0] = S.p[y][1];
+        S.p[y][1] = p;
+    }
+    s->last_k = K;
+    return hip_status(hipGetLastError());
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *yy_strerror(int st)
+{
+    switch (st) {
+    case YY_OK: return "ok";
+    case YY_ERR_ARG: return "invalid argument";
+    case YY_ERR_GEOMETRY: return "overlap interpolation would extrapolate (overlap too small)";
+    case YY_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case YY_ERR_HIP: return "HIP runtime error";
+    case YY_ERR_NONFINITE: return "non-finite norm (the step diverged)";
+    case YY_ERR_STATE: return "call out of order";
+    default: return "unknown status";
+    }
+}
+
+int yy_workspace_bytes(const yy_grid *g, int32_t prec, uint64_t *bytes)
+{
+    if (!valid_grid(g) || !bytes || (prec != YY_FP64 && prec != YY_FP32_MIXED)) return YY_ERR_ARG;
+    *bytes = (uint64_t)make_layout(g, prec).total;
+    return YY_OK;
+}
+
+int yy_create(const yy_grid *g, int32_t prec, void *dev_ws, uint64_t ws_bytes, yy_shell **out)
+{
+    if (!out) return YY_ERR_ARG;
+    *out = nullptr;
+    if (!valid_grid(g) || !dev_ws || (prec != YY_FP64 && prec != YY_FP32_MIXED)) return YY_ERR_ARG;
+    Layout L = make_layout(g, prec);
+    if ((uintptr_t)dev_ws % ALIGN) return YY_ERR_WORKSPACE;
+    if (ws_bytes < (uint64_t)L.total) return YY_ERR_WORKSPACE;
+    Frame F;
+    F.r1 = g->r1;
+    F.r2 = g->r2;
+    F.delta = g->delta > 0.0 ? g->delta : M_PI / (2.0 * (g->nt - 2));
+    F.dr = (g->r2 - g->r1) / g->nr;
+    F.th0 = M_PI / 4.0 - F.delta;
+    F.ph0 = -3.0 * M_PI / 4.0 - F.delta;
+    F.dth = (M_PI / 2.0 + 2.0 * F.delta) / g->nt;
+    F.dph = (1.5 * M_PI + 2.0 * F.delta) / g->np;
+    std::vector<FillScalar> cc;
+    std::vector<FillVector> vt, vp;
+    if (!build_fill(F, L.d, cc, vt, vp)) return YY_ERR_GEOMETRY;
+    yy_shell *s = new (std::nothrow) yy_shell();
+    if (!s) return YY_ERR_ARG;
+    s->L = L;
+    s->F = F;
+    s->ws = (char *)dev_ws;
+    // zero the whole workspace (fields start at zero)
+    zero_doubles((double *)s->ws, L.total / 8, nullptr);
+    // tables
+    std::vector<double> td;
+    host_tables<double>(F, L.d, td);
+    hipError_t e = hipMemcpy(s->ws + L.off_tab_d, td.data(), td.size() * 8, hipMemcpyHostToDevice);
+    bind_geo<double>(s->gd, (const double *)(s->ws + L.off_tab_d), L.d, F);
+    if (prec == YY_FP64) {
+        bind_geo<double>(s->g64, (const double *)(s->ws + L.off_tab_d), L.d, F);
+        bind_state<double>(s);
+    } else {
+        std::vector<float> tf;
+        host_tables<float>(F, L.d, tf);
+        if (e == hipSuccess)
+            e = hipMemcpy(s->ws + L.off_tab_r, tf.data(), tf.size() * 4, hipMemcpyHostToDevice);
+        bind_geo<float>(s->g32, (const float *)(s->ws + L.off_tab_r), L.d, F);
+        bind_state<float>(s);
+    }
+    char *fb = s->ws + L.off_fill;
+    s->fcc = (FillScalar *)fb;
+    s->fvt = (FillVector *)(fb + cc.size() * sizeof(FillScalar));
+    s->fvp = s->fvt + vt.size();
+    if (e == hipSuccess) e = hipMemcpy(s->fcc, cc.data(), cc.size() * sizeof(FillScalar), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->fvt, vt.data(), vt.size() * sizeof(FillVector), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->fvp, vp.data(), vp.size() * sizeof(FillVector), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        delete s;
+        return YY_ERR_HIP;
+    }
+    s->partial = (double *)(s->ws + L.off_partial);
+    s->norms = (double *)(s->ws + L.off_norms);
+    for (int q = 0; q < NSLOT; q++) s->nblocks[q] = 0;
+    *out = s;
+    return YY_OK;
+}
+
+int yy_set_params(yy_shell *s, const yy_params *p)
+{
+    if (!s || !p) return YY_ERR_ARG;
+    if (!(p->dt > 0.0) || !(p->chi > 0.0) || !(p->pr > 0.0) || !std::isfinite(p->ra) ||
+        !std::isfinite(p->dt) || !std::isfinite(p->t_inner) || !std::isfinite(p->t_outer))
+        return YY_ERR_ARG;
+    if (p->mode != YY_ADDITIVE) return YY_ERR_ARG;
+    s->prm = *p;
+    set_coefs<double>(s->gd, *p);
+    set_coefs<double>(s->g64, *p);
+    set_coefs<float>(s->g32, *p);
+    s->have_params = true;
+    s->need_fill = true;   // wall values may have changed
+    return YY_OK;
+}
+
+static bool field_ok(int f) { return f >= 0 && f < YY_NFIELDS; }
+
+int yy_set_field(yy_shell *s, int32_t field, int32_t level, int32_t layout, const double *src,
+                 hipStream_t st)
+{
+    if (!s || !field_ok(field) || !src || (layout != YY_MAC && layout != YY_PADDED) || level < 0 || level > 2)
+        return YY_ERR_ARG;
+    const int loc = loc_of(field);
+    if (field == YY_P1 || field == YY_P2) {
+        if (level == YY_LEVEL_NM1) return YY_ERR_ARG;
+        const int y = field == YY_P2;
+        double *dst = s->L.prec == YY_FP64 ? s->s64.p[y][level == 0 ? 0 : 1] : s->s32.p[y][level == 0 ? 0 : 1];
+        io_double(s->L.d, dst, src, nullptr, loc, layout, st);
+    } else if (s->L.prec == YY_FP64) {
+        Ops<double>::io(s->L.d, field_ptr<double>(s, field, level), src, nullptr, loc, layout, st);
+    } else {
+        Ops<float>::io(s->L.d, field_ptr<float>(s, field, level), src, nullptr, loc, layout, st);
+    }
+    s->need_fill = true;
+    return hip_status(hipGetLastError());
+}
+
+int yy_get_field(yy_shell *s, int32_t field, int32_t level, int32_t layout, double *dst,
+                 hipStream_t st)
+{
+    if (!s || !field_ok(field) || !dst || (layout != YY_MAC && layout != YY_PADDED) || level < 0 || level > 2)
+        return YY_ERR_ARG;
+    const int loc = loc_of(field);
+    if (field == YY_P1 || field == YY_P2) {
+        if (level == YY_LEVEL_NM1) return YY_ERR_ARG;
+        const int y = field == YY_P2;
+        double *src = s->L.prec == YY_FP64 ? s->s64.p[y][level == 0 ? 0 : 1] : s->s32.p[y][level == 0 ? 0 : 1];
+        io_double(s->L.d, src, nullptr, dst, loc, layout, st);
+    } else if (s->L.prec == YY_FP64) {
+        Ops<double>::io(s->L.d, field_ptr<double>(s, field, level), nullptr, dst, loc, layout, st);
+    } else {
+        Ops<float>::io(s->L.d, field_ptr<float>(s, field, level), nullptr, dst, loc, layout, st);
+    }
+    return hip_status(hipGetLastError());
+}
+
+int yy_set_forcing(yy_shell *s, int32_t field, const double *src, hipStream_t st)
+{
+    if (!s) return YY_ERR_ARG;
+    int c;
+    switch (field) {
+    case YY_T: c = 0; break;
+    case YY_U1R: c = 1; break;
+    case YY_U1T: c = 2; break;
+    case YY_U1P: c = 3; break;
+    default: return YY_ERR_ARG;
+    }
+    const int loc = loc_of(field);
+    if (s->L.prec == YY_FP64) {
+        s->s64.force[c] = src ? (double *)s->force_ptr[c] : nullptr;
+        if (src) Ops<double>::io(s->L.d, (double *)s->force_ptr[c], src, nullptr, loc, YY_MAC, st);
+    } else {
+        s->s32.force[c] = src ? (float *)s->force_ptr[c] : nullptr;
+        if (src) Ops<float>::io(s->L.d, (float *)s->force_ptr[c], src, nullptr, loc, YY_MAC, st);
+    }
+    return hip_status(hipGetLastError());
+}
+
+int yy_step(yy_shell *s, int32_t K, hipStream_t st)
+{
+    if (!s || K < 1 || K > MAXK) return YY_ERR_ARG;
+    if (!s->have_params) return YY_ERR_STATE;
+    if (s->sticky != YY_OK) return s->sticky;
+    return s->L.prec == YY_FP64 ? step_impl<double>(s, K, st) : step_impl<float>(s, K, st);
+}
+
+int yy_get_norms(yy_shell *s, double *out, int32_t cap, hipStream_t st)
+{
+    if (!s || !out || cap < 0) return YY_ERR_ARG;
+    const int n = s->last_k * 2 * NSLOT;
+    std::vector<double> h(n > 0 ? n : 1);
+    hipError_t e = hipSuccess;
+    if (n > 0) e = hipMemcpyAsync(h.data(), s->norms, n * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return YY_ERR_HIP;
+    bool finite = true;
+    for (int q = 0; q < n; q++) {
+        if (q < cap) out[q] = h[q];
+        if (!std::isfinite(h[q])) finite = false;
+    }
+    if (!finite) {
+        s->sticky = YY_ERR_NONFINITE;
+        return YY_ERR_NONFINITE;
+    }
+    return n;
+}
+
+int yy_destroy(yy_shell *s)
+{
+    if (!s) return YY_ERR_ARG;
+    delete s;
+    return YY_OK;
+}
+
+int yy_internal_dims(const yy_shell *s, int64_t dims[4], int32_t *elem_bytes)
+{
+    if (!s || !dims) return YY_ERR_ARG;
+    dims[0] = 2;
+    dims[1] = s->L.d.nr + 2;
+    dims[2] = s->L.d.nt + 2;
+    dims[3] = s->L.d.sJ;
+    if (elem_bytes) *elem_bytes = (int32_t)s->L.elem;
+    return YY_OK;
+}
+
+int yy_fill(yy_shell *s, int32_t level, hipStream_t st)
+{
+    if (!s || level < 0 || level > 2) return YY_ERR_ARG;
+    if (s->L.prec == YY_FP64) do_fill<double>(s, level, 3, st);
+    else do_fill<float>(s, level, 3, st);
+    return hip_status(hipGetLastError());
+}
+
+int yy_extrapolate(yy_shell *s, hipStream_t st)
+{
+    if (!s) return YY_ERR_ARG;
+    if (s->L.prec == YY_FP64) Ops<double>::extrap(s->L.d, s->s64, st);
+    else Ops<float>::extrap(s->L.d, s->s32, st);
+    return hip_status(hipGetLastError());
+}
+
+int yy_sweep(yy_shell *s, int32_t field, int32_t dir, const void *x, void *y, hipStream_t st)
+{
+    if (!s || !x || !y || dir < 0 || dir > 2 || !field_ok(field) || field == YY_P1 || field == YY_P2)
+        return YY_ERR_ARG;
+    if (!s->have_params) return YY_ERR_STATE;
+    if (s->L.prec == YY_FP64)
+        Ops<double>::sweep(s->L.d, s->g64, s->gd, s->s64, field, dir, (const double *)x, (double *)y, 0,
+                           nullptr, nullptr, 0, st);
+    else
+        Ops<float>::sweep(s->L.d, s->g32, s->gd, s->s32, field, dir, (const float *)x, (float *)y, 0,
+                          nullptr, nullptr, 0, st);
+    return hip_status(hipGetLastError());
+}
+
+int yy_sweep_diffusion(yy_shell *s, int32_t dir, const void *x, void *y, hipStream_t st)
+{
+    if (!s || !x || !y || dir < 0 || dir > 2) return YY_ERR_ARG;
+    if (!s->have_params) return YY_ERR_STATE;
+    if (s->L.prec == YY_FP64)
+        Ops<double>::sweep(s->L.d, s->g64, s->gd, s->s64, YY_T, dir, (const double *)x, (double *)y, 0,
+                           nullptr, nullptr, 1, st);
+    else
+        Ops<float>::sweep(s->L.d, s->g32, s->gd, s->s32, YY_T, dir, (const float *)x, (float *)y, 0,
+                          nullptr, nullptr, 1, st);
+    return hip_status(hipGetLastError());
+}
+
+int yy_residual(yy_shell *s, int32_t field, void *out, hipStream_t st)
+{
+    if (!s || !out || !field_ok(field) || field == YY_P1 || field == YY_P2) return YY_ERR_ARG;
+    if (!s->have_params) return YY_ERR_STATE;
+    if (s->L.prec == YY_FP64) Ops<double>::residual(s->L.d, s->g64, s->s64, field, (double *)out, st);
+    else Ops<float>::residual(s->L.d, s->g32, s->s32, field, (float *)out, st);
+    return hip_status(hipGetLastError());
+}
+
+}  // extern "C"

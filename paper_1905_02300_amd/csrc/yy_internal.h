@@ -1,0 +1,95 @@
+// yy_internal.h -- types shared by the host orchestrator and the gfx950
+// kernels of libyy.so (not part of the public ABI).
+//
+// Device layout of every field: [patch][i][j][k] with one ghost layer,
+// logical index -1..N per direction, k (phi) fastest, row pitch padded to a
+// multiple of 16 elements; face f of a face-located field at logical f.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace yy {
+
+enum Loc { CC = 0, FR = 1, FT = 2, FP = 3 };   // centre, r-, theta-, phi-face
+
+struct Dims {
+    int nr, nt, np;
+    int64_t sJ, sI, sP;      // element strides of j, i and patch (k: 1)
+};
+
+__host__ __device__ inline int64_t ix(const Dims &d, int p, int i, int j, int k)
+{
+    return (int64_t)p * d.sP + (int64_t)(i + 1) * d.sI + (int64_t)(j + 1) * d.sJ + (k + 1);
+}
+
+// metric tables and grid constants in compute precision R
+template <typename R> struct Geo {
+    const R *rc;    // r at centres, index i+1, i = -1..nr
+    const R *rf;    // r at faces, index f+1, f = -1..nr+1
+    const R *sc, *cc;   // sin, cos theta at centres, index j+1, j = -1..nt
+    const R *sf, *cf;   // sin, cos theta at faces, index f+1, f = -1..nt+1
+    R dr, dth, dph, r1;
+    R cphat;        // 1 / (R1^2 sin^2(theta_1) dphi^2), theta_1 = pi/4 - d
+    R ht, tau, inv_tau;
+    R pr, ic, prra; // Pr, 1/(2 chi), Pr*Ra
+    double inv_chi;
+};
+
+// one interpolation target of a scalar (centre-type in theta and phi)
+struct FillScalar {
+    int32_t tj, tk;          // target (logical j, k)
+    int32_t dj, dk;          // donor window start (logical j, k) in the other patch
+    double wt[4], wp[4];     // cubic Lagrange weights along theta, phi
+};
+
+// one interpolation target of a tangential velocity component: both of the
+// other patch's components are interpolated (each on its own staggered
+// grid) and rotated: value = ma * u_theta~ + mb * u_phi~
+struct FillVector {
+    int32_t tj, tk;
+    int32_t tjA, tkA;        // window on the theta-face grid
+    int32_t tjB, tkB;        // window on the phi-face grid
+    double wtA[4], wpA[4], wtB[4], wpB[4];
+    double ma, mb;
+};
+
+// pointers of one step (compute precision R; pressures double)
+template <typename R> struct State {
+    R *T[3];                 // levels n, n-1, working iterate k
+    R *Ts;                   // T*
+    R *u[2][3][3];           // [system][component r,t,p][level]
+    R *us[2][3];             // [system][component] extrapolated
+    double *p[2][2];         // [system][level n, working]
+    R *force[4];             // T, u_r, u_t, u_p forcing (or null)
+    R *res;                  // residual / sweep buffer
+    R *cb;                   // Thomas scratch (c')
+};
+
+constexpr int NBMAX = 1024;      // blocks per patch of a norm-producing launch
+constexpr int NSLOT = 10;        // norm slots
+
+// ---- launchers (yy_kernels.hip) ----
+template <typename R> struct Ops {
+    static void extrap(const Dims &d, const State<R> &s, hipStream_t st);
+    static void copy_levels(const Dims &d, const State<R> &s, int from, int to, hipStream_t st);
+    static void fill(const Dims &d, const State<R> &s, int level, const FillScalar *cc, int ncc,
+                     const FillVector *vt, int nvt, const FillVector *vp, int nvp,
+                     double t_in, double t_out, int patch_mask, hipStream_t st);
+    static void residual(const Dims &d, const Geo<R> &g, const State<R> &s, int field, R *out,
+                         hipStream_t st);
+    // one sweep; mode 0: y = solve(x); mode 1: psi_k += solve(x) and norm
+    static void sweep(const Dims &d, const Geo<R> &g, const Geo<double> &gd, const State<R> &s,
+                      int field, int dir, const R *x, R *y, int mode, double *partial,
+                      int *nblocks, int diffusion_only, hipStream_t st);
+    static void pressure(const Dims &d, const Geo<R> &g, const Geo<double> &gd, const State<R> &s,
+                         int sys, double *partial_inc, double *partial_div, int *nblocks,
+                         hipStream_t st);
+    static void io(const Dims &d, R *internal, const double *ext, double *ext_out, int field_loc,
+                   int layout, hipStream_t st);
+};
+void io_double(const Dims &d, double *internal, const double *ext, double *ext_out, int field_loc,
+               int layout, hipStream_t st);
+void reduce_norms(const double *partial, const int *nblocks_dev, double *out, hipStream_t st);
+void zero_doubles(double *p, int64_t n, hipStream_t st);
+
+}  // namespace yy

@@ -1,0 +1,242 @@
+"""Parity of the HIP path (libyy.so through its C-ABI) with the FP64 CPU
+oracle on the same seeded inputs: each kernel alone, then whole steps.
+
+Bar: FP64 relative error <= 1e-12 (max abs difference over max abs value of
+the oracle's field); the FP32-mixed step is compared with the FP64 step at
+its stated error.
+"""
+import numpy as np
+import pytest
+
+from paper_1905_02300_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    scale = max(np.max(np.abs(b)), 1e-300)
+    return np.max(np.abs(a - b)) / scale
+
+
+@pytest.fixture(scope="module")
+def yy():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1905_02300_amd import yy as mod
+    mod.load()
+    return mod
+
+
+def _pair(oracle_lib, yy, nr, nt, np_, prec=0, **prm):
+    o = oracle_lib.Shell(nr, nt, np_)
+    g = yy.Shell(nr, nt, np_, prec=prec)
+    p = dict(pr=1.0, ra=0.0, dt=1e-3, chi=1.0, t_inner=0.0, t_outer=0.0)
+    p.update(prm)
+    o.set_params(pr=p["pr"], ra=p["ra"], tau=p["dt"], chi=p["chi"], t_inner=p["t_inner"],
+                 t_outer=p["t_outer"])
+    g.set_params(**p)
+    return o, g
+
+
+def _unknown_mask(shape, field):
+    loc = I.LOC[field]
+    m = np.zeros(shape, bool)
+    lo = [1 if loc == key else 0 for key in "rtp"]
+    n = [shape[1] - 2, shape[2] - 2, shape[3] - 2]
+    m[:, 1 + lo[0]:1 + n[0], 1 + lo[1]:1 + n[1], 1 + lo[2]:1 + n[2]] = True
+    return m
+
+
+def _set_random(o, g, rng, levels, scale=1.0, layout_padded=True):
+    for f in range(9):
+        for lev in levels:
+            if f in (I.P1, I.P2) and lev == 1:
+                continue
+            a = scale * rng.uniform(-1, 1, o.padded_shape())
+            o.set_field(f, lev, a, layout=1)
+            g.set_field(f, lev, a, layout=1)
+
+
+def test_fill_parity(oracle_lib, yy):
+    print("case: fill 6x16x48", flush=True)
+    o, g = _pair(oracle_lib, yy, 6, 16, 48, t_inner=1.0, t_outer=0.3)
+    rng = np.random.default_rng(11)
+    _set_random(o, g, rng, [0])
+    o.fill(0)
+    g.fill(0)
+    for f in range(9):
+        a = g.get_field(f, 0, layout=1).cpu().numpy()
+        b = o.get_field(f, 0, layout=1)
+        assert _rel(a, b) <= 1e-14, I.FIELD_NAMES[f]
+
+
+@pytest.mark.parametrize("field", [I.T, I.U1R, I.U1T, I.U1P, I.U2R, I.U2T, I.U2P])
+@pytest.mark.parametrize("d", [0, 1, 2])
+def test_sweep_parity(oracle_lib, yy, field, d):
+    print(f"case: sweep field {field} dir {d} 5x13x40", flush=True)
+    o, g = _pair(oracle_lib, yy, 5, 13, 40, pr=0.7, dt=0.05, chi=1.3)
+    rng = np.random.default_rng(100 + 3 * field + d)
+    _set_random(o, g, rng, [0, 1])
+    o.extrapolate()
+    g.extrapolate()
+    x = rng.uniform(-1, 1, o.padded_shape())
+    ref = o.sweep(field, d, x)
+    xt = g.to_internal(x)
+    yt = g.internal_tensor()
+    g.sweep(field, d, xt, yt)
+    got = g.from_internal(yt).cpu().numpy()
+    m = _unknown_mask(o.padded_shape(), field)
+    assert _rel(got[m], ref[m]) <= TOL
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+def test_sweep_diffusion_parity(oracle_lib, yy, d):
+    print(f"case: sweep_diffusion dir {d}", flush=True)
+    o, g = _pair(oracle_lib, yy, 6, 14, 42, pr=1.0, dt=1e-2)
+    o.extrapolate()                      # zero velocity: T's factors are pure diffusion
+    x = np.random.default_rng(7 + d).uniform(-1, 1, o.padded_shape())
+    ref = o.sweep(I.T, d, x)
+    yt = g.internal_tensor()
+    g.sweep_diffusion(d, g.to_internal(x), yt)
+    got = g.from_internal(yt).cpu().numpy()
+    m = _unknown_mask(o.padded_shape(), I.T)
+    assert _rel(got[m], ref[m]) <= TOL
+
+
+@pytest.mark.parametrize("field", [I.T, I.U1R, I.U1T, I.U1P, I.U2R, I.U2T, I.U2P])
+def test_residual_parity(oracle_lib, yy, field):
+    print(f"case: residual field {field}", flush=True)
+    o, g = _pair(oracle_lib, yy, 5, 12, 36, pr=0.8, ra=50.0, dt=0.02, chi=0.9)
+    rng = np.random.default_rng(200 + field)
+    _set_random(o, g, rng, [0, 1, 2])
+    for f in (I.T, I.U1R, I.U1T, I.U1P):
+        a = rng.uniform(-1, 1, I.Grid(5, 12, 36).mac_shape(f))
+        o.set_forcing(f, a)
+        g.set_forcing(f, a)
+    o.extrapolate()
+    g.extrapolate()
+    ref = 0.02 * o.residual(field)
+    out = g.internal_tensor()
+    g.residual(field, out)
+    got = g.from_internal(out).cpu().numpy()
+    m = _unknown_mask(o.padded_shape(), field)
+    assert _rel(got[m], ref[m]) <= TOL
+
+
+def _mms_pair(oracle_lib, yy, nr, nt, np_, dt, prec=0, pr=1.0, ra=1e3):
+    o, g = _pair(oracle_lib, yy, nr, nt, np_, prec=prec, pr=pr, ra=ra, dt=dt)
+    grid = I.Grid(nr, nt, np_)
+    s0, sm = I.mms_state(grid, 0.0), I.mms_state(grid, -dt)
+    for f in range(9):
+        o.set_field(f, 0, s0[f])
+        g.set_field(f, 0, s0[f])
+        if f not in (I.P1, I.P2):
+            o.set_field(f, 1, sm[f])
+            g.set_field(f, 1, sm[f])
+    return o, g, grid
+
+
+def _mms_steps(o, g, grid, dt, nsteps, K, pr=1.0, ra=1e3):
+    for s in range(nsteps):
+        for f in (I.T, I.U1R, I.U1T, I.U1P):
+            a = I.mms_forcing(grid, (s + 0.5) * dt, f, pr, ra)
+            if o is not None:
+                o.set_forcing(f, a)
+            g.set_forcing(f, a)
+        if o is not None:
+            o.step(K)
+        g.step(K)
+
+
+def test_step_parity_manufactured_16x24x72(oracle_lib, yy):
+    """The small FP64 workload: R1=0.5, R2=1, 16x24x72 per patch, Pr=1,
+    Ra=1e3, dt=1e-3, 10 steps x 2 Schwarz iterations, manufactured
+    solution with its forcing."""
+    print("case: full step 16x24x72 x10", flush=True)
+    o, g, grid = _mms_pair(oracle_lib, yy, 16, 24, 72, 1e-3)
+    _mms_steps(o, g, grid, 1e-3, 10, 2)
+    for f in range(9):
+        a = g.get_field(f).cpu().numpy()
+        b = o.get_field(f)
+        assert _rel(a, b) <= TOL, (I.FIELD_NAMES[f], _rel(a, b))
+    for f in (I.T, I.U2R, I.U2T, I.U2P):
+        assert _rel(g.get_field(f, 1).cpu().numpy(), o.get_field(f, 1)) <= TOL
+    assert _rel(g.norms(), o.norms(2)) <= 1e-10
+
+
+def test_step_parity_convection(oracle_lib, yy):
+    """Convection start (conductive T + seeded noise, hydrostatic p, T(R1)=1)
+    at Ra=1e5, dt=2e-4, 3 Schwarz iterations, 2 steps."""
+    print("case: convection 12x30x90 x2", flush=True)
+    nr, nt, np_ = 12, 30, 90
+    o, g = _pair(oracle_lib, yy, nr, nt, np_, pr=1.0, ra=1e5, dt=2e-4, t_inner=1.0)
+    st = I.convection_state(I.Grid(nr, nt, np_), 1.0, 1e5, seed=3)
+    for f in range(9):
+        o.set_field(f, 0, st[f])
+        g.set_field(f, 0, st[f])
+        if f not in (I.P1, I.P2):
+            o.set_field(f, 1, st[f])
+            g.set_field(f, 1, st[f])
+    nsteps, K = 2, 3
+    for _ in range(nsteps):
+        o.step(K)
+        g.step(K)
+    # The hydrostatic pressure gradient and the buoyancy (size M = Pr Ra
+    # max|T|) cancel to leave the small driving of u; each residual
+    # evaluation rounds them at ~eps M, and each of the n K corrections
+    # applies tau times that to u.  Velocities are held to 1e-12 relative
+    # plus that rounding floor; T and p to 1e-12 relative.
+    M = 1.0 * 1e5 * np.max(np.abs(st[I.T]))
+    floor = 16 * np.finfo(float).eps * 2e-4 * M * nsteps * K
+    for f in range(9):
+        a = g.get_field(f).cpu().numpy()
+        b = o.get_field(f)
+        err = np.max(np.abs(a - b))
+        if f in (I.T, I.P1, I.P2):
+            assert err <= TOL * np.max(np.abs(b)), (I.FIELD_NAMES[f], _rel(a, b))
+        else:
+            assert err <= TOL * np.max(np.abs(b)) + floor, (I.FIELD_NAMES[f], _rel(a, b), err, floor)
+        print(f"  {I.FIELD_NAMES[f]}: relative error {_rel(a, b):.2e}")
+
+
+def test_fp32_mixed_within_stated_error(oracle_lib, yy):
+    """FP32 stencils and sweeps with FP64 pressure, divergence and norms
+    stay within 1e-4 (relative) of the FP64 step on the manufactured run."""
+    print("case: fp32-mixed 16x24x72 x10", flush=True)
+    _, g64, grid = _mms_pair(oracle_lib, yy, 16, 24, 72, 1e-3, prec=0)
+    _, g32, _ = _mms_pair(oracle_lib, yy, 16, 24, 72, 1e-3, prec=1)
+    _mms_steps(None, g64, grid, 1e-3, 10, 2)
+    _mms_steps(None, g32, grid, 1e-3, 10, 2)
+    for f in range(9):
+        e = _rel(g32.get_field(f).cpu().numpy(), g64.get_field(f).cpu().numpy())
+        assert e < 1e-4, (I.FIELD_NAMES[f], e)
+
+
+def test_deterministic(oracle_lib, yy):
+    print("case: determinism", flush=True)
+    outs = []
+    for _ in range(2):
+        _, g, grid = _mms_pair(oracle_lib, yy, 8, 12, 36, 1e-3)
+        _mms_steps(None, g, grid, 1e-3, 3, 2)
+        outs.append([g.get_field(f).cpu().numpy() for f in range(9)] + [g.norms()])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_nonfinite_is_reported(oracle_lib, yy):
+    print("case: non-finite", flush=True)
+    _, g, grid = _mms_pair(oracle_lib, yy, 8, 12, 36, 1e-3)
+    t = np.zeros(grid.mac_shape(I.T))
+    t[0, 3, 4, 5] = np.nan
+    g.set_field(I.T, 0, t)
+    g.step(2)
+    with pytest.raises(yy.YYError) as e:
+        g.norms()
+    assert e.value.status == yy.YY_ERR_NONFINITE
+    with pytest.raises(yy.YYError):
+        g.step(1)
