@@ -1,0 +1,185 @@
+"""Throughput of the Yin-Yang AC direction-splitting time step on one MI355X.
+
+One step = the whole hot path: extrapolation, K Schwarz iterations (overlap
+interpolation + walls; residual and three direction-split line sweeps for T,
+u1 (r, theta, phi), u2 (r, theta, phi); FP64 pressure updates; norms) and
+the post-step interpolation, on a synthetic convecting shell (conductive
+temperature + seeded noise, hydrostatic pressure, u = 0) with every input
+resident in HBM before the timed region.
+
+Prints one JSON line (metric, value in Mcell-steps/s, per-kernel timing
+from HIP events, the roofline of the dominant kernel, and the oracle's
+CPU baseline on a bounded sample).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mcell-steps/s, FP64 vs FP32-mixed at stated error; line-solve HBM GB/s vs peak"
+HBM_PEAK_GBS = 8000.0
+
+# distinct arrays (read + written) per launch of each kernel class, in
+# compute-precision words (R) and FP64 words (D), per cell; classes merge
+# the launches of several fields, so the figure is their mean.
+# sweep: x in, y out (+ the advecting-velocity components its coefficients
+# use); last sweep: x in, psi^k read and written.
+_ADV = {  # (location, direction) -> extra u2* components read by the sweep
+    ("c", 0): 1, ("c", 1): 1, ("c", 2): 1,
+    ("r", 0): 1, ("r", 1): 1, ("r", 2): 1,
+    ("t", 0): 1, ("t", 1): 2, ("t", 2): 1,
+    ("p", 0): 1, ("p", 1): 1, ("p", 2): 3,
+}
+_ORDER = {"c": (0, 1, 2), "r": (1, 2, 0), "t": (2, 0, 1), "p": (0, 1, 2)}
+
+
+def class_words():
+    """{class: (R words per cell, D words per cell)} averaged over launches"""
+    fields = ["c", "r", "t", "p", "r", "t", "p"]          # T, u1, u2
+    sw = {0: [], 1: [], 2: []}
+    swl = {0: [], 1: [], 2: []}
+    for loc in fields:
+        o = _ORDER[loc]
+        for q in range(2):
+            sw[o[q]].append(2 + _ADV[(loc, o[q])])
+        swl[o[2]].append(3 + _ADV[(loc, o[2])])
+    W = {}
+    for d, name in enumerate("rtp"):
+        W["sweep_" + name] = (float(np.mean(sw[d])), 0.0)
+        W["sweep_" + name + "_last"] = (float(np.mean(swl[d])), 0.0)
+    # residuals: own levels n, k, *, u2* (3), write 1 (+ sources)
+    W["residual_T"] = (7.0, 0.0)                          # Tn Tk T* w3 out
+    W["residual_ur"] = (0.5 * (11 + 8), 0.5 * (1 + 3))    # s=1 / s=2 distinct arrays
+    W["residual_ut"] = (0.5 * (12 + 9), 0.5 * (1 + 3))
+    W["residual_up"] = (0.5 * (12 + 10), 0.5 * (1 + 3))
+    W["pressure_1"] = (6.0, 3.0)
+    W["pressure_2"] = (6.0, 5.0)
+    W["extrap"] = (21.0, 0.0)
+    W["copy"] = (14.0, 4.0)
+    return W
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--grid", default="128,384,1152")
+    ap.add_argument("--schwarz", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-grid", default="40,120,360")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_1905_02300_amd import inputs as I
+    from paper_1905_02300_amd import yy
+
+    assert torch.cuda.is_available(), "bench.py needs an MI355X"
+    nr, nt, np_ = (int(x) for x in args.grid.split(","))
+    pr, ra, dt, K = 1.0, 1e5, 2e-4, args.schwarz
+    prec = yy.YY_FP64 if args.prec == "fp64" else yy.YY_FP32_MIXED
+    grid = I.Grid(nr, nt, np_)
+    sh = yy.Shell(nr, nt, np_, prec=prec)
+    sh.set_params(pr=pr, ra=ra, dt=dt, chi=1.0, t_inner=1.0, t_outer=0.0)
+    st = I.convection_state(grid, pr, ra, seed=3)
+    for f in range(9):
+        sh.set_field(f, 0, st[f])
+        if f not in (I.P1, I.P2):
+            sh.set_field(f, 1, st[f])
+    del st
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        sh.step(K)
+    torch.cuda.synchronize()
+    sh.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sh.step(K)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = sh.profile_read(stream)
+    sh.profile(False)
+    norms = sh.norms()
+    cells = grid.cells
+    value = cells * args.steps / el / 1e6
+
+    wbytes = 8 if prec == yy.YY_FP64 else 4
+    W = class_words()
+    kernels = {}
+    for name, (ms, cnt) in prof.items():
+        if cnt == 0:
+            continue
+        entry = {"ms_total": ms, "launches": cnt, "ms_avg": ms / cnt}
+        if name in W:
+            r, d = W[name]
+            bytes_per = cells * (r * wbytes + d * 8)
+            entry["alg_bytes"] = bytes_per
+            entry["gbs"] = bytes_per / (ms / cnt * 1e-3) / 1e9
+        kernels[name] = entry
+    dom = max((k for k in kernels if "gbs" in kernels[k]), key=lambda k: kernels[k]["ms_total"])
+    dk = kernels[dom]
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": dk["gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                "alg_bytes_per_launch": dk["alg_bytes"], "ms_avg": dk["ms_avg"]}
+    tfile = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (dom, args.prec))
+    if os.path.exists(tfile):
+        with open(tfile) as fh:
+            roofline["traffic"] = json.load(fh).get("bytes_per_launch")
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(args.cpu_grid, pr, ra, dt, K)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "Mcell-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == yy.YY_FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"yinyang_ac_step_2x{nr}x{nt}x{np_}_{args.prec}_K{K}",
+                   "cells": cells, "grid_per_patch": [nr, nt, np_], "schwarz_iterations": K,
+                   "Pr": pr, "Ra": ra, "dt": dt, "parallelism": "single-gpu"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+        "last_step_norms_k_last": {"div_u2": float(norms[-1, :, 9].max()),
+                                   "dT": float(norms[-1, :, 0].max())},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(grid_s, pr, ra, dt, K):
+    """The oracle as it stands, on the host cores: one step of the same
+    workload (same physics and schedule) on a bounded grid."""
+    from oracle import yyo
+    from paper_1905_02300_amd import inputs as I
+    nr, nt, np_ = (int(x) for x in grid_s.split(","))
+    grid = I.Grid(nr, nt, np_)
+    o = yyo.Shell(nr, nt, np_)
+    o.set_params(pr=pr, ra=ra, tau=dt, chi=1.0, t_inner=1.0, t_outer=0.0)
+    st = I.convection_state(grid, pr, ra, seed=3)
+    for f in range(9):
+        o.set_field(f, 0, st[f])
+        o.set_field(f, 1, st[f])
+    del st
+    t0 = time.perf_counter()
+    o.step(K)
+    el = time.perf_counter() - t0
+    return {"value": grid.cells / el / 1e6, "unit": "Mcell-steps/s", "cores": yyo.omp_threads(),
+            "kind": "oracle",
+            "sample": f"one step (K={K}) of the same convecting-shell workload on a 2x{nr}x{nt}x{np_} "
+                      f"grid ({grid.cells} cells), {el:.1f} s wall"}
+
+
+if __name__ == "__main__":
+    main()

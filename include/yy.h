@@ -175,6 +175,23 @@ int yy_sweep_diffusion(yy_shell *s, int32_t dir, const void *dev_x, void *dev_y,
  * compute precision, written at the unknowns only). */
 int yy_residual(yy_shell *s, int32_t field, void *dev_out, hipStream_t stream);
 
+/* ---- live per-kernel timing (HIP events on the caller's stream) ---- */
+
+/* Kernel classes timed by the profiler. */
+#define YY_NPROF 16
+
+/* enable != 0: start recording a hipEvent pair around every kernel launch
+ * group of later calls (previous records are dropped); 0: stop. */
+int yy_profile(yy_shell *s, int32_t enable);
+
+/* Synchronise the stream and return, per kernel class (index < YY_NPROF),
+ * the summed elapsed milliseconds and the number of timed launch groups
+ * since yy_profile(s, 1).  Returns YY_NPROF. */
+int yy_profile_read(yy_shell *s, double *ms, int64_t *count, hipStream_t stream);
+
+/* Name of a kernel class ("sweep_p_last", ...), or NULL if out of range. */
+const char *yy_profile_name(int32_t cls);
+
 #ifdef __cplusplus
 }
 #endif

@@ -236,7 +236,22 @@ template <typename R> void set_coefs(Geo<R> &g, const yy_params &p)
 
 }  // namespace
 
+enum ProfClass {
+    PC_EXTRAP = 0, PC_COPY, PC_FILL, PC_RES_T, PC_RES_UR, PC_RES_UT, PC_RES_UP,
+    PC_SW_R, PC_SW_T, PC_SW_P, PC_SW_R_LAST, PC_SW_T_LAST, PC_SW_P_LAST,
+    PC_PRESS1, PC_PRESS2, PC_REDUCE
+};
+static const char *prof_names[YY_NPROF] = {
+    "extrap", "copy", "fill", "residual_T", "residual_ur", "residual_ut", "residual_up",
+    "sweep_r", "sweep_t", "sweep_p", "sweep_r_last", "sweep_t_last", "sweep_p_last",
+    "pressure_1", "pressure_2", "norm_reduce"};
+
 struct yy_shell {
+    // live timing: event pairs around launch groups
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_cls;
+    size_t ev_used = 0;
     Layout L;
     Frame F;
     yy_params prm;
@@ -312,8 +327,28 @@ template <typename R> R *field_ptr(yy_shell *s, int f, int lev)
     return st.u[y][c][lev];
 }
 
+// RAII pair of timing events around a launch group (no-op unless enabled)
+struct Timed {
+    yy_shell *s;
+    hipStream_t st;
+    size_t slot;
+    Timed(yy_shell *s_, int cls, hipStream_t st_) : s(s_), st(st_), slot((size_t)-1)
+    {
+        if (!s->prof || s->ev_used + 2 > s->ev.size()) return;
+        slot = s->ev_used;
+        s->ev_used += 2;
+        s->ev_cls[slot / 2] = cls;
+        (void)hipEventRecord(s->ev[slot], st);
+    }
+    ~Timed()
+    {
+        if (slot != (size_t)-1) (void)hipEventRecord(s->ev[slot + 1], st);
+    }
+};
+
 template <typename R> void do_fill(yy_shell *s, int lev, int pmask, hipStream_t st)
 {
+    Timed tm(s, PC_FILL, st);
     Ops<R>::fill(s->L.d, state_of<R>(s), lev, s->fcc, (int)s->L.ncc, s->fvt, (int)s->L.nvt, s->fvp,
                  (int)s->L.nvp, s->prm.t_inner, s->prm.t_outer, pmask, st);
 }
@@ -323,9 +358,16 @@ template <typename R> void solve_field(yy_shell *s, int f, hipStream_t st)
     State<R> &S = state_of<R>(s);
     const int loc = loc_of(f);
     static const int order[4][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1}, {0, 1, 2}};
-    Ops<R>::residual(s->L.d, geo_of<R>(s), S, f, S.res, st);
-    Ops<R>::sweep(s->L.d, geo_of<R>(s), s->gd, S, f, order[loc][0], S.res, S.res, 0, nullptr, nullptr, 0, st);
-    Ops<R>::sweep(s->L.d, geo_of<R>(s), s->gd, S, f, order[loc][1], S.res, S.res, 0, nullptr, nullptr, 0, st);
+    {
+        Timed tm(s, PC_RES_T + loc, st);
+        Ops<R>::residual(s->L.d, geo_of<R>(s), S, f, S.res, st);
+    }
+    for (int q = 0; q < 2; q++) {
+        Timed tm(s, PC_SW_R + order[loc][q], st);
+        Ops<R>::sweep(s->L.d, geo_of<R>(s), s->gd, S, f, order[loc][q], S.res, S.res, 0, nullptr,
+                      nullptr, 0, st);
+    }
+    Timed tm(s, PC_SW_R_LAST + order[loc][2], st);
     Ops<R>::sweep(s->L.d, geo_of<R>(s), s->gd, S, f, order[loc][2], S.res, S.res, 1,
                   s->partial + (int64_t)f * 2 * NBMAX, &s->nblocks[f], 0, st);
 }
@@ -338,22 +380,35 @@ template <typename R> int step_impl(yy_shell *s, int K, hipStream_t st)
         do_fill<R>(s, 1, 3, st);
         s->need_fill = false;
     }
-    Ops<R>::extrap(s->L.d, S, st);
-    Ops<R>::copy_levels(s->L.d, S, 0, 2, st);
+    {
+        Timed tm(s, PC_EXTRAP, st);
+        Ops<R>::extrap(s->L.d, S, st);
+    }
+    {
+        Timed tm(s, PC_COPY, st);
+        Ops<R>::copy_levels(s->L.d, S, 0, 2, st);
+    }
     for (int k = 0; k < K; k++) {
         do_fill<R>(s, 2, 3, st);
         solve_field<R>(s, YY_T, st);
         solve_field<R>(s, YY_U1R, st);
         solve_field<R>(s, YY_U1T, st);
         solve_field<R>(s, YY_U1P, st);
-        Ops<R>::pressure(s->L.d, geo_of<R>(s), s->gd, S, 1, s->partial + (int64_t)YY_P1 * 2 * NBMAX,
-                         nullptr, &s->nblocks[YY_P1], st);
+        {
+            Timed tm(s, PC_PRESS1, st);
+            Ops<R>::pressure(s->L.d, geo_of<R>(s), s->gd, S, 1, s->partial + (int64_t)YY_P1 * 2 * NBMAX,
+                             nullptr, &s->nblocks[YY_P1], st);
+        }
         solve_field<R>(s, YY_U2R, st);
         solve_field<R>(s, YY_U2T, st);
         solve_field<R>(s, YY_U2P, st);
-        Ops<R>::pressure(s->L.d, geo_of<R>(s), s->gd, S, 2, s->partial + (int64_t)YY_P2 * 2 * NBMAX,
-                         s->partial + (int64_t)9 * 2 * NBMAX, &s->nblocks[YY_P2], st);
+        {
+            Timed tm(s, PC_PRESS2, st);
+            Ops<R>::pressure(s->L.d, geo_of<R>(s), s->gd, S, 2, s->partial + (int64_t)YY_P2 * 2 * NBMAX,
+                             s->partial + (int64_t)9 * 2 * NBMAX, &s->nblocks[YY_P2], st);
+        }
         s->nblocks[9] = s->nblocks[YY_P2];
+        Timed tm(s, PC_REDUCE, st);
         reduce_norms(s->partial, s->nblocks, s->norms + (int64_t)k * 2 * NSLOT, st);
     }
     do_fill<R>(s, 2, 3, st);
@@ -574,8 +629,47 @@ int yy_get_norms(yy_shell *s, double *out, int32_t cap, hipStream_t st)
 int yy_destroy(yy_shell *s)
 {
     if (!s) return YY_ERR_ARG;
+    for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
     delete s;
     return YY_OK;
+}
+
+int yy_profile(yy_shell *s, int32_t enable)
+{
+    if (!s) return YY_ERR_ARG;
+    if (enable && s->ev.empty()) {
+        const size_t n = 2 * 8192;
+        s->ev.resize(n);
+        s->ev_cls.resize(n / 2);
+        for (size_t q = 0; q < n; q++)
+            if (hipEventCreate(&s->ev[q]) != hipSuccess) return YY_ERR_HIP;
+    }
+    s->prof = enable != 0;
+    if (enable) s->ev_used = 0;
+    return YY_OK;
+}
+
+int yy_profile_read(yy_shell *s, double *ms, int64_t *count, hipStream_t st)
+{
+    if (!s || !ms || !count) return YY_ERR_ARG;
+    if (hipStreamSynchronize(st) != hipSuccess) return YY_ERR_HIP;
+    for (int c = 0; c < YY_NPROF; c++) {
+        ms[c] = 0.0;
+        count[c] = 0;
+    }
+    for (size_t q = 0; q + 1 < s->ev_used; q += 2) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, s->ev[q], s->ev[q + 1]) != hipSuccess) return YY_ERR_HIP;
+        const int c = s->ev_cls[q / 2];
+        ms[c] += t;
+        count[c] += 1;
+    }
+    return YY_NPROF;
+}
+
+const char *yy_profile_name(int32_t c)
+{
+    return (c >= 0 && c < YY_NPROF) ? prof_names[c] : nullptr;
 }
 
 int yy_internal_dims(const yy_shell *s, int64_t dims[4], int32_t *elem_bytes)

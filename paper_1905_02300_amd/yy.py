@@ -23,7 +23,8 @@ NNORMS = 10
 EXPORTS = ["yy_workspace_bytes", "yy_create", "yy_set_params", "yy_set_field", "yy_get_field",
            "yy_set_forcing", "yy_step", "yy_get_norms", "yy_destroy", "yy_strerror",
            "yy_internal_dims", "yy_fill", "yy_extrapolate", "yy_sweep", "yy_sweep_diffusion",
-           "yy_residual"]
+           "yy_residual", "yy_profile", "yy_profile_read", "yy_profile_name"]
+NPROF = 16
 
 
 class YYError(RuntimeError):
@@ -73,6 +74,10 @@ def load():
     L.yy_sweep.argtypes = [vp, i32, i32, vp, vp, vp]
     L.yy_sweep_diffusion.argtypes = [vp, i32, vp, vp, vp]
     L.yy_residual.argtypes = [vp, i32, vp, vp]
+    L.yy_profile.argtypes = [vp, i32]
+    L.yy_profile_read.argtypes = [vp, P(ctypes.c_double), P(i64), vp]
+    L.yy_profile_name.argtypes = [i32]
+    L.yy_profile_name.restype = ctypes.c_char_p
     _lib = L
     return L
 
@@ -219,6 +224,17 @@ class Shell:
     def residual(self, field, out, stream=None):
         _check(load().yy_residual(self.h, field, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)),
                "yy_residual")
+
+    def profile(self, enable=True):
+        _check(load().yy_profile(self.h, 1 if enable else 0), "yy_profile")
+
+    def profile_read(self, stream=None):
+        """{kernel class: (total ms, timed launch groups)} since profile(True)"""
+        L = load()
+        ms = (ctypes.c_double * NPROF)()
+        cnt = (ctypes.c_int64 * NPROF)()
+        _check(L.yy_profile_read(self.h, ms, cnt, _stream_ptr(stream)), "yy_profile_read")
+        return {L.yy_profile_name(c).decode(): (ms[c], cnt[c]) for c in range(NPROF)}
 
     # ---- layout helpers (host side) ----
     def to_internal(self, padded):
