@@ -217,10 +217,17 @@ static void for_targets(const yyo *h, int loc, target_fn fn, void *ctx)
     for (int j = jlo; j <= jhi; j++) { fn(h, loc, j, kb0, ctx); fn(h, loc, j, kb1, ctx); }
 }
 
+/* A tangential-velocity target interpolates both of the other patch's
+ * components (theta-face and phi-face grids), so both spans are checked. */
 static void check_target(const yyo *h, int loc, int j, int k, void *ctx)
 {
     int *ok = (int *)ctx;
-    if (!target_ok(h, loc, t_at(h, loc, j), p_at(h, loc, k))) *ok = 0;
+    double th = t_at(h, loc, j), ph = p_at(h, loc, k);
+    if (loc == FT || loc == FP) {
+        if (!target_ok(h, FT, th, ph) || !target_ok(h, FP, th, ph)) *ok = 0;
+    } else if (!target_ok(h, loc, th, ph)) {
+        *ok = 0;
+    }
 }
 
 /* ------------------------------------------------------------------ */

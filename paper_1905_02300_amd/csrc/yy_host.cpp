@@ -25,13 +25,14 @@ struct Layout {
     int prec;
     int64_t ncc, nvt, nvp;   // interpolation targets per class
     // byte offsets
-    int64_t off_fields, off_p, off_tab_r, off_tab_d, off_fill, off_partial, off_norms, total;
+    int64_t off_fields, off_p, off_tab_r, off_tab_d, off_ptab_r, off_ptab_d, off_fill, off_partial,
+        off_norms, total;
     int64_t elem;            // bytes per compute element
     int nR;                  // compute-precision arrays
 };
 
-int64_t ntab_r(const Dims &d) { return (d.nr + 2) + (d.nr + 3); }
-int64_t ntab_t(const Dims &d) { return 2 * (d.nt + 2) + 2 * (d.nt + 3); }
+int64_t ntab_r(const Dims &d) { return (d.nr + 2) + (d.nr + 3) + (int64_t)NTAB_R * (d.nr + 3); }
+int64_t ntab_t(const Dims &d) { return 2 * (d.nt + 2) + 2 * (d.nt + 3) + (int64_t)NTAB_T * (d.nt + 3); }
 
 // compute-precision arrays: T (3 levels) + T*, u (2x3x3) + u* (2x3),
 // forcing (4), residual, Thomas scratch
@@ -68,6 +69,10 @@ Layout make_layout(const yy_grid *g, int prec)
     o += align_up((ntab_r(L.d) + ntab_t(L.d)) * L.elem, ALIGN);
     L.off_tab_d = o;
     o += align_up((ntab_r(L.d) + ntab_t(L.d)) * 8, ALIGN);
+    L.off_ptab_r = o;
+    o += align_up(3 * ((int64_t)g->nr + 3 + g->nt + 3) * L.elem, ALIGN);
+    L.off_ptab_d = o;
+    o += align_up(3 * ((int64_t)g->nr + 3 + g->nt + 3) * 8, ALIGN);
     L.off_fill = o;
     o += align_up(L.ncc * (int64_t)sizeof(FillScalar) + (L.nvt + L.nvp) * (int64_t)sizeof(FillVector), ALIGN);
     L.off_partial = o;
@@ -196,15 +201,74 @@ bool build_fill(const Frame &F, const Dims &d, std::vector<FillScalar> &cc,
     return ok;
 }
 
+double safe_inv(double x) { return x != 0.0 ? 1.0 / x : 0.0; }
+
+// Position tables, then the coefficient tables of the split operators
+// (unit viscosity) in the order of the Geo members, all in FP64.
 template <typename R> void host_tables(const Frame &F, const Dims &d, std::vector<R> &v)
 {
     v.clear();
-    for (int i = -1; i <= d.nr; i++) v.push_back((R)(F.r1 + (i + 0.5) * F.dr));
-    for (int f = -1; f <= d.nr + 1; f++) v.push_back((R)(F.r1 + f * F.dr));
-    for (int j = -1; j <= d.nt; j++) v.push_back((R)std::sin(F.th0 + (j + 0.5) * F.dth));
-    for (int j = -1; j <= d.nt; j++) v.push_back((R)std::cos(F.th0 + (j + 0.5) * F.dth));
-    for (int f = -1; f <= d.nt + 1; f++) v.push_back((R)std::sin(F.th0 + f * F.dth));
-    for (int f = -1; f <= d.nt + 1; f++) v.push_back((R)std::cos(F.th0 + f * F.dth));
+    auto rc = [&](int i) { return F.r1 + (i + 0.5) * F.dr; };
+    auto rf = [&](int f) { return F.r1 + f * F.dr; };
+    auto sc = [&](int j) { return std::sin(F.th0 + (j + 0.5) * F.dth); };
+    auto cc = [&](int j) { return std::cos(F.th0 + (j + 0.5) * F.dth); };
+    auto sf = [&](int f) { return std::sin(F.th0 + f * F.dth); };
+    auto cf = [&](int f) { return std::cos(F.th0 + f * F.dth); };
+    for (int i = -1; i <= d.nr; i++) v.push_back((R)rc(i));
+    for (int f = -1; f <= d.nr + 1; f++) v.push_back((R)rf(f));
+    for (int j = -1; j <= d.nt; j++) v.push_back((R)sc(j));
+    for (int j = -1; j <= d.nt; j++) v.push_back((R)cc(j));
+    for (int f = -1; f <= d.nt + 1; f++) v.push_back((R)sf(f));
+    for (int f = -1; f <= d.nt + 1; f++) v.push_back((R)cf(f));
+    const double dr2 = F.dr * F.dr, dt2 = F.dth * F.dth, R12 = F.r1 * F.r1;
+    std::vector<std::vector<double>> tr(NTAB_R), tt(NTAB_T);
+    for (int e = -1; e <= d.nr + 1; e++) {
+        const double c0 = rc(e), f0 = rf(e), cm = rc(e - 1), fm = rf(e - 1), fp = rf(e + 1), c1 = rc(e + 1);
+        (void)c1;
+        tr[0].push_back(safe_inv(c0));
+        tr[1].push_back(safe_inv(f0));
+        tr[2].push_back(safe_inv(c0 * c0));
+        tr[3].push_back(safe_inv(f0 * f0));
+        // D_rr at centre i = e: faces e, e+1
+        tr[4].push_back(f0 * f0 * safe_inv(c0 * c0 * dr2));
+        tr[5].push_back(fp * fp * safe_inv(c0 * c0 * dr2));
+        // u_r at face f = e: D_rr(face) - 2/r^2 + (2/r^3) d_r(r^2 .)
+        const double lo0 = cm * cm * safe_inv(f0 * f0 * dr2), up0 = c0 * c0 * safe_inv(f0 * f0 * dr2);
+        const double k3 = 2.0 * safe_inv(f0 * f0 * f0) / (2.0 * F.dr);
+        tr[6].push_back(lo0 - k3 * fm * fm);
+        tr[7].push_back(up0 + k3 * fp * fp);
+        tr[8].push_back(-(lo0 + up0) - 2.0 * safe_inv(f0 * f0));
+        // D11 = G_r Div_r at face f = e
+        tr[9].push_back(fm * fm * safe_inv(cm * cm * dr2));
+        tr[10].push_back(fp * fp * safe_inv(c0 * c0 * dr2));
+        tr[11].push_back(-f0 * f0 * (safe_inv(c0 * c0) + safe_inv(cm * cm)) / dr2);
+    }
+    for (int e = -1; e <= d.nt + 1; e++) {
+        const double s0 = sc(e), sF = sf(e), sFm = sf(e - 1), sFp = sf(e + 1), sCm = sc(e - 1);
+        // Dhat_thth at theta-centre j = e and theta-face f = e
+        tt[0].push_back(sF * safe_inv(R12 * s0 * dt2));
+        tt[1].push_back(sFp * safe_inv(R12 * s0 * dt2));
+        tt[2].push_back(sCm * safe_inv(R12 * sF * dt2));
+        tt[3].push_back(s0 * safe_inv(R12 * sF * dt2));
+        // u_theta: -u/sin^2 + (2 cos/sin^2) d_th(sin u), times 1/r^2
+        const double w = 2.0 * cf(e) * safe_inv(sF * sF) / (2.0 * F.dth);
+        tt[4].push_back(-w * sFm);
+        tt[5].push_back(w * sFp);
+        tt[6].push_back(-safe_inv(sF * sF));
+        // D22 = G_th Div_th at theta-face f = e, times 1/r^2
+        tt[7].push_back(sFm * safe_inv(sCm * dt2));
+        tt[8].push_back(sFp * safe_inv(s0 * dt2));
+        tt[9].push_back(-sF * (safe_inv(s0) + safe_inv(sCm)) / dt2);
+        tt[10].push_back(safe_inv(2.0 * s0 * F.dph));
+        tt[11].push_back(safe_inv(2.0 * sF * F.dph));
+        tt[12].push_back(safe_inv(s0 * s0));
+        tt[13].push_back(safe_inv(sF * sF));
+        tt[14].push_back(cc(e) * safe_inv(s0));
+    }
+    for (auto &t : tr)
+        for (double x : t) v.push_back((R)x);
+    for (auto &t : tt)
+        for (double x : t) v.push_back((R)x);
 }
 
 template <typename R> void bind_geo(Geo<R> &g, const R *base, const Dims &d, const Frame &F)
@@ -215,12 +279,48 @@ template <typename R> void bind_geo(Geo<R> &g, const R *base, const Dims &d, con
     g.cc = g.sc + (d.nt + 2);
     g.sf = g.cc + (d.nt + 2);
     g.cf = g.sf + (d.nt + 3);
+    const R *tr = g.cf + (d.nt + 3);
+    const int64_t lr = d.nr + 3, lt = d.nt + 3;
+    const R **rt[NTAB_R] = {&g.ir_c, &g.ir_f, &g.ir2_c, &g.ir2_f, &g.rc_lo, &g.rc_up,
+                            &g.rf_lo, &g.rf_up, &g.rf_di, &g.gf_lo, &g.gf_up, &g.gf_di};
+    for (int q = 0; q < NTAB_R; q++) *rt[q] = tr + q * lr;
+    const R *tt = tr + NTAB_R * lr;
+    const R **tp[NTAB_T] = {&g.tc_lo, &g.tc_up, &g.tf_lo, &g.tf_up, &g.ef_lo, &g.ef_up, &g.ef_di,
+                            &g.gt_lo, &g.gt_up, &g.gt_di, &g.h2p_c, &g.h2p_f, &g.is2_c, &g.is2_f,
+                            &g.cot_c};
+    for (int q = 0; q < NTAB_T; q++) *tp[q] = tt + q * lt;
+    g.h2r = (R)(1.0 / (2.0 * F.dr));
+    g.h2t = (R)(1.0 / (2.0 * F.dth));
+    g.idph2 = (R)(1.0 / (F.dph * F.dph));
     g.dr = (R)F.dr;
     g.dth = (R)F.dth;
     g.dph = (R)F.dph;
     g.r1 = (R)F.r1;
     const double th1 = M_PI / 4.0 - F.delta;
     g.cphat = (R)(1.0 / (F.r1 * F.r1 * std::sin(th1) * std::sin(th1) * F.dph * F.dph));
+}
+
+// parameter-dependent tables: Pr * (u_r radial) + (1/(2 chi)) * D11 per
+// r-face, and Pr * (u_theta extra) + (1/(2 chi)) * D22 per theta-face
+template <typename R>
+int upload_param_tables(Geo<R> &g, const Frame &F, const Dims &d, const yy_params &p, char *dev)
+{
+    std::vector<double> td;
+    host_tables<double>(F, d, td);
+    const int64_t lr = d.nr + 3, lt = d.nt + 3;
+    const double *tr = td.data() + (d.nr + 2) + (d.nr + 3) + 2 * (d.nt + 2) + 2 * (d.nt + 3);
+    const double *tt = tr + NTAB_R * lr;
+    const double pr = p.pr, ic = 1.0 / (2.0 * p.chi);
+    std::vector<R> v;
+    for (int q = 0; q < 3; q++)
+        for (int64_t e = 0; e < lr; e++) v.push_back((R)(pr * tr[(6 + q) * lr + e] + ic * tr[(9 + q) * lr + e]));
+    for (int q = 0; q < 3; q++)
+        for (int64_t e = 0; e < lt; e++) v.push_back((R)(pr * tt[(4 + q) * lt + e] + ic * tt[(7 + q) * lt + e]));
+    if (hipMemcpy(dev, v.data(), v.size() * sizeof(R), hipMemcpyHostToDevice) != hipSuccess) return YY_ERR_HIP;
+    const R *b = (const R *)dev;
+    g.fr_lo = b; g.fr_up = b + lr; g.fr_di = b + 2 * lr;
+    g.ft_lo = b + 3 * lr; g.ft_up = g.ft_lo + lt; g.ft_di = g.ft_lo + 2 * lt;
+    return YY_OK;
 }
 
 template <typename R> void set_coefs(Geo<R> &g, const yy_params &p)
@@ -529,6 +629,15 @@ int yy_set_params(yy_shell *s, const yy_params *p)
     set_coefs<double>(s->gd, *p);
     set_coefs<double>(s->g64, *p);
     set_coefs<float>(s->g32, *p);
+    int st = upload_param_tables<double>(s->gd, s->F, s->L.d, *p, s->ws + s->L.off_ptab_d);
+    if (st != YY_OK) return st;
+    if (s->L.prec == YY_FP64) {
+        s->g64.fr_lo = s->gd.fr_lo; s->g64.fr_up = s->gd.fr_up; s->g64.fr_di = s->gd.fr_di;
+        s->g64.ft_lo = s->gd.ft_lo; s->g64.ft_up = s->gd.ft_up; s->g64.ft_di = s->gd.ft_di;
+    } else {
+        st = upload_param_tables<float>(s->g32, s->F, s->L.d, *p, s->ws + s->L.off_ptab_r);
+        if (st != YY_OK) return st;
+    }
     s->have_params = true;
     s->need_fill = true;   // wall values may have changed
     return YY_OK;

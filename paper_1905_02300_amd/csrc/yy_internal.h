@@ -33,7 +33,27 @@ template <typename R> struct Geo {
     R ht, tau, inv_tau;
     R pr, ic, prra; // Pr, 1/(2 chi), Pr*Ra
     double inv_chi;
+    // Coefficient tables of the split operators (unit viscosity, built in
+    // FP64 on the host), index i+1 / f+1 / j+1 as above; they replace the
+    // per-point divisions of the metric factors.
+    const R *ir_c, *ir_f, *ir2_c, *ir2_f;   // 1/r, 1/r^2 at r-centres, r-faces
+    const R *rc_lo, *rc_up;                 // D_rr at r-centres
+    const R *rf_lo, *rf_up, *rf_di;         // u_r radial viscous operator at r-faces
+    const R *gf_lo, *gf_up, *gf_di;         // D11 at r-faces
+    const R *tc_lo, *tc_up;                 // Dhat_thth at theta-centres
+    const R *tf_lo, *tf_up;                 // Dhat_thth at theta-faces
+    const R *ef_lo, *ef_up, *ef_di;         // u_theta extra viscous terms (x 1/r^2)
+    const R *gt_lo, *gt_up, *gt_di;         // D22 at theta-faces (x 1/r^2)
+    const R *h2p_c, *h2p_f;                 // 1/(2 sin(theta) dphi), centres / faces
+    const R *is2_c, *is2_f;                 // 1/sin^2(theta), centres / faces
+    const R *cot_c;                         // cot(theta) at centres
+    R h2r, h2t, idph2;                      // 1/(2 dr), 1/(2 dtheta), 1/dphi^2
+    // parameter-dependent combinations (rebuilt when Pr or chi change):
+    // Pr * rf_* + ic * gf_* (u_r radial operator) and Pr * ef_* + ic * gt_*
+    const R *fr_lo, *fr_up, *fr_di, *ft_lo, *ft_up, *ft_di;
 };
+constexpr int NTAB_R = 12;   // per-r coefficient tables (length nr+3)
+constexpr int NTAB_T = 15;   // per-theta coefficient tables (length nt+3)
 
 // one interpolation target of a scalar (centre-type in theta and phi)
 struct FillScalar {
@@ -91,5 +111,8 @@ void io_double(const Dims &d, double *internal, const double *ext, double *ext_o
                int layout, hipStream_t st);
 void reduce_norms(const double *partial, const int *nblocks_dev, double *out, hipStream_t st);
 void zero_doubles(double *p, int64_t n, hipStream_t st);
+// choose the register-resident partitioned line solver (default) or the
+// per-line Thomas kernel
+void set_partitioned(bool on);
 
 }  // namespace yy

@@ -62,76 +62,51 @@ template <int L, int D, typename R>
 __device__ __forceinline__ Tri<R> coef(const Geo<R> &g, int i, int j, R ar, R at, R ap, R nu)
 {
     Tri<R> c;
-    const R r0 = r_of<L>(g, i);
     if (D == 0) {
-        const R q = R(1) / (r0 * r0 * g.dr * g.dr);
         if (L == FR) {
-            const R rm = g.rc[i], rp = g.rc[i + 1];           // centres i-1, i
-            const R fm = g.rf[i], fp = g.rf[i + 2];           // faces i-1, i+1
-            c.lo = nu * rm * rm * q;
-            c.up = nu * rp * rp * q;
-            c.di = -nu * (rm * rm + rp * rp) * q - nu * R(2) / (r0 * r0);
-            const R k3 = nu * R(2) / (r0 * r0 * r0) / (R(2) * g.dr);
-            c.lo -= k3 * fm * fm;
-            c.up += k3 * fp * fp;
-            const R dr2 = g.dr * g.dr;
-            c.lo += g.ic * fm * fm / (rm * rm * dr2);
-            c.up += g.ic * fp * fp / (rp * rp * dr2);
-            c.di -= g.ic * r0 * r0 * (R(1) / (rp * rp) + R(1) / (rm * rm)) / dr2;
+            // u_r is always a velocity unknown: nu = Pr, combined on the host
+            c.lo = g.fr_lo[i + 1];
+            c.up = g.fr_up[i + 1];
+            c.di = g.fr_di[i + 1];
         } else {
-            const R fm = g.rf[i + 1], fp = g.rf[i + 2];       // faces i, i+1
-            c.lo = nu * fm * fm * q;
-            c.up = nu * fp * fp * q;
-            c.di = -nu * (fm * fm + fp * fp) * q;
+            const R lo = g.rc_lo[i + 1], up = g.rc_up[i + 1];
+            c.lo = nu * lo;
+            c.up = nu * up;
+            c.di = -nu * (lo + up);
         }
-        const R a = ar / (R(2) * g.dr);
+        const R a = ar * g.h2r;
         c.lo += a;
         c.up -= a;
     } else if (D == 1) {
-        const R s0 = s_of<L>(g, j);
-        const R q = R(1) / (g.r1 * g.r1 * s0 * g.dth * g.dth);
+        const R ir = L == FR ? g.ir_f[i + 1] : g.ir_c[i + 1];
         if (L == FT) {
-            const R sm = g.sc[j], sp = g.sc[j + 1];           // centres j-1, j
-            const R fm = g.sf[j], fp = g.sf[j + 2];           // faces j-1, j+1
-            const R c0 = g.cf[j + 1];
-            c.lo = nu * sm * q;
-            c.up = nu * sp * q;
-            c.di = -nu * (sm + sp) * q;
-            const R e = nu / (r0 * r0 * s0 * s0);
-            c.di -= e;
-            const R k2 = R(2) * c0 * e / (R(2) * g.dth);
-            c.lo -= k2 * fm;
-            c.up += k2 * fp;
-            c.di -= ar / r0;
-            const R q2 = R(1) / (r0 * r0 * g.dth * g.dth);
-            c.lo += g.ic * fm * q2 / sm;
-            c.up += g.ic * fp * q2 / sp;
-            c.di -= g.ic * s0 * q2 * (R(1) / sp + R(1) / sm);
+            const R lo = g.tf_lo[j + 1], up = g.tf_up[j + 1];
+            const R ir2 = g.ir2_c[i + 1];
+            c.lo = nu * lo + ir2 * g.ft_lo[j + 1];
+            c.up = nu * up + ir2 * g.ft_up[j + 1];
+            c.di = -nu * (lo + up) + ir2 * g.ft_di[j + 1] - ar * ir;
         } else {
-            const R fm = g.sf[j + 1], fp = g.sf[j + 2];       // faces j, j+1
-            c.lo = nu * fm * q;
-            c.up = nu * fp * q;
-            c.di = -nu * (fm + fp) * q;
+            const R lo = g.tc_lo[j + 1], up = g.tc_up[j + 1];
+            c.lo = nu * lo;
+            c.up = nu * up;
+            c.di = -nu * (lo + up);
         }
-        const R a = at / (R(2) * r0 * g.dth);
+        const R a = at * ir * g.h2t;
         c.lo += a;
         c.up -= a;
     } else {
-        const R s0 = s_of<L>(g, j);
+        const R ir = L == FR ? g.ir_f[i + 1] : g.ir_c[i + 1];
         c.lo = nu * g.cphat;
         c.up = nu * g.cphat;
         c.di = R(-2) * nu * g.cphat;
         if (L == FP) {
-            const R c0 = c_of<L>(g, j);
-            const R e = R(1) / (r0 * r0 * s0 * s0);
-            c.di -= nu * e;
-            c.di -= (ar + at * c0 / s0) / r0;
-            const R q3 = g.ic * e / (g.dph * g.dph);
+            const R ir2 = g.ir2_c[i + 1], e = g.is2_c[j + 1];
+            const R q3 = g.ic * e * g.idph2 * ir2;
+            c.di += -nu * e * ir2 - (ar + at * g.cot_c[j + 1]) * ir - R(2) * q3;
             c.lo += q3;
             c.up += q3;
-            c.di -= R(2) * q3;
         }
-        const R a = ap / (R(2) * r0 * s0 * g.dph);
+        const R a = ap * ir * (L == FT ? g.h2p_f[j + 1] : g.h2p_c[j + 1]);
         c.lo += a;
         c.up -= a;
     }
@@ -441,7 +416,7 @@ __device__ R source(const Dims &d, const Geo<R> &g, const RhsIn<R> &in, int64_t 
 }
 
 template <typename R, int L>
-__global__ void k_residual(Dims d, Geo<R> g, State<R> s, RhsIn<R> in, R *out)
+__global__ void __launch_bounds__(256) k_residual(Dims d, Geo<R> g, State<R> s, RhsIn<R> in, R *out)
 {
     const int p = blockIdx.y;
     const int i0 = ulo<L>(0), j0 = ulo<L>(1), k0 = ulo<L>(2);
@@ -551,6 +526,344 @@ __global__ void __launch_bounds__(256) k_sweep(Dims d, Geo<R> g, Geo<double> gd,
     }
 }
 
+// ---------------------------------------------------------------------------
+// a5 (register-resident form): partitioned line solve.  A line of n
+// unknowns is split into P chunks of 2..M consecutive rows, one chunk per
+// thread, held in registers.  Each chunk is reduced by two-way elimination
+// (forward, then backward) to rows written through its own first and last
+// unknowns; the 2P reduced rows form a tridiagonal system solved by one
+// thread per line (Thomas), after which every chunk recovers its interior.
+// The line is read once and written once: no c'/d' round trip to memory.
+// ---------------------------------------------------------------------------
+// Forward elimination of row m of a chunk as it is assembled (row m:
+// lo x_{m-1} + di x_m + up x_{m+1} = rhs).  Rows 0 and 1 are normalised;
+// rows m >= 2 are rewritten through the chunk's first unknown x_0.
+template <typename R, int M>
+__device__ __forceinline__ void chunk_forward(R (&a)[M], R (&c)[M], R (&d)[M], int m, R lo, R di,
+                                              R up, R rhs)
+{
+    if (m < 2) {
+        const R r = R(1) / di;
+        a[m] = lo * r;
+        c[m] = up * r;
+        d[m] = rhs * r;
+    } else {
+        const R r = R(1) / (di - lo * c[m - 1]);
+        d[m] = r * (rhs - lo * d[m - 1]);
+        c[m] = r * up;
+        a[m] = -r * lo * a[m - 1];
+    }
+}
+
+// Backward elimination: rows 1..mt-2 become a_i x_0 + x_i + c_i x_{mt-1} =
+// d_i; row 0 becomes a_0 x_{-1} + x_0 + c_0 x_{mt-1} = d_0 (two-way
+// elimination of a partitioned tridiagonal solve).
+template <typename R, int M>
+__device__ __forceinline__ void chunk_backward(R (&a)[M], R (&c)[M], R (&d)[M], int mt)
+{
+#pragma unroll
+    for (int i = M - 3; i >= 1; i--) {
+        if (i <= mt - 3) {
+            d[i] = d[i] - c[i] * d[i + 1];
+            a[i] = a[i] - c[i] * a[i + 1];
+            c[i] = -c[i] * c[i + 1];
+        }
+    }
+    if (mt >= 3) {
+        const R r = R(1) / (R(1) - c[0] * a[1]);
+        d[0] = r * (d[0] - c[0] * d[1]);
+        a[0] = r * a[0];
+        c[0] = -r * c[0] * c[1];
+    }
+}
+
+// last row of a chunk (runtime index into a register array)
+template <typename R, int M>
+__device__ __forceinline__ void chunk_last(const R (&a)[M], const R (&c)[M], const R (&d)[M], int mt,
+                                           R &ga, R &gc, R &gd)
+{
+    ga = a[0]; gc = c[0]; gd = d[0];
+#pragma unroll
+    for (int i = 1; i < M; i++)
+        if (i == mt - 1) { ga = a[i]; gc = c[i]; gd = d[i]; }
+}
+
+// Thomas over the 2P reduced rows (lower, upper, rhs; unit diagonal) kept in
+// a strided array: row r at base[r * rs]; overwrites rhs with the solution.
+template <typename R>
+__device__ __forceinline__ void reduced_solve(R *lo, R *up, R *rhs, int nrow, int rs)
+{
+    R cp = R(0), dp = R(0);
+    for (int r = 0; r < nrow; r++) {
+        const R l = lo[r * rs];
+        const R den = R(1) - l * cp;
+        cp = up[r * rs] / den;
+        dp = (rhs[r * rs] - l * dp) / den;
+        up[r * rs] = cp;
+        rhs[r * rs] = dp;
+    }
+    R xn = R(0);
+    for (int r = nrow - 1; r >= 0; r--) {
+        xn = rhs[r * rs] - up[r * rs] * xn;
+        rhs[r * rs] = xn;
+    }
+}
+
+// one row of the line system (I - tau/2 L) at global row g of n
+template <typename R, int L, int D, bool DIFF>
+__device__ __forceinline__ void line_row(const Dims &d, const Geo<R> &g, const State<R> &s, int64_t q,
+                                         int ii, int jj, int gr, int n, R nu, R &lo, R &di, R &up)
+{
+    R ar = R(0), at = R(0), ap = R(0);
+    if (!DIFF) adv<L>(s, d, q, ar, at, ap);
+    const Tri<R> c = coef<L, D>(g, ii, jj, ar, at, ap, nu);
+    lo = gr > 0 ? -g.ht * c.lo : R(0);
+    up = gr < n - 1 ? -g.ht * c.up : R(0);
+    di = R(1) - g.ht * c.di;
+    if (D == 0 && L != FR) {
+        if (gr == 0) di = R(1) - g.ht * (c.di - c.lo);
+        if (gr == n - 1) di = R(1) - g.ht * (c.di - c.up);
+    }
+}
+
+template <int L, int D> __device__ __forceinline__ double vol_at(const Geo<double> &gd, int ii, int jj)
+{
+    const double r0 = L == FR ? gd.rf[ii + 1] : gd.rc[ii + 1];
+    const double s0 = L == FT ? gd.sf[jj + 1] : gd.sc[jj + 1];
+    return r0 * r0 * s0 * gd.dr * gd.dth * gd.dph;
+}
+
+// Strided lines (D = 0: r, D = 1: theta).  Block (W, P): lane x <-> k (W
+// consecutive k, coalesced), y <-> chunk.  A task = (k-tile, other index).
+template <typename R, int L, int D, int MODE, bool DIFF, int M>
+__global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<double> gd, State<R> s,
+                                                        const R *x, R *y, R *psi, double *partial)
+{
+    extern __shared__ unsigned char smem_raw[];
+    R *sm = reinterpret_cast<R *>(smem_raw);
+    const int W = blockDim.x, P = blockDim.y;
+    const int lane = threadIdx.x, t = threadIdx.y;
+    const int p = blockIdx.y;
+    const int i0 = ulo<L>(0), j0 = ulo<L>(1), k0 = ulo<L>(2);
+    const int m0 = D == 0 ? i0 : j0;
+    const int n = ncell(d, D) - m0;
+    const int nk = d.np - k0;
+    const int nother = D == 0 ? d.nt - j0 : d.nr - i0;
+    const int ntile = (nk + W - 1) / W;
+    const int64_t stride = D == 0 ? d.sI : d.sJ;
+    const R nu = (L == CC && !DIFF) ? R(1) : g.pr;
+    // chunk rows [r0, r1)
+    const int r0 = (int)((int64_t)t * n / P), r1 = (int)((int64_t)(t + 1) * n / P);
+    const int mt = r1 - r0;
+    // reduced rows in LDS: [2P rows][3 values][W lanes]
+    R *rlo = sm, *rup = sm + 2 * P * W, *rrh = sm + 4 * P * W;
+    double acc = 0.0;
+    for (int task = blockIdx.x; task < ntile * nother; task += gridDim.x) {
+        const int tile = task % ntile, oth = task / ntile;
+        const int k = k0 + tile * W + lane;
+        const bool live = (k - k0) < nk;
+        int i = 0, j = 0;
+        if (D == 0) j = j0 + oth; else i = i0 + oth;
+        R a[M], c[M], dd[M];
+        const int64_t qf = ix(d, p, D == 0 ? m0 + r0 : i, D == 1 ? m0 + r0 : j, k);
+        if (live) {
+#pragma unroll
+            for (int m = 0; m < M; m++) {
+                if (m < mt) {
+                    const int gr = r0 + m;
+                    const int ii = D == 0 ? m0 + gr : i, jj = D == 1 ? m0 + gr : j;
+                    const int64_t q = qf + (int64_t)m * stride;
+                    R lo, di, up;
+                    line_row<R, L, D, DIFF>(d, g, s, q, ii, jj, gr, n, nu, lo, di, up);
+                    chunk_forward<R, M>(a, c, dd, m, lo, di, up, x[q]);
+                } else {
+                    a[m] = R(0); c[m] = R(0); dd[m] = R(0);
+                }
+            }
+            chunk_backward<R, M>(a, c, dd, mt);
+            R ga, gc, gdv;
+            chunk_last<R, M>(a, c, dd, mt, ga, gc, gdv);
+            if (mt == 1) { ga = R(0); }
+            rlo[(2 * t) * W + lane] = a[0];
+            rup[(2 * t) * W + lane] = c[0];
+            rrh[(2 * t) * W + lane] = dd[0];
+            rlo[(2 * t + 1) * W + lane] = mt == 1 ? R(0) : ga;
+            rup[(2 * t + 1) * W + lane] = mt == 1 ? R(0) : gc;
+            rrh[(2 * t + 1) * W + lane] = mt == 1 ? R(0) : gdv;
+        }
+        __syncthreads();
+        if (t == 0 && live) reduced_solve<R>(rlo + lane, rup + lane, rrh + lane, 2 * P, W);
+        __syncthreads();
+        if (live) {
+            const R xs = rrh[(2 * t) * W + lane];
+            const R xe = mt == 1 ? xs : rrh[(2 * t + 1) * W + lane];
+#pragma unroll
+            for (int m = 0; m < M; m++) {
+                if (m < mt) {
+                    const R v = (m == 0) ? xs : (m == mt - 1 ? xe : dd[m] - a[m] * xs - c[m] * xe);
+                    const int gr = r0 + m;
+                    const int ii = D == 0 ? m0 + gr : i, jj = D == 1 ? m0 + gr : j;
+                    const int64_t q = qf + (int64_t)m * stride;
+                    if (MODE == 0) {
+                        y[q] = v;
+                    } else {
+                        psi[q] += v;
+                        acc += vol_at<L, D>(gd, ii, jj) * (double)v * (double)v;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (MODE == 1) {
+        // block_sum needs a 1-D thread index: flatten
+        double v = acc;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        __shared__ double red[16];
+        const int flat = t * W + lane;
+        if ((flat & 63) == 0) red[flat >> 6] = v;
+        __syncthreads();
+        if (flat == 0) {
+            double tot = 0.0;
+            const int nw = (W * P) >> 6;
+            for (int w = 0; w < nw; w++) tot += red[w];
+            partial[p * NBMAX + blockIdx.x] = tot;
+        }
+    }
+}
+
+// Contiguous lines (D = 2, phi).  One wave per line, one chunk per lane;
+// 4 lines per 256-thread block.  A task = one (i, j) line.
+template <typename R, int L, int MODE, bool DIFF, int M>
+__global__ void __launch_bounds__(256) k_sweep_contig(Dims d, Geo<R> g, Geo<double> gd, State<R> s,
+                                                      const R *x, R *y, R *psi, double *partial, int P)
+{
+    __shared__ R rlo[4][128], rup[4][128], rrh[4][128];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int p = blockIdx.y;
+    const int i0 = ulo<L>(0), j0 = ulo<L>(1), k0 = ulo<L>(2);
+    const int n = d.np - k0;
+    const int ni = d.nr - i0, nj = d.nt - j0;
+    const int64_t nlines = (int64_t)ni * nj;
+    const R nu = (L == CC && !DIFF) ? R(1) : g.pr;
+    const int r0 = (int)((int64_t)lane * n / P), r1 = (int)((int64_t)(lane + 1) * n / P);
+    const int mt = lane < P ? r1 - r0 : 0;
+    double acc = 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * 4; base < nlines; base += (int64_t)gridDim.x * 4) {
+        const int64_t line = base + w;
+        const bool live = line < nlines && mt > 0;
+        const int i = i0 + (int)(line / nj), j = j0 + (int)(line % nj);
+        R a[M], c[M], dd[M];
+        if (live) {
+            const int64_t q0 = ix(d, p, i, j, k0 + r0);
+#pragma unroll
+            for (int m = 0; m < M; m++) {
+                if (m < mt) {
+                    R lo, di, up;
+                    line_row<R, L, 2, DIFF>(d, g, s, q0 + m, i, j, r0 + m, n, nu, lo, di, up);
+                    chunk_forward<R, M>(a, c, dd, m, lo, di, up, x[q0 + m]);
+                } else {
+                    a[m] = R(0); c[m] = R(0); dd[m] = R(0);
+                }
+            }
+            chunk_backward<R, M>(a, c, dd, mt);
+            R ga, gc, gdv;
+            chunk_last<R, M>(a, c, dd, mt, ga, gc, gdv);
+            rlo[w][2 * lane] = a[0];
+            rup[w][2 * lane] = c[0];
+            rrh[w][2 * lane] = dd[0];
+            rlo[w][2 * lane + 1] = ga;
+            rup[w][2 * lane + 1] = gc;
+            rrh[w][2 * lane + 1] = gdv;
+        }
+        __syncthreads();
+        if (lane == 0 && line < nlines) reduced_solve<R>(rlo[w], rup[w], rrh[w], 2 * P, 1);
+        __syncthreads();
+        if (live) {
+            const R xs = rrh[w][2 * lane], xe = rrh[w][2 * lane + 1];
+            const int64_t q0 = ix(d, p, i, j, k0 + r0);
+#pragma unroll
+            for (int m = 0; m < M; m++) {
+                if (m < mt) {
+                    const R v = (m == 0) ? xs : (m == mt - 1 ? xe : dd[m] - a[m] * xs - c[m] * xe);
+                    if (MODE == 0) {
+                        y[q0 + m] = v;
+                    } else {
+                        psi[q0 + m] += v;
+                        acc += vol_at<L, 2>(gd, i, j) * (double)v * (double)v;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (MODE == 1) {
+        const double tot = block_sum(acc);
+        if (threadIdx.x == 0) partial[p * NBMAX + blockIdx.x] = tot;
+    }
+}
+
+// Launch the partitioned solver when the line fits the register chunks,
+// else the per-line Thomas kernel.  Returns false if it fell back.
+template <typename R, int L, int D, int MODE, bool DIFF>
+static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double> &gd,
+                               const State<R> &s, const R *x, R *y, R *psi, double *partial,
+                               int *nblocks, hipStream_t st)
+{
+    const int i0 = ulo<L>(0), j0 = ulo<L>(1), k0 = ulo<L>(2);
+    if (D < 2) {
+        // the u_theta polar sweep reads the most per-row data: smaller chunks
+        constexpr int M = (L == FT && D == 1) ? 12 : 16;
+        const int n = ncell(d, D) - (D == 0 ? i0 : j0);
+        int P = (n + M - 1) / M;
+        if (P < 1) P = 1;
+        // W lanes (consecutive k) per chunk row; W * P <= 512 and a whole
+        // number of 64-lane waves
+        int W = 64;
+        while (W * P > 512 && W > 8) W >>= 1;
+        const int q = 64 / W;
+        P = (P + q - 1) / q * q;
+        if (W * P > 512 || P > n) return false;
+        const int nk = d.np - k0;
+        const int nother = D == 0 ? d.nt - j0 : d.nr - i0;
+        int64_t tasks = (int64_t)((nk + W - 1) / W) * nother;
+        int64_t b = tasks;
+        if (b > NBMAX) b = NBMAX;
+        if (nblocks) *nblocks = (int)b;
+        const size_t lds = (size_t)6 * P * W * sizeof(R);
+        hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, M>), dim3((unsigned)b, 2), dim3(W, P),
+                           lds, st, d, g, gd, s, x, y, psi, partial);
+        return true;
+    } else {
+        const int n = d.np - k0;
+        int P = n / 2;
+        if (P > 64) P = 64;
+        if (P < 1) P = 1;
+        const int need = (n + P - 1) / P;
+        if (need > 32) return false;
+        const int64_t nlines = (int64_t)(d.nr - i0) * (d.nt - j0);
+        int64_t b = (nlines + 3) / 4;
+        if (b > NBMAX) b = NBMAX;
+        if (nblocks) *nblocks = (int)b;
+        if (need <= 8)
+            hipLaunchKernelGGL((k_sweep_contig<R, L, MODE, DIFF, 8>), dim3((unsigned)b, 2), dim3(256), 0, st,
+                               d, g, gd, s, x, y, psi, partial, P);
+        else if (need <= 16)
+            hipLaunchKernelGGL((k_sweep_contig<R, L, MODE, DIFF, 16>), dim3((unsigned)b, 2), dim3(256), 0, st,
+                               d, g, gd, s, x, y, psi, partial, P);
+        else if (need <= 24)
+            hipLaunchKernelGGL((k_sweep_contig<R, L, MODE, DIFF, 24>), dim3((unsigned)b, 2), dim3(256), 0, st,
+                               d, g, gd, s, x, y, psi, partial, P);
+        else
+            hipLaunchKernelGGL((k_sweep_contig<R, L, MODE, DIFF, 32>), dim3((unsigned)b, 2), dim3(256), 0, st,
+                               d, g, gd, s, x, y, psi, partial, P);
+        return true;
+    }
+}
+
+static bool use_partitioned = true;
+void set_partitioned(bool on) { use_partitioned = on; }
+
 template <typename R, int L, int D, int MODE, bool DIFF>
 static void launch_sweep(const Dims &d, const Geo<R> &g, const Geo<double> &gd, const State<R> &s,
                          const R *x, R *y, R *psi, double *partial, int *nblocks, hipStream_t st)
@@ -558,6 +871,8 @@ static void launch_sweep(const Dims &d, const Geo<R> &g, const Geo<double> &gd, 
     const int i0 = ulo<L>(0), j0 = ulo<L>(1), k0 = ulo<L>(2);
     const int nA = D == 0 ? d.nt - j0 : d.nr - i0;
     const int nB = D == 2 ? d.nt - j0 : d.np - k0;
+    if (use_partitioned && launch_partitioned<R, L, D, MODE, DIFF>(d, g, gd, s, x, y, psi, partial, nblocks, st))
+        return;
     int64_t b = ((int64_t)nA * nB + 255) / 256;
     if (MODE == 1 && b > NBMAX) b = NBMAX;
     if (nblocks) *nblocks = (int)b;

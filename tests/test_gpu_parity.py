@@ -94,6 +94,28 @@ def test_sweep_parity(oracle_lib, yy, field, d):
     assert _rel(got[m], ref[m]) <= TOL
 
 
+@pytest.mark.parametrize("shape", [(40, 48, 144), (12, 200, 600), (4, 8, 1152), (130, 9, 12)])
+@pytest.mark.parametrize("field", [I.T, I.U2R, I.U2T, I.U2P])
+def test_sweep_parity_line_lengths(oracle_lib, yy, shape, field):
+    """Line lengths that split into several register chunks per line
+    (strided r/theta blocks of 1..32 chunks, ragged k-tiles; phi lines of
+    up to 1152 points, 18 rows per lane)."""
+    print(f"case: sweep field {field} shape {shape}", flush=True)
+    o, g = _pair(oracle_lib, yy, *shape, pr=1.3, dt=0.02, chi=0.8)
+    rng = np.random.default_rng(300 + field + sum(shape))
+    _set_random(o, g, rng, [0, 1], scale=0.5)
+    o.extrapolate()
+    g.extrapolate()
+    m = _unknown_mask(o.padded_shape(), field)
+    for d in range(3):
+        x = rng.uniform(-1, 1, o.padded_shape())
+        ref = o.sweep(field, d, x)
+        yt = g.internal_tensor()
+        g.sweep(field, d, g.to_internal(x), yt)
+        got = g.from_internal(yt).cpu().numpy()
+        assert _rel(got[m], ref[m]) <= TOL, (d, _rel(got[m], ref[m]))
+
+
 @pytest.mark.parametrize("d", [0, 1, 2])
 def test_sweep_diffusion_parity(oracle_lib, yy, d):
     print(f"case: sweep_diffusion dir {d}", flush=True)
