@@ -101,7 +101,7 @@ def test_sweep_parity_line_lengths(oracle_lib, yy, shape, field):
     (strided r/theta blocks of 1..32 chunks, ragged k-tiles; phi lines of
     up to 1152 points, 18 rows per lane)."""
     print(f"case: sweep field {field} shape {shape}", flush=True)
-    o, g = _pair(oracle_lib, yy, *shape, pr=1.3, dt=0.02, chi=0.8)
+    o, g = _pair(oracle_lib, yy, *shape, pr=1.3, dt=1e-3, chi=0.8)
     rng = np.random.default_rng(300 + field + sum(shape))
     _set_random(o, g, rng, [0, 1], scale=0.5)
     o.extrapolate()
