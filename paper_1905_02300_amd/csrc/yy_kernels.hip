@@ -577,6 +577,44 @@ __device__ __forceinline__ void chunk_backward(R (&a)[M], R (&c)[M], R (&d)[M], 
     }
 }
 
+// Reduced system of a partitioned solve.  Chunk t keeps two rows,
+//   S_t: al_t x_{e(t-1)} + x_{s(t)} + be_t x_{e(t)}   = de_t   (its first row)
+//   E_t: ga_t x_{s(t)}   + x_{e(t)} + et_t x_{s(t+1)} = ze_t   (its last row)
+// Eliminating the first unknowns x_s with S_t and S_{t+1} leaves one row per
+// chunk in the last unknowns only:
+//   A_t x_{e(t-1)} + B_t x_{e(t)} + C_t x_{e(t+1)} = D_t,
+// solved by parallel cyclic reduction (all chunks at once, log2 P levels).
+template <typename R> struct Row4 { R a, b, c, d; };
+
+template <typename R>
+__device__ __forceinline__ Row4<R> erow(R al, R be, R de, R ga, R et, R ze, R al1, R be1, R de1)
+{
+    Row4<R> r;
+    r.a = -ga * al;
+    r.b = R(1) - ga * be - et * al1;
+    r.c = -et * be1;
+    r.d = ze - ga * de - et * de1;
+    return r;
+}
+
+// one PCR level: combine row t with rows t-h (m) and t+h (p)
+template <typename R>
+__device__ __forceinline__ Row4<R> pcr_level(const Row4<R> &t, const Row4<R> &m, const Row4<R> &p)
+{
+    const R k1 = t.a / m.b, k2 = t.c / p.b;
+    Row4<R> o;
+    o.a = -k1 * m.a;
+    o.c = -k2 * p.c;
+    o.b = t.b - k1 * m.c - k2 * p.a;
+    o.d = t.d - k1 * m.d - k2 * p.d;
+    return o;
+}
+
+template <typename R> __device__ __forceinline__ R shfl_r(R v, int src)
+{
+    return __shfl(v, src, 64);
+}
+
 // last row of a chunk (runtime index into a register array)
 template <typename R, int M>
 __device__ __forceinline__ void chunk_last(const R (&a)[M], const R (&c)[M], const R (&d)[M], int mt,
@@ -655,8 +693,8 @@ __global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<dou
     // chunk rows [r0, r1)
     const int r0 = (int)((int64_t)t * n / P), r1 = (int)((int64_t)(t + 1) * n / P);
     const int mt = r1 - r0;
-    // reduced rows in LDS: [2P rows][3 values][W lanes]
-    R *rlo = sm, *rup = sm + 2 * P * W, *rrh = sm + 4 * P * W;
+    // reduced-system exchange in LDS: four [P][W] arrays
+    R *sA = sm, *sB = sm + P * W, *sC = sm + 2 * P * W, *sD = sm + 3 * P * W;
     double acc = 0.0;
     for (int task = blockIdx.x; task < ntile * nother; task += gridDim.x) {
         const int tile = task % ntile, oth = task / ntile;
@@ -665,6 +703,8 @@ __global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<dou
         int i = 0, j = 0;
         if (D == 0) j = j0 + oth; else i = i0 + oth;
         R a[M], c[M], dd[M];
+#pragma unroll
+        for (int m = 0; m < M; m++) { a[m] = R(0); c[m] = R(0); dd[m] = R(0); }
         const int64_t qf = ix(d, p, D == 0 ? m0 + r0 : i, D == 1 ? m0 + r0 : j, k);
         if (live) {
 #pragma unroll
@@ -681,22 +721,47 @@ __global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<dou
                 }
             }
             chunk_backward<R, M>(a, c, dd, mt);
-            R ga, gc, gdv;
-            chunk_last<R, M>(a, c, dd, mt, ga, gc, gdv);
-            if (mt == 1) { ga = R(0); }
-            rlo[(2 * t) * W + lane] = a[0];
-            rup[(2 * t) * W + lane] = c[0];
-            rrh[(2 * t) * W + lane] = dd[0];
-            rlo[(2 * t + 1) * W + lane] = mt == 1 ? R(0) : ga;
-            rup[(2 * t + 1) * W + lane] = mt == 1 ? R(0) : gc;
-            rrh[(2 * t + 1) * W + lane] = mt == 1 ? R(0) : gdv;
         }
+        // reduced rows: S_t in registers, S_{t+1} through LDS
+        R ga = R(0), gc = R(0), gdv = R(0);
+        if (live) chunk_last<R, M>(a, c, dd, mt, ga, gc, gdv);
+        sA[t * W + lane] = a[0];
+        sB[t * W + lane] = c[0];
+        sC[t * W + lane] = dd[0];
         __syncthreads();
-        if (t == 0 && live) reduced_solve<R>(rlo + lane, rup + lane, rrh + lane, 2 * P, W);
+        R al1 = R(0), be1 = R(0), de1 = R(0);
+        if (t + 1 < P) {
+            al1 = sA[(t + 1) * W + lane];
+            be1 = sB[(t + 1) * W + lane];
+            de1 = sC[(t + 1) * W + lane];
+        }
+        Row4<R> row = erow<R>(a[0], c[0], dd[0], ga, gc, gdv, al1, be1, de1);
+        if (!live) { row.a = R(0); row.b = R(1); row.c = R(0); row.d = R(0); }
+        for (int h = 1; h < P; h <<= 1) {
+            __syncthreads();
+            sA[t * W + lane] = row.a;
+            sB[t * W + lane] = row.b;
+            sC[t * W + lane] = row.c;
+            sD[t * W + lane] = row.d;
+            __syncthreads();
+            Row4<R> rm = {R(0), R(1), R(0), R(0)}, rp = {R(0), R(1), R(0), R(0)};
+            if (t - h >= 0) {
+                const int o = (t - h) * W + lane;
+                rm.a = sA[o]; rm.b = sB[o]; rm.c = sC[o]; rm.d = sD[o];
+            }
+            if (t + h < P) {
+                const int o = (t + h) * W + lane;
+                rp.a = sA[o]; rp.b = sB[o]; rp.c = sC[o]; rp.d = sD[o];
+            }
+            row = pcr_level<R>(row, rm, rp);
+        }
+        const R xe = row.d / row.b;
         __syncthreads();
+        sA[t * W + lane] = xe;
+        __syncthreads();
+        const R xem = t > 0 ? sA[(t - 1) * W + lane] : R(0);
+        const R xs = dd[0] - a[0] * xem - c[0] * xe;
         if (live) {
-            const R xs = rrh[(2 * t) * W + lane];
-            const R xe = mt == 1 ? xs : rrh[(2 * t + 1) * W + lane];
 #pragma unroll
             for (int m = 0; m < M; m++) {
                 if (m < mt) {
@@ -732,66 +797,102 @@ __global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<dou
     }
 }
 
-// Contiguous lines (D = 2, phi).  One wave per line, one chunk per lane;
-// 4 lines per 256-thread block.  A task = one (i, j) line.
+// Contiguous lines (D = 2, phi).  One wave per line (LPB lines per block).
+// Phase A, coalesced: lane e%64 assembles row e (coefficients from the
+// tables and the advecting velocity) and stores (lo, di, up, x) in LDS,
+// transposed to [row-in-chunk][chunk] (padded) so that phase B reads are
+// conflict-free.  Phase B: lane c eliminates chunk c (rows c*m .. c*m+m-1)
+// in registers, the reduced system is solved by PCR over wave shuffles, and
+// the chunk's solution goes back to LDS.  Phase C, coalesced: write y (or
+// psi += y and the increment norm).
 template <typename R, int L, int MODE, bool DIFF, int M>
 __global__ void __launch_bounds__(256) k_sweep_contig(Dims d, Geo<R> g, Geo<double> gd, State<R> s,
-                                                      const R *x, R *y, R *psi, double *partial, int P)
+                                                      const R *x, R *y, R *psi, double *partial,
+                                                      int P, int mc)
 {
-    __shared__ R rlo[4][128], rup[4][128], rrh[4][128];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    extern __shared__ unsigned char smem_raw[];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lpb = blockDim.x >> 6;
     const int p = blockIdx.y;
     const int i0 = ulo<L>(0), j0 = ulo<L>(1), k0 = ulo<L>(2);
     const int n = d.np - k0;
     const int ni = d.nr - i0, nj = d.nt - j0;
     const int64_t nlines = (int64_t)ni * nj;
+    const int ld = P + 1;                      // padded row length of the transposed arrays
+    const int per = 4 * mc * ld;               // elements per line
+    R *sl = reinterpret_cast<R *>(smem_raw) + (int64_t)w * per;
+    R *tlo = sl, *tdi = sl + mc * ld, *tup = sl + 2 * mc * ld, *tx = sl + 3 * mc * ld;
     const R nu = (L == CC && !DIFF) ? R(1) : g.pr;
-    const int r0 = (int)((int64_t)lane * n / P), r1 = (int)((int64_t)(lane + 1) * n / P);
-    const int mt = lane < P ? r1 - r0 : 0;
+    const int mt = lane < P ? (lane < P - 1 ? mc : n - (P - 1) * mc) : 0;
     double acc = 0.0;
-    for (int64_t base = (int64_t)blockIdx.x * 4; base < nlines; base += (int64_t)gridDim.x * 4) {
+    for (int64_t base = (int64_t)blockIdx.x * lpb; base < nlines; base += (int64_t)gridDim.x * lpb) {
         const int64_t line = base + w;
-        const bool live = line < nlines && mt > 0;
-        const int i = i0 + (int)(line / nj), j = j0 + (int)(line % nj);
-        R a[M], c[M], dd[M];
-        if (live) {
-            const int64_t q0 = ix(d, p, i, j, k0 + r0);
-#pragma unroll
-            for (int m = 0; m < M; m++) {
-                if (m < mt) {
-                    R lo, di, up;
-                    line_row<R, L, 2, DIFF>(d, g, s, q0 + m, i, j, r0 + m, n, nu, lo, di, up);
-                    chunk_forward<R, M>(a, c, dd, m, lo, di, up, x[q0 + m]);
-                } else {
-                    a[m] = R(0); c[m] = R(0); dd[m] = R(0);
-                }
+        const bool lv = line < nlines;
+        const int i = i0 + (int)(lv ? line / nj : 0), j = j0 + (int)(lv ? line % nj : 0);
+        const int64_t q0 = ix(d, p, i, j, k0);
+        if (lv) {
+            for (int e = lane; e < n; e += 64) {
+                R lo, di, up;
+                line_row<R, L, 2, DIFF>(d, g, s, q0 + e, i, j, e, n, nu, lo, di, up);
+                const int cc = e / mc, rr = e - cc * mc;
+                const int o = rr * ld + cc;
+                tlo[o] = lo;
+                tdi[o] = di;
+                tup[o] = up;
+                tx[o] = x[q0 + e];
             }
-            chunk_backward<R, M>(a, c, dd, mt);
-            R ga, gc, gdv;
-            chunk_last<R, M>(a, c, dd, mt, ga, gc, gdv);
-            rlo[w][2 * lane] = a[0];
-            rup[w][2 * lane] = c[0];
-            rrh[w][2 * lane] = dd[0];
-            rlo[w][2 * lane + 1] = ga;
-            rup[w][2 * lane + 1] = gc;
-            rrh[w][2 * lane + 1] = gdv;
         }
         __syncthreads();
-        if (lane == 0 && line < nlines) reduced_solve<R>(rlo[w], rup[w], rrh[w], 2 * P, 1);
-        __syncthreads();
-        if (live) {
-            const R xs = rrh[w][2 * lane], xe = rrh[w][2 * lane + 1];
-            const int64_t q0 = ix(d, p, i, j, k0 + r0);
+        R a[M], c[M], dd[M];
 #pragma unroll
-            for (int m = 0; m < M; m++) {
-                if (m < mt) {
-                    const R v = (m == 0) ? xs : (m == mt - 1 ? xe : dd[m] - a[m] * xs - c[m] * xe);
-                    if (MODE == 0) {
-                        y[q0 + m] = v;
-                    } else {
-                        psi[q0 + m] += v;
-                        acc += vol_at<L, 2>(gd, i, j) * (double)v * (double)v;
-                    }
+        for (int m = 0; m < M; m++) {
+            a[m] = R(0); c[m] = R(0); dd[m] = R(0);
+            if (lv && m < mt) {
+                const int o = m * ld + lane;
+                chunk_forward<R, M>(a, c, dd, m, tlo[o], tdi[o], tup[o], tx[o]);
+            }
+        }
+        if (lv && mt > 0) chunk_backward<R, M>(a, c, dd, mt);
+        R ga = R(0), gc = R(0), gdv = R(0);
+        if (mt > 0) chunk_last<R, M>(a, c, dd, mt, ga, gc, gdv);
+        const R al1 = shfl_r(a[0], (lane + 1) & 63), be1 = shfl_r(c[0], (lane + 1) & 63),
+                de1 = shfl_r(dd[0], (lane + 1) & 63);
+        Row4<R> row;
+        if (lane < P) row = erow<R>(a[0], c[0], dd[0], ga, gc, gdv, lane + 1 < P ? al1 : R(0),
+                                    lane + 1 < P ? be1 : R(0), lane + 1 < P ? de1 : R(0));
+        else { row.a = R(0); row.b = R(1); row.c = R(0); row.d = R(0); }
+        for (int h = 1; h < P; h <<= 1) {
+            Row4<R> rm, rp;
+            rm.a = shfl_r(row.a, (lane - h) & 63); rm.b = shfl_r(row.b, (lane - h) & 63);
+            rm.c = shfl_r(row.c, (lane - h) & 63); rm.d = shfl_r(row.d, (lane - h) & 63);
+            rp.a = shfl_r(row.a, (lane + h) & 63); rp.b = shfl_r(row.b, (lane + h) & 63);
+            rp.c = shfl_r(row.c, (lane + h) & 63); rp.d = shfl_r(row.d, (lane + h) & 63);
+            if (lane - h < 0) { rm.a = R(0); rm.b = R(1); rm.c = R(0); rm.d = R(0); }
+            if (lane + h >= P) { rp.a = R(0); rp.b = R(1); rp.c = R(0); rp.d = R(0); }
+            row = pcr_level<R>(row, rm, rp);
+        }
+        const R xe = row.d / row.b;
+        const R xem0 = shfl_r(xe, (lane - 1) & 63);
+        const R xem = lane > 0 ? xem0 : R(0);
+        const R xs = dd[0] - a[0] * xem - c[0] * xe;
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            if (lv && m < mt) {
+                const R v = (m == 0) ? xs : (m == mt - 1 ? xe : dd[m] - a[m] * xs - c[m] * xe);
+                tx[m * ld + lane] = v;
+            }
+        }
+        __syncthreads();
+        if (lv) {
+            const double vol = MODE == 1 ? vol_at<L, 2>(gd, i, j) : 0.0;
+            for (int e = lane; e < n; e += 64) {
+                const int cc = e / mc, rr = e - cc * mc;
+                const R v = tx[rr * ld + cc];
+                if (MODE == 0) {
+                    y[q0 + e] = v;
+                } else {
+                    psi[q0 + e] += v;
+                    acc += vol * (double)v * (double)v;
                 }
             }
         }
@@ -830,33 +931,40 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
         int64_t b = tasks;
         if (b > NBMAX) b = NBMAX;
         if (nblocks) *nblocks = (int)b;
-        const size_t lds = (size_t)6 * P * W * sizeof(R);
+        if (2 * P > n && n > 1) return false;
+        const size_t lds = (size_t)4 * P * W * sizeof(R);
         hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, M>), dim3((unsigned)b, 2), dim3(W, P),
                            lds, st, d, g, gd, s, x, y, psi, partial);
         return true;
     } else {
         const int n = d.np - k0;
-        int P = n / 2;
-        if (P > 64) P = 64;
-        if (P < 1) P = 1;
-        const int need = (n + P - 1) / P;
-        if (need > 32) return false;
+        // uniform chunks of mc rows (last chunk >= 2 rows), P <= 64 lanes
+        int mc = (n + 63) / 64;
+        if (mc < 2) mc = 2;
+        int P = (n + mc - 1) / mc;
+        while (P > 1 && n - (P - 1) * mc < 2) {
+            mc++;
+            P = (n + mc - 1) / mc;
+        }
+        if (mc > 32 || P > 64) return false;
+        const size_t per_line = (size_t)4 * mc * (P + 1) * sizeof(R);
+        int lpb = (int)(65536 / per_line);
+        if (lpb > 4) lpb = 4;
+        if (lpb < 1) return false;
         const int64_t nlines = (int64_t)(d.nr - i0) * (d.nt - j0);
-        int64_t b = (nlines + 3) / 4;
+        int64_t b = (nlines + lpb - 1) / lpb;
         if (b > NBMAX) b = NBMAX;
         if (nblocks) *nblocks = (int)b;
-        if (need <= 8)
-            hipLaunchKernelGGL((k_sweep_contig<R, L, MODE, DIFF, 8>), dim3((unsigned)b, 2), dim3(256), 0, st,
-                               d, g, gd, s, x, y, psi, partial, P);
-        else if (need <= 16)
-            hipLaunchKernelGGL((k_sweep_contig<R, L, MODE, DIFF, 16>), dim3((unsigned)b, 2), dim3(256), 0, st,
-                               d, g, gd, s, x, y, psi, partial, P);
-        else if (need <= 24)
-            hipLaunchKernelGGL((k_sweep_contig<R, L, MODE, DIFF, 24>), dim3((unsigned)b, 2), dim3(256), 0, st,
-                               d, g, gd, s, x, y, psi, partial, P);
+        const size_t lds = per_line * lpb;
+        const dim3 grid((unsigned)b, 2), block(64 * lpb);
+        if (mc <= 8)
+            hipLaunchKernelGGL((k_sweep_contig<R, L, MODE, DIFF, 8>), grid, block, lds, st, d, g, gd, s, x, y, psi, partial, P, mc);
+        else if (mc <= 16)
+            hipLaunchKernelGGL((k_sweep_contig<R, L, MODE, DIFF, 16>), grid, block, lds, st, d, g, gd, s, x, y, psi, partial, P, mc);
+        else if (mc <= 24)
+            hipLaunchKernelGGL((k_sweep_contig<R, L, MODE, DIFF, 24>), grid, block, lds, st, d, g, gd, s, x, y, psi, partial, P, mc);
         else
-            hipLaunchKernelGGL((k_sweep_contig<R, L, MODE, DIFF, 32>), dim3((unsigned)b, 2), dim3(256), 0, st,
-                               d, g, gd, s, x, y, psi, partial, P);
+            hipLaunchKernelGGL((k_sweep_contig<R, L, MODE, DIFF, 32>), grid, block, lds, st, d, g, gd, s, x, y, psi, partial, P, mc);
         return true;
     }
 }
