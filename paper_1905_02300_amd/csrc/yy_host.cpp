@@ -242,6 +242,9 @@ template <typename R> void host_tables(const Frame &F, const Dims &d, std::vecto
         tr[9].push_back(fm * fm * safe_inv(cm * cm * dr2));
         tr[10].push_back(fp * fp * safe_inv(c0 * c0 * dr2));
         tr[11].push_back(-f0 * f0 * (safe_inv(c0 * c0) + safe_inv(cm * cm)) / dr2);
+        // Div_r at centre i = e
+        tr[12].push_back(fp * fp * safe_inv(c0 * c0 * F.dr));
+        tr[13].push_back(f0 * f0 * safe_inv(c0 * c0 * F.dr));
     }
     for (int e = -1; e <= d.nt + 1; e++) {
         const double s0 = sc(e), sF = sf(e), sFm = sf(e - 1), sFp = sf(e + 1), sCm = sc(e - 1);
@@ -264,6 +267,12 @@ template <typename R> void host_tables(const Frame &F, const Dims &d, std::vecto
         tt[12].push_back(safe_inv(s0 * s0));
         tt[13].push_back(safe_inv(sF * sF));
         tt[14].push_back(cc(e) * safe_inv(s0));
+        // Div_th at centre j = e (times 1/r), Div_ph factor, cot at faces, 1/sin
+        tt[15].push_back(sFp * safe_inv(s0 * F.dth));
+        tt[16].push_back(sF * safe_inv(s0 * F.dth));
+        tt[17].push_back(safe_inv(s0 * F.dph));
+        tt[18].push_back(cf(e) * safe_inv(sF));
+        tt[19].push_back(safe_inv(s0));
     }
     for (auto &t : tr)
         for (double x : t) v.push_back((R)x);
@@ -282,16 +291,21 @@ template <typename R> void bind_geo(Geo<R> &g, const R *base, const Dims &d, con
     const R *tr = g.cf + (d.nt + 3);
     const int64_t lr = d.nr + 3, lt = d.nt + 3;
     const R **rt[NTAB_R] = {&g.ir_c, &g.ir_f, &g.ir2_c, &g.ir2_f, &g.rc_lo, &g.rc_up,
-                            &g.rf_lo, &g.rf_up, &g.rf_di, &g.gf_lo, &g.gf_up, &g.gf_di};
+                            &g.rf_lo, &g.rf_up, &g.rf_di, &g.gf_lo, &g.gf_up, &g.gf_di,
+                            &g.dr_p, &g.dr_m};
     for (int q = 0; q < NTAB_R; q++) *rt[q] = tr + q * lr;
     const R *tt = tr + NTAB_R * lr;
     const R **tp[NTAB_T] = {&g.tc_lo, &g.tc_up, &g.tf_lo, &g.tf_up, &g.ef_lo, &g.ef_up, &g.ef_di,
                             &g.gt_lo, &g.gt_up, &g.gt_di, &g.h2p_c, &g.h2p_f, &g.is2_c, &g.is2_f,
-                            &g.cot_c};
+                            &g.cot_c, &g.dt_p, &g.dt_m, &g.dp_c, &g.cot_f, &g.is_c};
     for (int q = 0; q < NTAB_T; q++) *tp[q] = tt + q * lt;
     g.h2r = (R)(1.0 / (2.0 * F.dr));
     g.h2t = (R)(1.0 / (2.0 * F.dth));
     g.idph2 = (R)(1.0 / (F.dph * F.dph));
+    g.idr = (R)(1.0 / F.dr);
+    g.idth = (R)(1.0 / F.dth);
+    g.idph = (R)(1.0 / F.dph);
+    g.r12 = (R)(F.r1 * F.r1);
     g.dr = (R)F.dr;
     g.dth = (R)F.dth;
     g.dph = (R)F.dph;

@@ -47,13 +47,17 @@ template <typename R> struct Geo {
     const R *h2p_c, *h2p_f;                 // 1/(2 sin(theta) dphi), centres / faces
     const R *is2_c, *is2_f;                 // 1/sin^2(theta), centres / faces
     const R *cot_c;                         // cot(theta) at centres
+    const R *dr_p, *dr_m;                   // Div_r at r-centre i: rf(i+1)^2, rf(i)^2 over rc^2 dr
+    const R *dt_p, *dt_m, *dp_c;            // Div_th at theta-centre j (x 1/r); 1/(sin dphi)
+    const R *cot_f, *is_c;                  // cot(theta) at faces, 1/sin(theta) at centres
     R h2r, h2t, idph2;                      // 1/(2 dr), 1/(2 dtheta), 1/dphi^2
+    R idr, idth, idph, r12;                 // 1/dr, 1/dtheta, 1/dphi, R1^2
     // parameter-dependent combinations (rebuilt when Pr or chi change):
     // Pr * rf_* + ic * gf_* (u_r radial operator) and Pr * ef_* + ic * gt_*
     const R *fr_lo, *fr_up, *fr_di, *ft_lo, *ft_up, *ft_di;
 };
-constexpr int NTAB_R = 12;   // per-r coefficient tables (length nr+3)
-constexpr int NTAB_T = 15;   // per-theta coefficient tables (length nt+3)
+constexpr int NTAB_R = 14;   // per-r coefficient tables (length nr+3)
+constexpr int NTAB_T = 20;   // per-theta coefficient tables (length nt+3)
 
 // one interpolation target of a scalar (centre-type in theta and phi)
 struct FillScalar {

@@ -337,23 +337,21 @@ template <typename R> struct RhsIn {
 };
 
 // Div_r, Div_theta, Div_phi of one stored velocity component at the centre
-// with storage index q (centre (i, j, k))
-template <typename R, typename A>
-__device__ __forceinline__ A div_r(const Geo<R> &g, const R *a, int64_t q, int64_t sI, int i)
+// with storage index q (centre (i, j, k)), from the metric tables
+template <typename R>
+__device__ __forceinline__ R div_r(const Geo<R> &g, const R *a, int64_t q, int64_t sI, int i)
 {
-    const A fp = g.rf[i + 2], fm = g.rf[i + 1], rc = g.rc[i + 1];
-    return (fp * fp * (A)a[q + sI] - fm * fm * (A)a[q]) / (rc * rc * (A)g.dr);
+    return g.dr_p[i + 1] * a[q + sI] - g.dr_m[i + 1] * a[q];
 }
-template <typename R, typename A>
-__device__ __forceinline__ A div_t(const Geo<R> &g, const R *a, int64_t q, int64_t sJ, int i, int j)
+template <typename R>
+__device__ __forceinline__ R div_t(const Geo<R> &g, const R *a, int64_t q, int64_t sJ, int i, int j)
 {
-    return ((A)g.sf[j + 2] * (A)a[q + sJ] - (A)g.sf[j + 1] * (A)a[q]) /
-           ((A)g.rc[i + 1] * (A)g.sc[j + 1] * (A)g.dth);
+    return g.ir_c[i + 1] * (g.dt_p[j + 1] * a[q + sJ] - g.dt_m[j + 1] * a[q]);
 }
-template <typename R, typename A>
-__device__ __forceinline__ A div_p(const Geo<R> &g, const R *a, int64_t q, int i, int j)
+template <typename R>
+__device__ __forceinline__ R div_p(const Geo<R> &g, const R *a, int64_t q, int i, int j)
 {
-    return ((A)a[q + 1] - (A)a[q]) / ((A)g.rc[i + 1] * (A)g.sc[j + 1] * (A)g.dph);
+    return g.ir_c[i + 1] * g.dp_c[j + 1] * (a[q + 1] - a[q]);
 }
 
 template <typename R>
@@ -363,94 +361,154 @@ __device__ __forceinline__ double ptilde(const RhsIn<R> &in, int64_t q)
     return in.psn[q] + 0.5 * (in.p1k[q] - in.p1n[q]);
 }
 
-template <typename R, int L>
-__device__ R source(const Dims &d, const Geo<R> &g, const RhsIn<R> &in, int64_t q, int i, int j,
-                    R ar, R at, R ap)
-{
-    const int64_t sI = d.sI, sJ = d.sJ;
-    R S = in.f ? in.f[q] : R(0);
-    if (L == CC) return S;
-    if (L == FR) {
-        // grad-div with the extrapolated upper blocks: (D12 u_t* + D13 u_p*)/(2 chi)
-        const R d12 = (div_t<R, R>(g, in.us[1], q, sJ, i, j) - div_t<R, R>(g, in.us[1], q - sI, sJ, i - 1, j)) / g.dr;
-        const R d13 = (div_p<R, R>(g, in.us[2], q, i, j) - div_p<R, R>(g, in.us[2], q - sI, i - 1, j)) / g.dr;
-        S += g.ic * (d12 + d13);
-        const R r0 = g.rf[i + 1];
-        S += (at * vel<1, FR>(in.us[1], q, d) + ap * vel<2, FR>(in.us[2], q, d)) / r0;
-        S -= (R)((ptilde(in, q) - ptilde(in, q - sI)) / (double)g.dr);
-        S += g.prra * R(0.25) * ((in.Tn[q - sI] + in.Tk[q - sI]) + (in.Tn[q] + in.Tk[q]));
-    } else if (L == FT) {
-        const R r0 = g.rc[i + 1], s0 = g.sf[j + 1], c0 = g.cf[j + 1];
-        // (D21 u_r^{n+1/2} + D23 u_p*)/(2 chi)
-        const R dj0 = R(0.5) * (div_r<R, R>(g, in.un[0], q, sI, i) + div_r<R, R>(g, in.uk[0], q, sI, i));
-        const R dj1 = R(0.5) * (div_r<R, R>(g, in.un[0], q - sJ, sI, i) + div_r<R, R>(g, in.uk[0], q - sJ, sI, i));
-        const R d21 = (dj0 - dj1) / (r0 * g.dth);
-        const R d23 = (div_p<R, R>(g, in.us[2], q, i, j) - div_p<R, R>(g, in.us[2], q - sJ, i, j - 1)) / (r0 * g.dth);
-        S += g.ic * (d21 + d23);
-        // Pr[(2/r^2) d_th u_r + (2 cos/(r^3 sin)) d_r(r^2 u_r)] at n+1/2
-        auto ub = [&](int64_t qq) { return R(0.5) * (in.un[0][qq] + in.uk[0][qq]); };
-        const R dth_ur = R(0.5) * ((ub(q) - ub(q - sJ)) + (ub(q + sI) - ub(q + sI - sJ))) / g.dth;
-        const R fp2 = g.rf[i + 2] * g.rf[i + 2], fm2 = g.rf[i + 1] * g.rf[i + 1];
-        const R dr_r2ur = R(0.5) * ((fp2 * ub(q - sJ + sI) - fm2 * ub(q - sJ)) +
-                                    (fp2 * ub(q + sI) - fm2 * ub(q))) / g.dr;
-        S += g.pr * (R(2) / (r0 * r0) * dth_ur + R(2) * c0 / (r0 * r0 * r0 * s0) * dr_r2ur);
-        S += ap * vel<2, FT>(in.us[2], q, d) * c0 / (s0 * r0);
-        S -= (R)((ptilde(in, q) - ptilde(in, q - sJ)) / ((double)r0 * (double)g.dth));
-    } else {
-        const R r0 = g.rc[i + 1], s0 = g.sc[j + 1], c0 = g.cc[j + 1];
-        const R gg = r0 * s0 * g.dph;
-        // (D31 u_r^{n+1/2} + D32 u_t^{n+1/2})/(2 chi)
-        const R a0 = R(0.5) * (div_r<R, R>(g, in.un[0], q, sI, i) + div_r<R, R>(g, in.uk[0], q, sI, i));
-        const R a1 = R(0.5) * (div_r<R, R>(g, in.un[0], q - 1, sI, i) + div_r<R, R>(g, in.uk[0], q - 1, sI, i));
-        const R b0 = R(0.5) * (div_t<R, R>(g, in.un[1], q, sJ, i, j) + div_t<R, R>(g, in.uk[1], q, sJ, i, j));
-        const R b1 = R(0.5) * (div_t<R, R>(g, in.un[1], q - 1, sJ, i, j) + div_t<R, R>(g, in.uk[1], q - 1, sJ, i, j));
-        S += g.ic * ((a0 - a1) / gg + (b0 - b1) / gg);
-        auto ubr = [&](int64_t qq) { return R(0.5) * (in.un[0][qq] + in.uk[0][qq]); };
-        auto ubt = [&](int64_t qq) { return R(0.5) * (in.un[1][qq] + in.uk[1][qq]); };
-        const R dph_ur = R(0.5) * ((ubr(q) - ubr(q - 1)) + (ubr(q + sI) - ubr(q + sI - 1))) / g.dph;
-        const R dph_ut = R(0.5) * ((ubt(q) - ubt(q - 1)) + (ubt(q + sJ) - ubt(q + sJ - 1))) / g.dph;
-        S += g.pr * (R(2) / (r0 * r0 * s0) * dph_ur + R(2) * c0 / (r0 * r0 * s0 * s0) * dph_ut);
-        S -= (R)((ptilde(in, q) - ptilde(in, q - 1)) / ((double)r0 * (double)s0 * (double)g.dph));
-    }
-    return S;
-}
+// Residual, column-marching form: a thread owns one (patch, j, k) column
+// and walks i upwards, keeping every value it needs at i-1 / i / i+1 of the
+// same (j, k) offset in registers (sliding windows), so each r-neighbour is
+// fetched once.  The arithmetic is the point form above, term by term.
+template <typename R> struct Col {
+    // psibar = (psi^n + psi^{k-1})/2 at i-1, i, i+1
+    R bm, b0, bp;
+    // averaged-velocity windows: value at offset (dj,dk) and radial i+e
+    R a0, a1, c0, c1, e0, e1, f0, f1, g0, g1, h0, h1;
+    double p0, pm;   // p~ at i and i-1 (FR)
+};
 
 template <typename R, int L>
-__global__ void __launch_bounds__(256) k_residual(Dims d, Geo<R> g, State<R> s, RhsIn<R> in, R *out)
+__global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R> s, RhsIn<R> in, R *out)
 {
     const int p = blockIdx.y;
-    const int i0 = ulo<L>(0), j0 = ulo<L>(1), k0 = ulo<L>(2);
-    const int ni = d.nr - i0, nj = d.nt - j0, nk = d.np - k0;
+    const int j0 = ulo<L>(1), k0 = ulo<L>(2), i0 = ulo<L>(0);
+    const int nj = d.nt - j0, nk = d.np - k0;
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= (int64_t)ni * nj * nk) return;
-    const int k = k0 + (int)(t % nk);
-    const int j = j0 + (int)((t / nk) % nj);
-    const int i = i0 + (int)(t / ((int64_t)nk * nj));
-    const int64_t q = ix(d, p, i, j, k);
+    if (t >= (int64_t)nj * nk) return;
+    const int k = k0 + (int)(t % nk), j = j0 + (int)(t / nk);
     const int64_t sI = d.sI, sJ = d.sJ;
     const R nu = L == CC ? R(1) : g.pr;
-    R ar, at, ap;
-    adv<L>(s, d, q, ar, at, ap);
-    auto bar = [&](int64_t qq) { return R(0.5) * (in.pn[qq] + in.pk[qq]); };
-    const Tri<R> c0 = coef<L, 0>(g, i, j, ar, at, ap, nu);
-    const Tri<R> c1 = coef<L, 1>(g, i, j, ar, at, ap, nu);
-    const Tri<R> c2 = coef<L, 2>(g, i, j, ar, at, ap, nu);
-    const R b0 = bar(q);
-    R Rv = c0.lo * bar(q - sI) + c0.di * b0 + c0.up * bar(q + sI);
-    Rv += c1.lo * bar(q - sJ) + c1.di * b0 + c1.up * bar(q + sJ);
-    Rv += c2.lo * bar(q - 1) + c2.di * b0 + c2.up * bar(q + 1);
-    // (F - Lhat) psi* = nu [(D_thth - Dhat_thth) + (D_phph - Dhat_phph)] psi*
-    const R r0 = r_of<L>(g, i), s0 = s_of<L>(g, j);
-    const R sm = L == FT ? g.sc[j] : g.sf[j + 1];
-    const R sp = L == FT ? g.sc[j + 1] : g.sf[j + 2];
-    const R x0 = in.ps[q];
-    const R lt = (sp * (in.ps[q + sJ] - x0) - sm * (x0 - in.ps[q - sJ])) / (s0 * g.dth * g.dth);
-    const R lp = in.ps[q + 1] - R(2) * x0 + in.ps[q - 1];
-    Rv += nu * ((R(1) / (r0 * r0) - R(1) / (g.r1 * g.r1)) * lt +
-                (R(1) / (r0 * r0 * s0 * s0 * g.dph * g.dph) - g.cphat) * lp);
-    Rv += source<R, L>(d, g, in, q, i, j, ar, at, ap);
-    Rv -= (in.pk[q] - in.pn[q]) * g.inv_tau;
-    out[q] = g.tau * Rv;
+    const R *pn = in.pn, *pk = in.pk, *ps = in.ps;
+    const R *wr = s.us[1][0], *wt = s.us[1][1], *wp = s.us[1][2];
+    auto bar = [&](int64_t qq) { return R(0.5) * (pn[qq] + pk[qq]); };
+    auto ub0 = [&](int64_t qq) { return R(0.5) * (in.un[0][qq] + in.uk[0][qq]); };
+    int64_t q = ix(d, p, i0, j, k);
+    Col<R> w;
+    w.bm = bar(q - sI);
+    w.b0 = bar(q);
+    // windows whose lower radial point is i-1 (FR) are primed with i-1
+    if (L == FR) {
+        w.a0 = wt[q - sI]; w.a1 = wt[q - sI + sJ];       // w_t at (i-1, j), (i-1, j+1)
+        w.c0 = wp[q - sI]; w.c1 = wp[q - sI + 1];        // w_p at (i-1, k), (i-1, k+1)
+        w.e0 = in.us[1][q - sI]; w.e1 = in.us[1][q - sI + sJ];
+        w.f0 = in.us[2][q - sI]; w.f1 = in.us[2][q - sI + 1];
+        w.g0 = in.Tn[q - sI] + in.Tk[q - sI];
+        w.pm = ptilde(in, q - sI);
+    } else if (L == CC) {
+        w.a0 = wr[q];                                    // w_r at face i
+    } else if (L == FT) {
+        w.a0 = wr[q - sJ]; w.a1 = wr[q];                 // w_r at face i, (j-1) and j
+        w.c0 = in.un[0][q - sJ] + in.uk[0][q - sJ];      // 2 ubar_r at face i, j-1
+        w.c1 = in.un[0][q] + in.uk[0][q];                // 2 ubar_r at face i, j
+    } else {
+        w.a0 = wr[q - 1]; w.a1 = wr[q];                  // w_r at face i, (k-1) and k
+        w.c0 = in.un[0][q - 1] + in.uk[0][q - 1];
+        w.c1 = in.un[0][q] + in.uk[0][q];
+    }
+    for (int i = i0; i < d.nr; i++, q += sI) {
+        w.bp = bar(q + sI);
+        R ar, at, ap, S = in.f ? in.f[q] : R(0);
+        if (L == CC) {
+            const R wr1 = wr[q + sI];
+            ar = R(0.5) * (w.a0 + wr1);
+            at = R(0.5) * (wt[q] + wt[q + sJ]);
+            ap = R(0.5) * (wp[q] + wp[q + 1]);
+            w.a0 = wr1;
+        } else if (L == FR) {
+            const R t0 = wt[q], t1 = wt[q + sJ], p0 = wp[q], p1 = wp[q + 1];
+            ar = wr[q];
+            at = R(0.25) * ((w.a0 + w.a1) + (t0 + t1));
+            ap = R(0.25) * ((w.c0 + w.c1) + (p0 + p1));
+            const R e0 = in.us[1][q], e1 = in.us[1][q + sJ], f0 = in.us[2][q], f1 = in.us[2][q + 1];
+            // (D12 u_t* + D13 u_p*)/(2 chi)
+            const R dtc = g.ir_c[i + 1] * (g.dt_p[j + 1] * e1 - g.dt_m[j + 1] * e0);
+            const R dtm = g.ir_c[i] * (g.dt_p[j + 1] * w.e1 - g.dt_m[j + 1] * w.e0);
+            const R dpc = g.ir_c[i + 1] * g.dp_c[j + 1] * (f1 - f0);
+            const R dpm = g.ir_c[i] * g.dp_c[j + 1] * (w.f1 - w.f0);
+            S += g.ic * g.idr * ((dtc - dtm) + (dpc - dpm));
+            const R vt = R(0.25) * ((w.e0 + w.e1) + (e0 + e1));
+            const R vp = R(0.25) * ((w.f0 + w.f1) + (f0 + f1));
+            S += (at * vt + ap * vp) * g.ir_f[i + 1];
+            const double pt = ptilde(in, q);
+            S -= (R)((pt - w.pm) * (double)g.idr);
+            const R tg = in.Tn[q] + in.Tk[q];
+            S += g.prra * R(0.25) * (w.g0 + tg);
+            w.a0 = t0; w.a1 = t1; w.c0 = p0; w.c1 = p1;
+            w.e0 = e0; w.e1 = e1; w.f0 = f0; w.f1 = f1;
+            w.g0 = tg; w.pm = pt;
+        } else if (L == FT) {
+            const R r0 = wr[q - sJ + sI], r1 = wr[q + sI];
+            ar = R(0.25) * ((w.a0 + r0) + (w.a1 + r1));
+            at = wt[q];
+            ap = R(0.25) * ((wp[q - sJ] + wp[q - sJ + 1]) + (wp[q] + wp[q + 1]));
+            const R ir = g.ir_c[i + 1], ir2 = g.ir2_c[i + 1], cot = g.cot_f[j + 1];
+            const R u0 = in.un[0][q - sJ + sI] + in.uk[0][q - sJ + sI];    // 2 ubar_r at (i+1, j-1)
+            const R u1 = in.un[0][q + sI] + in.uk[0][q + sI];              // 2 ubar_r at (i+1, j)
+            // Div_r of ubar at centres (i, j) and (i, j-1), times 2
+            const R dj0 = g.dr_p[i + 1] * u1 - g.dr_m[i + 1] * w.c1;
+            const R dj1 = g.dr_p[i + 1] * u0 - g.dr_m[i + 1] * w.c0;
+            const R *u2s = in.us[2];
+            const R d23 = g.ir_c[i + 1] * (g.dp_c[j + 1] * (u2s[q + 1] - u2s[q]) -
+                                           g.dp_c[j] * (u2s[q - sJ + 1] - u2s[q - sJ]));
+            S += g.ic * ir * g.idth * (R(0.5) * (dj0 - dj1) + d23);
+            const R dth_ur = R(0.5) * ((R(0.5) * w.c1 - R(0.5) * w.c0) + (R(0.5) * u1 - R(0.5) * u0)) * g.idth;
+            const R fp2 = g.rf[i + 2] * g.rf[i + 2], fm2 = g.rf[i + 1] * g.rf[i + 1];
+            const R dr_r2ur = R(0.5) * ((fp2 * R(0.5) * u0 - fm2 * R(0.5) * w.c0) +
+                                        (fp2 * R(0.5) * u1 - fm2 * R(0.5) * w.c1)) * g.idr;
+            S += g.pr * R(2) * ir2 * (dth_ur + cot * ir * dr_r2ur);
+            const R vp = R(0.25) * ((u2s[q - sJ] + u2s[q - sJ + 1]) + (u2s[q] + u2s[q + 1]));
+            S += ap * vp * cot * ir;
+            S -= (R)((ptilde(in, q) - ptilde(in, q - sJ)) * (double)ir * (double)g.idth);
+            w.a0 = r0; w.a1 = r1; w.c0 = u0; w.c1 = u1;
+        } else {
+            const R r0 = wr[q - 1 + sI], r1 = wr[q + sI];
+            ar = R(0.25) * ((w.a0 + r0) + (w.a1 + r1));
+            at = R(0.25) * ((wt[q - 1] + wt[q - 1 + sJ]) + (wt[q] + wt[q + sJ]));
+            ap = wp[q];
+            const R ir = g.ir_c[i + 1], ir2 = g.ir2_c[i + 1], isn = g.is_c[j + 1], cot = g.cot_c[j + 1];
+            const R igg = ir * g.dp_c[j + 1];
+            const R u0 = in.un[0][q - 1 + sI] + in.uk[0][q - 1 + sI];      // 2 ubar_r at (i+1, k-1)
+            const R u1 = in.un[0][q + sI] + in.uk[0][q + sI];              // 2 ubar_r at (i+1, k)
+            const R a0 = g.dr_p[i + 1] * u1 - g.dr_m[i + 1] * w.c1;
+            const R a1 = g.dr_p[i + 1] * u0 - g.dr_m[i + 1] * w.c0;
+            const R *tn = in.un[1], *tk = in.uk[1];
+            const R th00 = tn[q] + tk[q], th01 = tn[q + sJ] + tk[q + sJ];
+            const R thm0 = tn[q - 1] + tk[q - 1], thm1 = tn[q - 1 + sJ] + tk[q - 1 + sJ];
+            const R b0 = ir * (g.dt_p[j + 1] * th01 - g.dt_m[j + 1] * th00);
+            const R b1 = ir * (g.dt_p[j + 1] * thm1 - g.dt_m[j + 1] * thm0);
+            S += g.ic * igg * R(0.5) * ((a0 - a1) + (b0 - b1));
+            const R dph_ur = R(0.5) * ((R(0.5) * w.c1 - R(0.5) * w.c0) + (R(0.5) * u1 - R(0.5) * u0)) * g.idph;
+            const R dph_ut = R(0.5) * ((R(0.5) * th00 - R(0.5) * thm0) + (R(0.5) * th01 - R(0.5) * thm1)) * g.idph;
+            S += g.pr * R(2) * ir2 * isn * (dph_ur + cot * dph_ut);
+            S -= (R)((ptilde(in, q) - ptilde(in, q - 1)) * (double)igg);
+            w.a0 = r0; w.a1 = r1; w.c0 = u0; w.c1 = u1;
+        }
+        const Tri<R> c0 = coef<L, 0>(g, i, j, ar, at, ap, nu);
+        const Tri<R> c1 = coef<L, 1>(g, i, j, ar, at, ap, nu);
+        const Tri<R> c2 = coef<L, 2>(g, i, j, ar, at, ap, nu);
+        R Rv = c0.lo * w.bm + c0.di * w.b0 + c0.up * w.bp;
+        Rv += c1.lo * bar(q - sJ) + c1.di * w.b0 + c1.up * bar(q + sJ);
+        Rv += c2.lo * bar(q - 1) + c2.di * w.b0 + c2.up * bar(q + 1);
+        const R ir2 = L == FR ? g.ir2_f[i + 1] : g.ir2_c[i + 1];
+        const R hlo = L == FT ? g.tf_lo[j + 1] : g.tc_lo[j + 1];
+        const R hup = L == FT ? g.tf_up[j + 1] : g.tc_up[j + 1];
+        const R is2 = L == FT ? g.is2_f[j + 1] : g.is2_c[j + 1];
+        const R x0 = ps[q];
+        const R lt = hup * (ps[q + sJ] - x0) - hlo * (x0 - ps[q - sJ]);
+        const R lp = ps[q + 1] - R(2) * x0 + ps[q - 1];
+        Rv += nu * ((g.r12 * ir2 - R(1)) * lt + (ir2 * is2 * g.idph2 - g.cphat) * lp);
+        Rv += S;
+        Rv -= (pk[q] - pn[q]) * g.inv_tau;
+        out[q] = g.tau * Rv;
+        w.bm = w.b0;
+        w.b0 = w.bp;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1061,13 +1119,13 @@ void Ops<R>::residual(const Dims &d, const Geo<R> &g, const State<R> &s, int fie
     in.p1n = s.p[0][0];
     in.p1k = s.p[0][1];
     in.sys = sys;
-    const int i0 = L == FR, j0 = L == FT, k0 = L == FP;
-    const int64_t n = (int64_t)(d.nr - i0) * (d.nt - j0) * (d.np - k0);
+    const int j0 = L == FT, k0 = L == FP;
+    const int64_t n = (int64_t)(d.nt - j0) * (d.np - k0);
     dim3 gr((unsigned)((n + 255) / 256), 2);
-    if (L == CC) hipLaunchKernelGGL((k_residual<R, CC>), gr, dim3(256), 0, st, d, g, s, in, out);
-    else if (L == FR) hipLaunchKernelGGL((k_residual<R, FR>), gr, dim3(256), 0, st, d, g, s, in, out);
-    else if (L == FT) hipLaunchKernelGGL((k_residual<R, FT>), gr, dim3(256), 0, st, d, g, s, in, out);
-    else hipLaunchKernelGGL((k_residual<R, FP>), gr, dim3(256), 0, st, d, g, s, in, out);
+    if (L == CC) hipLaunchKernelGGL((k_residual_col<R, CC>), gr, dim3(256), 0, st, d, g, s, in, out);
+    else if (L == FR) hipLaunchKernelGGL((k_residual_col<R, FR>), gr, dim3(256), 0, st, d, g, s, in, out);
+    else if (L == FT) hipLaunchKernelGGL((k_residual_col<R, FT>), gr, dim3(256), 0, st, d, g, s, in, out);
+    else hipLaunchKernelGGL((k_residual_col<R, FP>), gr, dim3(256), 0, st, d, g, s, in, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1080,12 +1138,10 @@ template <typename R>
 __device__ __forceinline__ double div_h(const Geo<double> &gd, const R *ur, const R *ut, const R *up,
                                         int64_t q, const Dims &d, int i, int j)
 {
-    const double fp = gd.rf[i + 2], fm = gd.rf[i + 1], rc = gd.rc[i + 1];
-    const double sc = gd.sc[j + 1];
-    const double a = (fp * fp * (double)ur[q + d.sI] - fm * fm * (double)ur[q]) / (rc * rc * gd.dr);
-    const double b = (gd.sf[j + 2] * (double)ut[q + d.sJ] - gd.sf[j + 1] * (double)ut[q]) / (rc * sc * gd.dth);
-    const double c = ((double)up[q + 1] - (double)up[q]) / (rc * sc * gd.dph);
-    return a + b + c;
+    const double a = gd.dr_p[i + 1] * (double)ur[q + d.sI] - gd.dr_m[i + 1] * (double)ur[q];
+    const double b = gd.dt_p[j + 1] * (double)ut[q + d.sJ] - gd.dt_m[j + 1] * (double)ut[q];
+    const double c = gd.dp_c[j + 1] * ((double)up[q + 1] - (double)up[q]);
+    return a + gd.ir_c[i + 1] * (b + c);
 }
 
 template <typename R>
