@@ -75,10 +75,15 @@ def main():
     ap.add_argument("--schwarz", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-grid", default="40,120,360")
+    ap.add_argument("--mixed-error", type=int, default=0,
+                    help="run FP64 and FP32-mixed side by side for N steps and report their difference")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.mixed_error:
+        mixed_error(args)
+        return
 
     import torch
     from paper_1905_02300_amd import inputs as I
@@ -156,6 +161,45 @@ def main():
                                    "dT": float(norms[-1, :, 0].max())},
     }
     print(json.dumps(out), flush=True)
+
+
+def mixed_error(args):
+    """FP32-mixed (FP32 stencils and sweeps; FP64 pressure, divergence and
+    norms) against FP64 on the same grid and initial state after N steps:
+    relative L2 (volume-free, over MAC points) and Linf errors of u, p, T."""
+    import torch
+    from paper_1905_02300_amd import inputs as I
+    from paper_1905_02300_amd import yy
+    nr, nt, np_ = (int(x) for x in args.grid.split(","))
+    pr, ra, dt, K = 1.0, 1e5, 2e-4, args.schwarz
+    grid = I.Grid(nr, nt, np_)
+    st = I.convection_state(grid, pr, ra, seed=3)
+    shells, ms = {}, {}
+    for name, prec in (("fp64", yy.YY_FP64), ("fp32", yy.YY_FP32_MIXED)):
+        sh = yy.Shell(nr, nt, np_, prec=prec)
+        sh.set_params(pr=pr, ra=ra, dt=dt, chi=1.0, t_inner=1.0, t_outer=0.0)
+        for f in range(9):
+            sh.set_field(f, 0, st[f])
+            if f not in (I.P1, I.P2):
+                sh.set_field(f, 1, st[f])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.mixed_error):
+            sh.step(K)
+        torch.cuda.synchronize()
+        ms[name] = (time.perf_counter() - t0) / args.mixed_error * 1e3
+        shells[name] = sh
+    errs = {}
+    for f, nm in ((I.U2R, "u_r"), (I.U2T, "u_theta"), (I.U2P, "u_phi"), (I.P2, "p"), (I.T, "T")):
+        a = shells["fp32"].get_field(f)
+        b = shells["fp64"].get_field(f)
+        d = a - b
+        errs[nm] = {"l2_rel": float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(b)),
+                    "linf_rel": float(d.abs().max() / b.abs().max())}
+    print(json.dumps({"workload": f"fp32_mixed_vs_fp64_2x{nr}x{nt}x{np_}_K{K}", "steps": args.mixed_error,
+                      "errors": errs, "fp64_ms_per_step": ms["fp64"], "fp32_mixed_ms_per_step": ms["fp32"],
+                      "fp32_mixed_speedup": ms["fp64"] / ms["fp32"],
+                      "cells": grid.cells}), flush=True)
 
 
 def cpu_baseline(grid_s, pr, ra, dt, K):

@@ -346,6 +346,7 @@ template <typename R> void set_coefs(Geo<R> &g, const yy_params &p)
     g.ic = (R)(1.0 / (2.0 * p.chi));
     g.prra = (R)(p.pr * p.ra);
     g.inv_chi = 1.0 / p.chi;
+    g.prra_d = p.pr * p.ra;
 }
 
 }  // namespace

@@ -32,7 +32,7 @@ template <typename R> struct Geo {
     R cphat;        // 1 / (R1^2 sin^2(theta_1) dphi^2), theta_1 = pi/4 - d
     R ht, tau, inv_tau;
     R pr, ic, prra; // Pr, 1/(2 chi), Pr*Ra
-    double inv_chi;
+    double inv_chi, prra_d;
     // Coefficient tables of the split operators (unit viscosity, built in
     // FP64 on the host), index i+1 / f+1 / j+1 as above; they replace the
     // per-point divisions of the metric factors.

@@ -371,6 +371,7 @@ template <typename R> struct Col {
     // averaged-velocity windows: value at offset (dj,dk) and radial i+e
     R a0, a1, c0, c1, e0, e1, f0, f1, g0, g1, h0, h1;
     double p0, pm;   // p~ at i and i-1 (FR)
+    double tg;       // T^n + T^k at i-1 (FR), in FP64
 };
 
 template <typename R, int L>
@@ -398,7 +399,7 @@ __global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R>
         w.c0 = wp[q - sI]; w.c1 = wp[q - sI + 1];        // w_p at (i-1, k), (i-1, k+1)
         w.e0 = in.us[1][q - sI]; w.e1 = in.us[1][q - sI + sJ];
         w.f0 = in.us[2][q - sI]; w.f1 = in.us[2][q - sI + 1];
-        w.g0 = in.Tn[q - sI] + in.Tk[q - sI];
+        w.tg = (double)in.Tn[q - sI] + (double)in.Tk[q - sI];
         w.pm = ptilde(in, q - sI);
     } else if (L == CC) {
         w.a0 = wr[q];                                    // w_r at face i
@@ -435,13 +436,14 @@ __global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R>
             const R vt = R(0.25) * ((w.e0 + w.e1) + (e0 + e1));
             const R vp = R(0.25) * ((w.f0 + w.f1) + (f0 + f1));
             S += (at * vt + ap * vp) * g.ir_f[i + 1];
+            // -d_r p~ + Pr Ra T^{n+1/2}: the hydrostatic balance cancels
+            // two large terms, so they are combined in FP64 before rounding
             const double pt = ptilde(in, q);
-            S -= (R)((pt - w.pm) * (double)g.idr);
-            const R tg = in.Tn[q] + in.Tk[q];
-            S += g.prra * R(0.25) * (w.g0 + tg);
+            const double tg = (double)in.Tn[q] + (double)in.Tk[q];
+            S += (R)(g.prra_d * 0.25 * (w.tg + tg) - (pt - w.pm) * (double)g.idr);
             w.a0 = t0; w.a1 = t1; w.c0 = p0; w.c1 = p1;
             w.e0 = e0; w.e1 = e1; w.f0 = f0; w.f1 = f1;
-            w.g0 = tg; w.pm = pt;
+            w.tg = tg; w.pm = pt;
         } else if (L == FT) {
             const R r0 = wr[q - sJ + sI], r1 = wr[q + sI];
             ar = R(0.25) * ((w.a0 + r0) + (w.a1 + r1));
