@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--schwarz", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-grid", default="40,120,360")
+    ap.add_argument("--ensemble", type=int, default=0,
+                    help="batched ensemble of N shells (uneven sizes, seed 5), FP32-mixed, graph-captured")
     ap.add_argument("--mixed-error", type=int, default=0,
                     help="run FP64 and FP32-mixed side by side for N steps and report their difference")
     args = ap.parse_args()
@@ -83,6 +85,9 @@ def main():
         sys.exit(2)
     if args.mixed_error:
         mixed_error(args)
+        return
+    if args.ensemble:
+        ensemble(args)
         return
 
     import torch
@@ -200,6 +205,47 @@ def mixed_error(args):
                       "errors": errs, "fp64_ms_per_step": ms["fp64"], "fp32_mixed_ms_per_step": ms["fp32"],
                       "fp32_mixed_speedup": ms["fp64"] / ms["fp32"],
                       "cells": grid.cells}), flush=True)
+
+
+def ensemble(args):
+    """N shells of uneven sizes (Nr in [16,64], Nt in [48,192], Np = 3 Nt,
+    Ra log-uniform in [1e3, 1e6], seed 5), FP32-mixed, K Schwarz
+    iterations, advanced together by the captured graphs; compared with the
+    same shells stepped one after another without a graph."""
+    import torch
+    from paper_1905_02300_amd import inputs as I
+    from paper_1905_02300_amd import yy
+    shapes = I.ensemble_shapes(args.ensemble, seed=5)
+    K, dt, pr = args.schwarz, 2e-4, 1.0
+    ens = yy.Ensemble([s[:3] for s in shapes], prec=yy.YY_FP32_MIXED)
+    cells = 0
+    for q, (nr, nt, np_, ra) in enumerate(shapes):
+        g = I.Grid(nr, nt, np_)
+        cells += g.cells
+        sh = ens.shells[q]
+        sh.set_params(pr=pr, ra=ra, dt=dt, chi=1.0, t_inner=1.0, t_outer=0.0)
+        st = I.convection_state(g, pr, ra, seed=1000 + q)
+        for f in range(9):
+            sh.set_field(f, 0, st[f])
+            if f not in (I.P1, I.P2):
+                sh.set_field(f, 1, st[f])
+    res = {}
+    for mode in ("eager", "graph"):
+        graph = mode == "graph"
+        for _ in range(max(args.warmup, 2)):
+            ens.step(K, graph=graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ens.step(K, graph=graph)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[mode] = {"ms_per_step": el / args.steps * 1e3, "mcell_steps_s": cells * args.steps / el / 1e6}
+    print(json.dumps({"metric": METRIC, "value": res["graph"]["mcell_steps_s"], "unit": "Mcell-steps/s",
+                      "workload": f"ensemble_{args.ensemble}_shells_seed5_fp32mixed_K{K}", "cells": cells,
+                      "steps": args.steps, "graph": res["graph"], "sequential_eager": res["eager"],
+                      "graph_speedup_over_sequential": res["eager"]["ms_per_step"] / res["graph"]["ms_per_step"],
+                      "shells": [list(s[:3]) + [round(s[3], 1)] for s in shapes]}), flush=True)
 
 
 def cpu_baseline(grid_s, pr, ra, dt, K):

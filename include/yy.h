@@ -175,6 +175,34 @@ int yy_sweep_diffusion(yy_shell *s, int32_t dir, const void *dev_x, void *dev_y,
  * compute precision, written at the unknowns only). */
 int yy_residual(yy_shell *s, int32_t field, void *dev_out, hipStream_t stream);
 
+/* ---- ensembles: many independent shells advanced by one graph ---- */
+
+typedef struct yy_ensemble yy_ensemble;
+
+/* Total workspace of an ensemble of n shells (grids[0..n-1], one
+ * precision), each shell's part 256-byte aligned.  Errors: YY_ERR_ARG. */
+int yy_ensemble_workspace_bytes(int32_t n, const yy_grid *grids, int32_t prec, uint64_t *bytes);
+
+/* Create n shells inside one caller workspace.  Each shell is then set up
+ * and read through the single-shell calls on yy_ensemble_shell(e, s).
+ * Errors: as yy_create for any shell; on error *out is NULL. */
+int yy_ensemble_create(int32_t n, const yy_grid *grids, int32_t prec, void *dev_ws, uint64_t ws_bytes,
+                       yy_ensemble **out);
+
+/* Handle of shell s (0 <= s < n), or NULL. */
+yy_shell *yy_ensemble_shell(yy_ensemble *e, int32_t s);
+
+/* Advance every shell one time step with n_schwarz Schwarz iterations.
+ * The first call (and the first after any field or parameter change)
+ * runs eagerly where a ghost refresh is pending, then captures the step of
+ * all shells, each on its own forked stream, into hipGraphs (one per phase
+ * of the time-level rotation) and replays them on later calls.
+ * graph = 0 enqueues the shells one after another on the stream instead.
+ * Errors: YY_ERR_ARG, YY_ERR_STATE (a shell without params), YY_ERR_HIP. */
+int yy_ensemble_step(yy_ensemble *e, int32_t n_schwarz, int32_t graph, hipStream_t stream);
+
+int yy_ensemble_destroy(yy_ensemble *e);
+
 /* ---- live per-kernel timing (HIP events on the caller's stream) ---- */
 
 /* Kernel classes timed by the profiler. */

@@ -362,6 +362,7 @@ static const char *prof_names[YY_NPROF] = {
     "pressure_1", "pressure_2", "norm_reduce"};
 
 struct yy_shell {
+    uint64_t version = 0;    // bumped by every state or parameter change
     // live timing: event pairs around launch groups
     bool prof = false;
     std::vector<hipEvent_t> ev;
@@ -487,6 +488,8 @@ template <typename R> void solve_field(yy_shell *s, int f, hipStream_t st)
                   s->partial + (int64_t)f * 2 * NBMAX, &s->nblocks[f], 0, st);
 }
 
+template <typename R> void rotate_levels(yy_shell *s);
+
 template <typename R> int step_impl(yy_shell *s, int K, hipStream_t st)
 {
     State<R> &S = state_of<R>(s);
@@ -527,7 +530,16 @@ template <typename R> int step_impl(yy_shell *s, int K, hipStream_t st)
         reduce_norms(s->partial, s->nblocks, s->norms + (int64_t)k * 2 * NSLOT, st);
     }
     do_fill<R>(s, 2, 3, st);
-    // rotate levels: n-1 <- n <- k, and the old n-1 becomes the next work level
+    rotate_levels<R>(s);
+    s->last_k = K;
+    return hip_status(hipGetLastError());
+}
+
+// rotate time levels: n-1 <- n <- k; the old n-1 becomes the next working
+// level (host pointers only; the period is 6 = lcm of 3 and 2 levels)
+template <typename R> void rotate_levels(yy_shell *s)
+{
+    State<R> &S = state_of<R>(s);
     R *t = S.T[1];
     S.T[1] = S.T[0]; S.T[0] = S.T[2]; S.T[2] = t;
     for (int y = 0; y < 2; y++)
@@ -542,8 +554,6 @@ template <typename R> int step_impl(yy_shell *s, int K, hipStream_t st)
         S.p[y][0] = S.p[y][1];
         S.p[y][1] = p;
     }
-    s->last_k = K;
-    return hip_status(hipGetLastError());
 }
 
 }  // namespace
@@ -655,6 +665,7 @@ int yy_set_params(yy_shell *s, const yy_params *p)
     }
     s->have_params = true;
     s->need_fill = true;   // wall values may have changed
+    s->version++;
     return YY_OK;
 }
 
@@ -677,6 +688,7 @@ int yy_set_field(yy_shell *s, int32_t field, int32_t level, int32_t layout, cons
         Ops<float>::io(s->L.d, field_ptr<float>(s, field, level), src, nullptr, loc, layout, st);
     }
     s->need_fill = true;
+    s->version++;
     return hip_status(hipGetLastError());
 }
 
@@ -711,6 +723,7 @@ int yy_set_forcing(yy_shell *s, int32_t field, const double *src, hipStream_t st
     default: return YY_ERR_ARG;
     }
     const int loc = loc_of(field);
+    s->version++;
     if (s->L.prec == YY_FP64) {
         s->s64.force[c] = src ? (double *)s->force_ptr[c] : nullptr;
         if (src) Ops<double>::io(s->L.d, (double *)s->force_ptr[c], src, nullptr, loc, YY_MAC, st);
@@ -857,6 +870,227 @@ int yy_residual(yy_shell *s, int32_t field, void *out, hipStream_t st)
     if (s->L.prec == YY_FP64) Ops<double>::residual(s->L.d, s->g64, s->s64, field, (double *)out, st);
     else Ops<float>::residual(s->L.d, s->g32, s->s32, field, (float *)out, st);
     return hip_status(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// ensembles
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct yy_ensemble {
+    std::vector<yy_shell *> sh;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> join;
+    hipStream_t cap = nullptr;
+    hipEvent_t fork = nullptr;
+    hipGraph_t graph[6] = {};
+    hipGraphExec_t exec[6] = {};
+    bool captured = false;
+    int phase = 0, K = 0;
+    std::vector<uint64_t> versions;
+};
+
+namespace {
+
+int shell_step(yy_shell *s, int K, hipStream_t st)
+{
+    if (!s->have_params) return YY_ERR_STATE;
+    if (s->sticky != YY_OK) return s->sticky;
+    return s->L.prec == YY_FP64 ? step_impl<double>(s, K, st) : step_impl<float>(s, K, st);
+}
+
+void shell_rotate(yy_shell *s)
+{
+    if (s->L.prec == YY_FP64) rotate_levels<double>(s);
+    else rotate_levels<float>(s);
+}
+
+void drop_graphs(yy_ensemble *e)
+{
+    for (int f = 0; f < 6; f++) {
+        if (e->exec[f]) (void)hipGraphExecDestroy(e->exec[f]);
+        if (e->graph[f]) (void)hipGraphDestroy(e->graph[f]);
+        e->exec[f] = nullptr;
+        e->graph[f] = nullptr;
+    }
+    e->captured = false;
+}
+
+// capture the six rotation phases of one ensemble step; every shell's
+// kernels go on its own stream, forked from and joined to the capture stream
+int capture(yy_ensemble *e, int K)
+{
+    drop_graphs(e);
+    std::vector<bool> prof(e->sh.size());
+    for (size_t q = 0; q < e->sh.size(); q++) {
+        prof[q] = e->sh[q]->prof;
+        e->sh[q]->prof = false;
+    }
+    int st = YY_OK;
+    for (int f = 0; f < 6 && st == YY_OK; f++) {
+        hipError_t h = hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal);
+        if (h == hipSuccess) h = hipEventRecord(e->fork, e->cap);
+        for (size_t q = 0; q < e->sh.size() && h == hipSuccess; q++) {
+            h = hipStreamWaitEvent(e->streams[q], e->fork, 0);
+            if (h == hipSuccess) {
+                const int r = shell_step(e->sh[q], K, e->streams[q]);
+                if (r != YY_OK) { st = r; h = hipErrorUnknown; }
+            }
+            if (h == hipSuccess) h = hipEventRecord(e->join[q], e->streams[q]);
+            if (h == hipSuccess) h = hipStreamWaitEvent(e->cap, e->join[q], 0);
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t h2 = hipStreamEndCapture(e->cap, &g);
+        if (h == hipSuccess) h = h2;
+        if (h == hipSuccess) h = hipGraphInstantiate(&e->exec[f], g, nullptr, nullptr, 0);
+        e->graph[f] = g;
+        if (h != hipSuccess && st == YY_OK) st = YY_ERR_HIP;
+    }
+    for (size_t q = 0; q < e->sh.size(); q++) e->sh[q]->prof = prof[q];
+    if (st != YY_OK) {
+        drop_graphs(e);
+        return st;
+    }
+    e->captured = true;
+    e->phase = 0;
+    e->K = K;
+    for (size_t q = 0; q < e->sh.size(); q++) e->versions[q] = e->sh[q]->version;
+    return YY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int yy_ensemble_workspace_bytes(int32_t n, const yy_grid *grids, int32_t prec, uint64_t *bytes)
+{
+    if (n < 1 || !grids || !bytes) return YY_ERR_ARG;
+    uint64_t tot = 0;
+    for (int q = 0; q < n; q++) {
+        uint64_t b = 0;
+        const int st = yy_workspace_bytes(&grids[q], prec, &b);
+        if (st != YY_OK) return st;
+        tot += (uint64_t)align_up((int64_t)b, ALIGN);
+    }
+    *bytes = tot;
+    return YY_OK;
+}
+
+int yy_ensemble_create(int32_t n, const yy_grid *grids, int32_t prec, void *dev_ws, uint64_t ws_bytes,
+                       yy_ensemble **out)
+{
+    if (!out) return YY_ERR_ARG;
+    *out = nullptr;
+    uint64_t need = 0;
+    int st = yy_ensemble_workspace_bytes(n, grids, prec, &need);
+    if (st != YY_OK) return st;
+    if (!dev_ws || (uintptr_t)dev_ws % ALIGN) return YY_ERR_WORKSPACE;
+    if (ws_bytes < need) return YY_ERR_WORKSPACE;
+    // validate every geometry before touching the device
+    for (int q = 0; q < n; q++) {
+        Layout L = make_layout(&grids[q], prec);
+        Frame F;
+        F.r1 = grids[q].r1;
+        F.r2 = grids[q].r2;
+        F.delta = grids[q].delta > 0.0 ? grids[q].delta : M_PI / (2.0 * (grids[q].nt - 2));
+        F.dr = (F.r2 - F.r1) / grids[q].nr;
+        F.th0 = M_PI / 4.0 - F.delta;
+        F.ph0 = -3.0 * M_PI / 4.0 - F.delta;
+        F.dth = (M_PI / 2.0 + 2.0 * F.delta) / grids[q].nt;
+        F.dph = (1.5 * M_PI + 2.0 * F.delta) / grids[q].np;
+        std::vector<FillScalar> cc;
+        std::vector<FillVector> vt, vp;
+        if (!build_fill(F, L.d, cc, vt, vp)) return YY_ERR_GEOMETRY;
+    }
+    yy_ensemble *e = new (std::nothrow) yy_ensemble();
+    if (!e) return YY_ERR_ARG;
+    char *base = (char *)dev_ws;
+    for (int q = 0; q < n && st == YY_OK; q++) {
+        uint64_t b = 0;
+        yy_workspace_bytes(&grids[q], prec, &b);
+        yy_shell *sh = nullptr;
+        st = yy_create(&grids[q], prec, base, b, &sh);
+        if (st == YY_OK) e->sh.push_back(sh);
+        base += align_up((int64_t)b, ALIGN);
+    }
+    hipError_t h = hipSuccess;
+    if (st == YY_OK) {
+        e->streams.resize(n, nullptr);
+        e->join.resize(n, nullptr);
+        e->versions.resize(n, 0);
+        for (int q = 0; q < n && h == hipSuccess; q++) {
+            h = hipStreamCreateWithFlags(&e->streams[q], hipStreamNonBlocking);
+            if (h == hipSuccess) h = hipEventCreateWithFlags(&e->join[q], hipEventDisableTiming);
+        }
+        if (h == hipSuccess) h = hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking);
+        if (h == hipSuccess) h = hipEventCreateWithFlags(&e->fork, hipEventDisableTiming);
+        if (h != hipSuccess) st = YY_ERR_HIP;
+    }
+    if (st != YY_OK) {
+        yy_ensemble_destroy(e);
+        return st;
+    }
+    *out = e;
+    return YY_OK;
+}
+
+yy_shell *yy_ensemble_shell(yy_ensemble *e, int32_t s)
+{
+    if (!e || s < 0 || s >= (int32_t)e->sh.size()) return nullptr;
+    return e->sh[s];
+}
+
+int yy_ensemble_step(yy_ensemble *e, int32_t K, int32_t graph, hipStream_t stream)
+{
+    if (!e || K < 1 || K > MAXK) return YY_ERR_ARG;
+    for (yy_shell *s : e->sh) {
+        if (!s->have_params) return YY_ERR_STATE;
+        if (s->sticky != YY_OK) return s->sticky;
+    }
+    if (!graph) {
+        for (yy_shell *s : e->sh) {
+            const int st = shell_step(s, K, stream);
+            if (st != YY_OK) return st;
+        }
+        return YY_OK;
+    }
+    bool stale = !e->captured || e->K != K;
+    for (size_t q = 0; q < e->sh.size() && !stale; q++)
+        if (e->sh[q]->version != e->versions[q]) stale = true;
+    bool pending = false;
+    for (yy_shell *s : e->sh) pending = pending || s->need_fill;
+    if (stale && pending) {
+        // this step runs eagerly (it performs the pending ghost refresh);
+        // the graphs are captured for the following steps
+        for (yy_shell *s : e->sh) {
+            const int st = shell_step(s, K, stream);
+            if (st != YY_OK) return st;
+        }
+        return capture(e, K);
+    }
+    if (stale) {
+        const int st = capture(e, K);
+        if (st != YY_OK) return st;
+    }
+    if (hipGraphLaunch(e->exec[e->phase], stream) != hipSuccess) return YY_ERR_HIP;
+    for (yy_shell *s : e->sh) shell_rotate(s);
+    e->phase = (e->phase + 1) % 6;
+    return YY_OK;
+}
+
+int yy_ensemble_destroy(yy_ensemble *e)
+{
+    if (!e) return YY_ERR_ARG;
+    drop_graphs(e);
+    for (hipStream_t s : e->streams)
+        if (s) (void)hipStreamDestroy(s);
+    for (hipEvent_t v : e->join)
+        if (v) (void)hipEventDestroy(v);
+    if (e->cap) (void)hipStreamDestroy(e->cap);
+    if (e->fork) (void)hipEventDestroy(e->fork);
+    for (yy_shell *s : e->sh) yy_destroy(s);
+    delete e;
+    return YY_OK;
 }
 
 }  // extern "C"

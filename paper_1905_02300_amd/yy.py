@@ -23,7 +23,9 @@ NNORMS = 10
 EXPORTS = ["yy_workspace_bytes", "yy_create", "yy_set_params", "yy_set_field", "yy_get_field",
            "yy_set_forcing", "yy_step", "yy_get_norms", "yy_destroy", "yy_strerror",
            "yy_internal_dims", "yy_fill", "yy_extrapolate", "yy_sweep", "yy_sweep_diffusion",
-           "yy_residual", "yy_profile", "yy_profile_read", "yy_profile_name"]
+           "yy_residual", "yy_profile", "yy_profile_read", "yy_profile_name",
+           "yy_ensemble_workspace_bytes", "yy_ensemble_create", "yy_ensemble_shell",
+           "yy_ensemble_step", "yy_ensemble_destroy"]
 NPROF = 16
 
 
@@ -78,6 +80,12 @@ def load():
     L.yy_profile_read.argtypes = [vp, P(ctypes.c_double), P(i64), vp]
     L.yy_profile_name.argtypes = [i32]
     L.yy_profile_name.restype = ctypes.c_char_p
+    L.yy_ensemble_workspace_bytes.argtypes = [i32, P(Grid), i32, P(u64)]
+    L.yy_ensemble_create.argtypes = [i32, P(Grid), i32, vp, u64, P(vp)]
+    L.yy_ensemble_shell.argtypes = [vp, i32]
+    L.yy_ensemble_shell.restype = vp
+    L.yy_ensemble_step.argtypes = [vp, i32, i32, vp]
+    L.yy_ensemble_destroy.argtypes = [vp]
     _lib = L
     return L
 
@@ -111,21 +119,27 @@ def _stream_ptr(stream):
 class Shell:
     """One Yin-Yang shell on the current HIP device."""
 
-    def __init__(self, nr, nt, np_, r1=0.5, r2=1.0, delta=0.0, prec=YY_FP64, device="cuda"):
+    def __init__(self, nr, nt, np_, r1=0.5, r2=1.0, delta=0.0, prec=YY_FP64, device="cuda",
+                 _handle=None, _ws=None):
         import torch
         L = load()
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: libyy.so runs on MI355X only")
         self.nr, self.nt, self.np, self.prec = nr, nt, np_, prec
         self.grid = Grid(nr, nt, np_, r1, r2, delta)
-        nbytes = workspace_bytes(nr, nt, np_, r1, r2, delta, prec)
-        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
-        base = self.ws.data_ptr()
-        self._off = (-base) % 256
-        h = ctypes.c_void_p()
-        _check(L.yy_create(ctypes.byref(self.grid), prec, ctypes.c_void_p(base + self._off),
-                           nbytes, ctypes.byref(h)), "yy_create")
-        self.h = h
+        self._owned = _handle is None
+        if _handle is None:
+            nbytes = workspace_bytes(nr, nt, np_, r1, r2, delta, prec)
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+            base = self.ws.data_ptr()
+            self._off = (-base) % 256
+            h = ctypes.c_void_p()
+            _check(L.yy_create(ctypes.byref(self.grid), prec, ctypes.c_void_p(base + self._off),
+                               nbytes, ctypes.byref(h)), "yy_create")
+            self.h = h
+        else:
+            self.ws = _ws
+            self.h = ctypes.c_void_p(_handle)
         dims = (ctypes.c_int64 * 4)()
         eb = ctypes.c_int32()
         _check(L.yy_internal_dims(self.h, dims, ctypes.byref(eb)), "yy_internal_dims")
@@ -134,9 +148,9 @@ class Shell:
         self.K = 0
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and self._owned:
             load().yy_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:
@@ -246,3 +260,51 @@ class Shell:
 
     def from_internal(self, t):
         return t[..., :self.np + 2]
+
+
+class Ensemble:
+    """Independent shells in one workspace, stepped by one captured graph."""
+
+    def __init__(self, grids, prec=YY_FP32_MIXED, device="cuda"):
+        """grids: list of (nr, nt, np) or (nr, nt, np, r1, r2, delta)"""
+        import torch
+        L = load()
+        n = len(grids)
+        arr = (Grid * n)()
+        for q, g in enumerate(grids):
+            g = tuple(g) + (0.5, 1.0, 0.0)[len(g) - 3:] if len(g) < 6 else tuple(g)
+            arr[q] = Grid(*g)
+        nbytes = ctypes.c_uint64()
+        _check(L.yy_ensemble_workspace_bytes(n, arr, prec, ctypes.byref(nbytes)),
+               "yy_ensemble_workspace_bytes")
+        self.ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        h = ctypes.c_void_p()
+        _check(L.yy_ensemble_create(n, arr, prec, ctypes.c_void_p(base + off), nbytes.value,
+                                    ctypes.byref(h)), "yy_ensemble_create")
+        self.h = h
+        self.shells = []
+        for q in range(n):
+            sh = L.yy_ensemble_shell(self.h, q)
+            self.shells.append(Shell(arr[q].nr, arr[q].nt, arr[q].np, arr[q].r1, arr[q].r2,
+                                     arr[q].delta, prec, device, _handle=sh, _ws=self.ws))
+
+    def step(self, K, graph=True, stream=None):
+        _check(load().yy_ensemble_step(self.h, K, 1 if graph else 0, _stream_ptr(stream)),
+               "yy_ensemble_step")
+        for sh in self.shells:
+            sh.K = K
+
+    def close(self):
+        if getattr(self, "h", None):
+            for sh in self.shells:
+                sh.h = None
+            load().yy_ensemble_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
