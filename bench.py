@@ -74,6 +74,7 @@ def main():
     ap.add_argument("--grid", default="128,384,1152")
     ap.add_argument("--schwarz", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the line-solver tile autotuner")
     ap.add_argument("--cpu-grid", default="40,120,360")
     ap.add_argument("--ensemble", type=int, default=0,
                     help="batched ensemble of N shells (uneven sizes, seed 5), FP32-mixed, graph-captured")
@@ -108,6 +109,7 @@ def main():
             sh.set_field(f, 1, st[f])
     del st
     stream = torch.cuda.current_stream()
+    tiles = sh.autotune() if not args.no_tune else None
     for _ in range(args.warmup):
         sh.step(K)
     torch.cuda.synchronize()
@@ -161,6 +163,7 @@ def main():
                    "Pr": pr, "Ra": ra, "dt": dt, "parallelism": "single-gpu"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "tiles": tiles,
         "kernels": kernels,
         "last_step_norms_k_last": {"div_u2": float(norms[-1, :, 9].max()),
                                    "dT": float(norms[-1, :, 0].max())},
@@ -229,6 +232,11 @@ def ensemble(args):
             sh.set_field(f, 0, st[f])
             if f not in (I.P1, I.P2):
                 sh.set_field(f, 1, st[f])
+    tunes = {}
+    t0 = time.perf_counter()
+    for q, sh in enumerate(ens.shells):
+        tunes[q] = sh.autotune()
+    tune_s = time.perf_counter() - t0
     res = {}
     for mode in ("eager", "graph"):
         graph = mode == "graph"
@@ -245,6 +253,7 @@ def ensemble(args):
                       "workload": f"ensemble_{args.ensemble}_shells_seed5_fp32mixed_K{K}", "cells": cells,
                       "steps": args.steps, "graph": res["graph"], "sequential_eager": res["eager"],
                       "graph_speedup_over_sequential": res["eager"]["ms_per_step"] / res["graph"]["ms_per_step"],
+                      "autotune_seconds": tune_s, "tiles": tunes,
                       "shells": [list(s[:3]) + [round(s[3], 1)] for s in shapes]}), flush=True)
 
 

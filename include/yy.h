@@ -175,6 +175,22 @@ int yy_sweep_diffusion(yy_shell *s, int32_t dir, const void *dev_x, void *dev_y,
  * compute precision, written at the unknowns only). */
 int yy_residual(yy_shell *s, int32_t field, void *dev_out, hipStream_t stream);
 
+/* ---- line-solver autotuning ---- */
+
+/* Time every tile variant of the partitioned line solves of this shell
+ * (strided r/theta sweeps: rows per chunk 8/12/16 x lane width 64/32/16;
+ * phi sweeps: lines per block 1/2/4), each on the shell's own scratch
+ * buffer with its current advecting velocity, keep the fastest per
+ * (unknown, direction), and write the choices as a JSON object (a
+ * NUL-terminated string of at most cap bytes) to json_out if not NULL.
+ * Synchronises the stream.  Needs params.  Errors: YY_ERR_ARG,
+ * YY_ERR_STATE, YY_ERR_HIP. */
+int yy_autotune(yy_shell *s, char *json_out, int32_t cap, hipStream_t stream);
+
+/* Apply choices written by yy_autotune (a tuning cache).  Unknown keys are
+ * ignored.  Errors: YY_ERR_ARG (NULL or malformed). */
+int yy_set_tuning(yy_shell *s, const char *json);
+
 /* ---- ensembles: many independent shells advanced by one graph ---- */
 
 typedef struct yy_ensemble yy_ensemble;

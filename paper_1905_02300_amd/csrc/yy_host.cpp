@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/yy.h"
@@ -870,6 +871,119 @@ int yy_residual(yy_shell *s, int32_t field, void *out, hipStream_t st)
     if (s->L.prec == YY_FP64) Ops<double>::residual(s->L.d, s->g64, s->s64, field, (double *)out, st);
     else Ops<float>::residual(s->L.d, s->g32, s->s32, field, (float *)out, st);
     return hip_status(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// autotuning of the line-solver tiles
+// ---------------------------------------------------------------------------
+static const char *tune_field_name[4] = {"T", "u_r", "u_t", "u_p"};
+static const int tune_field_id[4] = {YY_T, YY_U2R, YY_U2T, YY_U2P};
+static const char dir_name[3] = {'r', 't', 'p'};
+
+static Tune &tune_of(yy_shell *s) { return s->L.prec == YY_FP64 ? s->s64.tune : s->s32.tune; }
+
+// time one sweep configuration: mean of 3 runs after one warm-up (ms)
+static double time_sweep(yy_shell *s, int field, int dir, hipStream_t st, hipEvent_t a, hipEvent_t b)
+{
+    void *buf = s->L.prec == YY_FP64 ? (void *)s->s64.res : (void *)s->s32.res;
+    if (yy_sweep(s, field, dir, buf, buf, st) != YY_OK) return 1e30;
+    (void)hipEventRecord(a, st);
+    for (int q = 0; q < 3; q++)
+        if (yy_sweep(s, field, dir, buf, buf, st) != YY_OK) return 1e30;
+    (void)hipEventRecord(b, st);
+    if (hipEventSynchronize(b) != hipSuccess) return 1e30;
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    return ms / 3.0;
+}
+
+extern "C" int yy_autotune(yy_shell *s, char *json_out, int32_t cap, hipStream_t st)
+{
+    if (!s) return YY_ERR_ARG;
+    if (!s->have_params) return YY_ERR_STATE;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return YY_ERR_HIP;
+    if (hipEventCreate(&b) != hipSuccess) return YY_ERR_HIP;
+    const bool prof = s->prof;
+    s->prof = false;
+    Tune &T = tune_of(s);
+    std::string js = "{";
+    for (int L = 0; L < 4; L++) {
+        for (int dir = 0; dir < 3; dir++) {
+            char key[16];
+            std::snprintf(key, sizeof key, "%s.%c", tune_field_name[L], dir_name[dir]);
+            char val[32];
+            if (dir < 2) {
+                int bm = 0, bw = 0;
+                double best = 1e30;
+                const int ms[3] = {8, 12, 16}, ws[3] = {64, 32, 16};
+                for (int im = 0; im < 3; im++)
+                    for (int iw = 0; iw < 3; iw++) {
+                        T.m[L][dir] = (int8_t)ms[im];
+                        T.w[L][dir] = (int8_t)ws[iw];
+                        const double t = time_sweep(s, tune_field_id[L], dir, st, a, b);
+                        if (t < best) { best = t; bm = ms[im]; bw = ws[iw]; }
+                    }
+                T.m[L][dir] = (int8_t)bm;
+                T.w[L][dir] = (int8_t)bw;
+                std::snprintf(val, sizeof val, "m%dw%d", bm, bw);
+            } else {
+                int bl = 0;
+                double best = 1e30;
+                const int ls[3] = {1, 2, 4};
+                for (int il = 0; il < 3; il++) {
+                    T.lpb[L] = (int8_t)ls[il];
+                    const double t = time_sweep(s, tune_field_id[L], dir, st, a, b);
+                    if (t < best) { best = t; bl = ls[il]; }
+                }
+                T.lpb[L] = (int8_t)bl;
+                std::snprintf(val, sizeof val, "l%d", bl);
+            }
+            if (js.size() > 1) js += ",";
+            js += "\"";
+            js += key;
+            js += "\":\"";
+            js += val;
+            js += "\"";
+        }
+    }
+    js += "}";
+    s->prof = prof;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    s->version++;
+    if (json_out && cap > 0) {
+        std::strncpy(json_out, js.c_str(), (size_t)cap - 1);
+        json_out[cap - 1] = 0;
+    }
+    return hip_status(hipGetLastError());
+}
+
+extern "C" int yy_set_tuning(yy_shell *s, const char *json)
+{
+    if (!s || !json) return YY_ERR_ARG;
+    Tune &T = tune_of(s);
+    const std::string js(json);
+    for (int L = 0; L < 4; L++)
+        for (int dir = 0; dir < 3; dir++) {
+            char key[24];
+            std::snprintf(key, sizeof key, "\"%s.%c\":\"", tune_field_name[L], dir_name[dir]);
+            const size_t at = js.find(key);
+            if (at == std::string::npos) continue;
+            const char *v = js.c_str() + at + std::strlen(key);
+            int m = 0, w = 0, l = 0;
+            if (dir < 2) {
+                if (std::sscanf(v, "m%dw%d", &m, &w) != 2) return YY_ERR_ARG;
+                if ((m != 8 && m != 12 && m != 16) || (w != 16 && w != 32 && w != 64)) return YY_ERR_ARG;
+                T.m[L][dir] = (int8_t)m;
+                T.w[L][dir] = (int8_t)w;
+            } else {
+                if (std::sscanf(v, "l%d", &l) != 1 || (l != 1 && l != 2 && l != 4)) return YY_ERR_ARG;
+                T.lpb[L] = (int8_t)l;
+            }
+        }
+    s->version++;
+    return YY_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -77,8 +77,16 @@ struct FillVector {
     double ma, mb;
 };
 
+// line-solver tile choices per location (CC, FR, FT, FP); 0 = built-in
+// default.  Strided r/theta sweeps: rows per chunk m (8, 12, 16) and the
+// largest lane width w (64, 32, 16); phi sweeps: lines per block (1, 2, 4).
+struct Tune {
+    int8_t m[4][2], w[4][2], lpb[4];
+};
+
 // pointers of one step (compute precision R; pressures double)
 template <typename R> struct State {
+    Tune tune;
     R *T[3];                 // levels n, n-1, working iterate k
     R *Ts;                   // T*
     R *u[2][3][3];           // [system][component r,t,p][level]

@@ -973,14 +973,18 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
 {
     const int i0 = ulo<L>(0), j0 = ulo<L>(1), k0 = ulo<L>(2);
     if (D < 2) {
-        // the u_theta polar sweep reads the most per-row data: smaller chunks
-        constexpr int M = (L == FT && D == 1) ? 12 : 16;
+        // rows per chunk: tuned, else 12 for the u_theta polar sweep (the
+        // most per-row data) and 16 otherwise
+        int M = s.tune.m[L][D];
+        if (M != 8 && M != 12 && M != 16) M = (L == FT && D == 1) ? 12 : 16;
         const int n = ncell(d, D) - (D == 0 ? i0 : j0);
         int P = (n + M - 1) / M;
         if (P < 1) P = 1;
         // W lanes (consecutive k) per chunk row; W * P <= 512 and a whole
         // number of 64-lane waves
-        int W = 64;
+        int wmax = s.tune.w[L][D];
+        if (wmax != 16 && wmax != 32 && wmax != 64) wmax = 64;
+        int W = wmax;
         while (W * P > 512 && W > 8) W >>= 1;
         const int q = 64 / W;
         P = (P + q - 1) / q * q;
@@ -993,8 +997,15 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
         if (nblocks) *nblocks = (int)b;
         if (2 * P > n && n > 1) return false;
         const size_t lds = (size_t)4 * P * W * sizeof(R);
-        hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, M>), dim3((unsigned)b, 2), dim3(W, P),
-                           lds, st, d, g, gd, s, x, y, psi, partial);
+        if (M == 8)
+            hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, 8>), dim3((unsigned)b, 2), dim3(W, P),
+                               lds, st, d, g, gd, s, x, y, psi, partial);
+        else if (M == 12)
+            hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, 12>), dim3((unsigned)b, 2), dim3(W, P),
+                               lds, st, d, g, gd, s, x, y, psi, partial);
+        else
+            hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, 16>), dim3((unsigned)b, 2), dim3(W, P),
+                               lds, st, d, g, gd, s, x, y, psi, partial);
         return true;
     } else {
         const int n = d.np - k0;
@@ -1011,6 +1022,8 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
         int lpb = (int)(65536 / per_line);
         if (lpb > 4) lpb = 4;
         if (lpb < 1) return false;
+        const int want = s.tune.lpb[L];
+        if ((want == 1 || want == 2 || want == 4) && want < lpb) lpb = want;
         const int64_t nlines = (int64_t)(d.nr - i0) * (d.nt - j0);
         int64_t b = (nlines + lpb - 1) / lpb;
         if (b > NBMAX) b = NBMAX;

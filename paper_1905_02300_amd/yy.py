@@ -25,7 +25,7 @@ EXPORTS = ["yy_workspace_bytes", "yy_create", "yy_set_params", "yy_set_field", "
            "yy_internal_dims", "yy_fill", "yy_extrapolate", "yy_sweep", "yy_sweep_diffusion",
            "yy_residual", "yy_profile", "yy_profile_read", "yy_profile_name",
            "yy_ensemble_workspace_bytes", "yy_ensemble_create", "yy_ensemble_shell",
-           "yy_ensemble_step", "yy_ensemble_destroy"]
+           "yy_ensemble_step", "yy_ensemble_destroy", "yy_autotune", "yy_set_tuning"]
 NPROF = 16
 
 
@@ -86,6 +86,8 @@ def load():
     L.yy_ensemble_shell.restype = vp
     L.yy_ensemble_step.argtypes = [vp, i32, i32, vp]
     L.yy_ensemble_destroy.argtypes = [vp]
+    L.yy_autotune.argtypes = [vp, ctypes.c_char_p, i32, vp]
+    L.yy_set_tuning.argtypes = [vp, ctypes.c_char_p]
     _lib = L
     return L
 
@@ -238,6 +240,15 @@ class Shell:
     def residual(self, field, out, stream=None):
         _check(load().yy_residual(self.h, field, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)),
                "yy_residual")
+
+    def autotune(self, stream=None):
+        """time the line-solver tile variants; returns the choices (JSON)"""
+        buf = ctypes.create_string_buffer(4096)
+        _check(load().yy_autotune(self.h, buf, 4096, _stream_ptr(stream)), "yy_autotune")
+        return buf.value.decode()
+
+    def set_tuning(self, js):
+        _check(load().yy_set_tuning(self.h, js.encode()), "yy_set_tuning")
 
     def profile(self, enable=True):
         _check(load().yy_profile(self.h, 1 if enable else 0), "yy_profile")

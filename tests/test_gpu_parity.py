@@ -289,3 +289,39 @@ def test_ensemble_graph_matches_eager(yy):
             b = ens[1].shells[q].get_field(f).cpu().numpy()
             assert np.array_equal(a, b), (q, I.FIELD_NAMES[f])
         assert np.array_equal(ens[0].shells[q].norms(), ens[1].shells[q].norms())
+
+
+@pytest.mark.parametrize("variant", ["m8w64", "m8w16", "m12w32", "m16w64", "m16w16"])
+def test_sweep_parity_every_tile(oracle_lib, yy, variant):
+    """Every tile choice the autotuner can make gives the oracle's answer."""
+    print(f"case: tile {variant}", flush=True)
+    shape = (40, 48, 144)
+    o, g = _pair(oracle_lib, yy, *shape, pr=1.1, dt=1e-3, chi=0.9)
+    rng = np.random.default_rng(77)
+    _set_random(o, g, rng, [0, 1], scale=0.5)
+    o.extrapolate()
+    g.extrapolate()
+    lpb = {"m8w64": 1, "m8w16": 2, "m12w32": 4, "m16w64": 1, "m16w16": 2}[variant]
+    js = "{" + ",".join(f'"{f}.{d}":"{variant}"' for f in ("T", "u_r", "u_t", "u_p") for d in "rt")
+    js += "," + ",".join(f'"{f}.p":"l{lpb}"' for f in ("T", "u_r", "u_t", "u_p")) + "}"
+    g.set_tuning(js)
+    for field in (I.T, I.U2R, I.U2T, I.U2P):
+        m = _unknown_mask(o.padded_shape(), field)
+        for d in range(3):
+            x = rng.uniform(-1, 1, o.padded_shape())
+            ref = o.sweep(field, d, x)
+            yt = g.internal_tensor()
+            g.sweep(field, d, g.to_internal(x), yt)
+            got = g.from_internal(yt).cpu().numpy()
+            assert _rel(got[m], ref[m]) <= TOL, (field, d, _rel(got[m], ref[m]))
+
+
+def test_autotune_round_trip(yy):
+    print("case: autotune", flush=True)
+    g = yy.Shell(12, 40, 120)
+    g.set_params(pr=1.0, ra=1e4, dt=2e-4)
+    js = g.autotune()
+    assert js.startswith("{") and '"u_t.t"' in js and '"T.p"' in js
+    g.set_tuning(js)
+    with pytest.raises(yy.YYError):
+        g.set_tuning('{"T.r":"m7w64"}')
