@@ -56,6 +56,8 @@ Layout make_layout(const yy_grid *g, int prec)
     L.d.sJ = align_up(g->np + 2, 16);
     L.d.sI = (int64_t)(g->nt + 2) * L.d.sJ;
     L.d.sP = (int64_t)(g->nr + 2) * L.d.sI;
+    L.d.p0 = 0;
+    L.d.npatch = 2;
     L.field_elems = 2 * L.d.sP;
     L.elem = prec == YY_FP64 ? 8 : 4;
     L.ncc = 2LL * g->np + 2LL * g->nt;
@@ -470,22 +472,21 @@ template <typename R> void do_fill(yy_shell *s, int lev, int pmask, hipStream_t 
                  (int)s->L.nvp, s->prm.t_inner, s->prm.t_outer, pmask, st);
 }
 
-template <typename R> void solve_field(yy_shell *s, int f, hipStream_t st)
+template <typename R> void solve_field(yy_shell *s, const Dims &d, int f, hipStream_t st)
 {
     State<R> &S = state_of<R>(s);
     const int loc = loc_of(f);
     static const int order[4][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1}, {0, 1, 2}};
     {
         Timed tm(s, PC_RES_T + loc, st);
-        Ops<R>::residual(s->L.d, geo_of<R>(s), S, f, S.res, st);
+        Ops<R>::residual(d, geo_of<R>(s), S, f, S.res, st);
     }
     for (int q = 0; q < 2; q++) {
         Timed tm(s, PC_SW_R + order[loc][q], st);
-        Ops<R>::sweep(s->L.d, geo_of<R>(s), s->gd, S, f, order[loc][q], S.res, S.res, 0, nullptr,
-                      nullptr, 0, st);
+        Ops<R>::sweep(d, geo_of<R>(s), s->gd, S, f, order[loc][q], S.res, S.res, 0, nullptr, nullptr, 0, st);
     }
     Timed tm(s, PC_SW_R_LAST + order[loc][2], st);
-    Ops<R>::sweep(s->L.d, geo_of<R>(s), s->gd, S, f, order[loc][2], S.res, S.res, 1,
+    Ops<R>::sweep(d, geo_of<R>(s), s->gd, S, f, order[loc][2], S.res, S.res, 1,
                   s->partial + (int64_t)f * 2 * NBMAX, &s->nblocks[f], 0, st);
 }
 
@@ -508,23 +509,35 @@ template <typename R> int step_impl(yy_shell *s, int K, hipStream_t st)
         Ops<R>::copy_levels(s->L.d, S, 0, 2, st);
     }
     for (int k = 0; k < K; k++) {
-        do_fill<R>(s, 2, 3, st);
-        solve_field<R>(s, YY_T, st);
-        solve_field<R>(s, YY_U1R, st);
-        solve_field<R>(s, YY_U1T, st);
-        solve_field<R>(s, YY_U1P, st);
-        {
-            Timed tm(s, PC_PRESS1, st);
-            Ops<R>::pressure(s->L.d, geo_of<R>(s), s->gd, S, 1, s->partial + (int64_t)YY_P1 * 2 * NBMAX,
-                             nullptr, &s->nblocks[YY_P1], st);
-        }
-        solve_field<R>(s, YY_U2R, st);
-        solve_field<R>(s, YY_U2T, st);
-        solve_field<R>(s, YY_U2P, st);
-        {
-            Timed tm(s, PC_PRESS2, st);
-            Ops<R>::pressure(s->L.d, geo_of<R>(s), s->gd, S, 2, s->partial + (int64_t)YY_P2 * 2 * NBMAX,
-                             s->partial + (int64_t)9 * 2 * NBMAX, &s->nblocks[YY_P2], st);
+        // additive: both patches at once from the other's iterate k-1;
+        // multiplicative (Algorithm of Sec. 4): Yin, then Yang from Yin's k
+        const int passes = s->prm.mode == YY_MULTIPLICATIVE ? 2 : 1;
+        for (int pass = 0; pass < passes; pass++) {
+            Dims d = s->L.d;
+            int pmask = 3;
+            if (passes == 2) {
+                d.p0 = pass;
+                d.npatch = 1;
+                pmask = 1 << pass;
+            }
+            do_fill<R>(s, 2, pmask, st);
+            solve_field<R>(s, d, YY_T, st);
+            solve_field<R>(s, d, YY_U1R, st);
+            solve_field<R>(s, d, YY_U1T, st);
+            solve_field<R>(s, d, YY_U1P, st);
+            {
+                Timed tm(s, PC_PRESS1, st);
+                Ops<R>::pressure(d, geo_of<R>(s), s->gd, S, 1, s->partial + (int64_t)YY_P1 * 2 * NBMAX,
+                                 nullptr, &s->nblocks[YY_P1], st);
+            }
+            solve_field<R>(s, d, YY_U2R, st);
+            solve_field<R>(s, d, YY_U2T, st);
+            solve_field<R>(s, d, YY_U2P, st);
+            {
+                Timed tm(s, PC_PRESS2, st);
+                Ops<R>::pressure(d, geo_of<R>(s), s->gd, S, 2, s->partial + (int64_t)YY_P2 * 2 * NBMAX,
+                                 s->partial + (int64_t)9 * 2 * NBMAX, &s->nblocks[YY_P2], st);
+            }
         }
         s->nblocks[9] = s->nblocks[YY_P2];
         Timed tm(s, PC_REDUCE, st);
@@ -650,7 +663,7 @@ int yy_set_params(yy_shell *s, const yy_params *p)
     if (!(p->dt > 0.0) || !(p->chi > 0.0) || !(p->pr > 0.0) || !std::isfinite(p->ra) ||
         !std::isfinite(p->dt) || !std::isfinite(p->t_inner) || !std::isfinite(p->t_outer))
         return YY_ERR_ARG;
-    if (p->mode != YY_ADDITIVE) return YY_ERR_ARG;
+    if (p->mode != YY_ADDITIVE && p->mode != YY_MULTIPLICATIVE) return YY_ERR_ARG;
     s->prm = *p;
     set_coefs<double>(s->gd, *p);
     set_coefs<double>(s->g64, *p);

@@ -15,6 +15,7 @@ enum Loc { CC = 0, FR = 1, FT = 2, FP = 3 };   // centre, r-, theta-, phi-face
 struct Dims {
     int nr, nt, np;
     int64_t sJ, sI, sP;      // element strides of j, i and patch (k: 1)
+    int p0, npatch;          // patches a launch covers: p0 .. p0+npatch-1
 };
 
 __host__ __device__ inline int64_t ix(const Dims &d, int p, int i, int j, int k)

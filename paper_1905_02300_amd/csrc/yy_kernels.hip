@@ -377,7 +377,7 @@ template <typename R> struct Col {
 template <typename R, int L>
 __global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R> s, RhsIn<R> in, R *out)
 {
-    const int p = blockIdx.y;
+    const int p = d.p0 + blockIdx.y;
     const int j0 = ulo<L>(1), k0 = ulo<L>(2), i0 = ulo<L>(0);
     const int nj = d.nt - j0, nk = d.np - k0;
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -525,7 +525,7 @@ template <typename R, int L, int D, int MODE, bool DIFF>
 __global__ void __launch_bounds__(256) k_sweep(Dims d, Geo<R> g, Geo<double> gd, State<R> s,
                                                const R *x, R *y, R *cb, R *psi, double *partial)
 {
-    const int p = blockIdx.y;
+    const int p = d.p0 + blockIdx.y;
     const int i0 = ulo<L>(0), j0 = ulo<L>(1), k0 = ulo<L>(2);
     // the two indices that label a line, and the along-line range
     const int nA = D == 0 ? d.nt - j0 : d.nr - i0;          // slow label
@@ -741,7 +741,7 @@ __global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<dou
     R *sm = reinterpret_cast<R *>(smem_raw);
     const int W = blockDim.x, P = blockDim.y;
     const int lane = threadIdx.x, t = threadIdx.y;
-    const int p = blockIdx.y;
+    const int p = d.p0 + blockIdx.y;
     const int i0 = ulo<L>(0), j0 = ulo<L>(1), k0 = ulo<L>(2);
     const int m0 = D == 0 ? i0 : j0;
     const int n = ncell(d, D) - m0;
@@ -872,7 +872,7 @@ __global__ void __launch_bounds__(256) k_sweep_contig(Dims d, Geo<R> g, Geo<doub
 {
     extern __shared__ unsigned char smem_raw[];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lpb = blockDim.x >> 6;
-    const int p = blockIdx.y;
+    const int p = d.p0 + blockIdx.y;
     const int i0 = ulo<L>(0), j0 = ulo<L>(1), k0 = ulo<L>(2);
     const int n = d.np - k0;
     const int ni = d.nr - i0, nj = d.nt - j0;
@@ -998,13 +998,13 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
         if (2 * P > n && n > 1) return false;
         const size_t lds = (size_t)4 * P * W * sizeof(R);
         if (M == 8)
-            hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, 8>), dim3((unsigned)b, 2), dim3(W, P),
+            hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, 8>), dim3((unsigned)b, d.npatch), dim3(W, P),
                                lds, st, d, g, gd, s, x, y, psi, partial);
         else if (M == 12)
-            hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, 12>), dim3((unsigned)b, 2), dim3(W, P),
+            hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, 12>), dim3((unsigned)b, d.npatch), dim3(W, P),
                                lds, st, d, g, gd, s, x, y, psi, partial);
         else
-            hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, 16>), dim3((unsigned)b, 2), dim3(W, P),
+            hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, 16>), dim3((unsigned)b, d.npatch), dim3(W, P),
                                lds, st, d, g, gd, s, x, y, psi, partial);
         return true;
     } else {
@@ -1029,7 +1029,7 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
         if (b > NBMAX) b = NBMAX;
         if (nblocks) *nblocks = (int)b;
         const size_t lds = per_line * lpb;
-        const dim3 grid((unsigned)b, 2), block(64 * lpb);
+        const dim3 grid((unsigned)b, d.npatch), block(64 * lpb);
         if (mc <= 8)
             hipLaunchKernelGGL((k_sweep_contig<R, L, MODE, DIFF, 8>), grid, block, lds, st, d, g, gd, s, x, y, psi, partial, P, mc);
         else if (mc <= 16)
@@ -1057,7 +1057,7 @@ static void launch_sweep(const Dims &d, const Geo<R> &g, const Geo<double> &gd, 
     int64_t b = ((int64_t)nA * nB + 255) / 256;
     if (MODE == 1 && b > NBMAX) b = NBMAX;
     if (nblocks) *nblocks = (int)b;
-    hipLaunchKernelGGL((k_sweep<R, L, D, MODE, DIFF>), dim3((unsigned)b, 2), dim3(256), 0, st, d, g,
+    hipLaunchKernelGGL((k_sweep<R, L, D, MODE, DIFF>), dim3((unsigned)b, d.npatch), dim3(256), 0, st, d, g,
                        gd, s, x, y, s.cb, psi, partial);
 }
 
@@ -1136,7 +1136,7 @@ void Ops<R>::residual(const Dims &d, const Geo<R> &g, const State<R> &s, int fie
     in.sys = sys;
     const int j0 = L == FT, k0 = L == FP;
     const int64_t n = (int64_t)(d.nt - j0) * (d.np - k0);
-    dim3 gr((unsigned)((n + 255) / 256), 2);
+    dim3 gr((unsigned)((n + 255) / 256), d.npatch);
     if (L == CC) hipLaunchKernelGGL((k_residual_col<R, CC>), gr, dim3(256), 0, st, d, g, s, in, out);
     else if (L == FR) hipLaunchKernelGGL((k_residual_col<R, FR>), gr, dim3(256), 0, st, d, g, s, in, out);
     else if (L == FT) hipLaunchKernelGGL((k_residual_col<R, FT>), gr, dim3(256), 0, st, d, g, s, in, out);
@@ -1163,7 +1163,7 @@ template <typename R>
 __global__ void __launch_bounds__(256) k_pressure(Dims d, Geo<double> gd, State<R> s, int sys,
                                                   double *pinc, double *pdiv)
 {
-    const int p = blockIdx.y;
+    const int p = d.p0 + blockIdx.y;
     const int y = sys - 1;
     const int64_t n = (int64_t)d.nr * d.nt * d.np;
     double ai = 0.0, ad = 0.0;
@@ -1201,7 +1201,7 @@ void Ops<R>::pressure(const Dims &d, const Geo<R> &g, const Geo<double> &gd, con
     int64_t b = (n + 255) / 256;
     if (b > NBMAX) b = NBMAX;
     *nb = (int)b;
-    hipLaunchKernelGGL(k_pressure<R>, dim3((unsigned)b, 2), dim3(256), 0, st, d, gd, s, sys, pinc, pdiv);
+    hipLaunchKernelGGL(k_pressure<R>, dim3((unsigned)b, d.npatch), dim3(256), 0, st, d, gd, s, sys, pinc, pdiv);
 }
 
 // ---------------------------------------------------------------------------

@@ -35,10 +35,11 @@ def yy():
 def _pair(oracle_lib, yy, nr, nt, np_, prec=0, **prm):
     o = oracle_lib.Shell(nr, nt, np_)
     g = yy.Shell(nr, nt, np_, prec=prec)
-    p = dict(pr=1.0, ra=0.0, dt=1e-3, chi=1.0, t_inner=0.0, t_outer=0.0)
+    p = dict(pr=1.0, ra=0.0, dt=1e-3, chi=1.0, t_inner=0.0, t_outer=0.0, mode=0)
     p.update(prm)
     o.set_params(pr=p["pr"], ra=p["ra"], tau=p["dt"], chi=p["chi"], t_inner=p["t_inner"],
                  t_outer=p["t_outer"])
+    o.set_mode(p["mode"])
     g.set_params(**p)
     return o, g
 
@@ -150,8 +151,8 @@ def test_residual_parity(oracle_lib, yy, field):
     assert _rel(got[m], ref[m]) <= TOL
 
 
-def _mms_pair(oracle_lib, yy, nr, nt, np_, dt, prec=0, pr=1.0, ra=1e3):
-    o, g = _pair(oracle_lib, yy, nr, nt, np_, prec=prec, pr=pr, ra=ra, dt=dt)
+def _mms_pair(oracle_lib, yy, nr, nt, np_, dt, prec=0, pr=1.0, ra=1e3, mode=0):
+    o, g = _pair(oracle_lib, yy, nr, nt, np_, prec=prec, pr=pr, ra=ra, dt=dt, mode=mode)
     grid = I.Grid(nr, nt, np_)
     s0, sm = I.mms_state(grid, 0.0), I.mms_state(grid, -dt)
     for f in range(9):
@@ -189,6 +190,19 @@ def test_step_parity_manufactured_16x24x72(oracle_lib, yy):
     for f in (I.T, I.U2R, I.U2T, I.U2P):
         assert _rel(g.get_field(f, 1).cpu().numpy(), o.get_field(f, 1)) <= TOL
     assert _rel(g.norms(), o.norms(2)) <= 1e-10
+
+
+def test_step_parity_multiplicative(oracle_lib, yy):
+    """Multiplicative Schwarz (Algorithm of Sec. 4: Yin, then Yang with
+    Yin's new values), manufactured run 12x24x72, 5 steps x K=3."""
+    print("case: multiplicative 12x24x72 x5", flush=True)
+    o, g, grid = _mms_pair(oracle_lib, yy, 12, 24, 72, 1e-3, mode=1)
+    _mms_steps(o, g, grid, 1e-3, 5, 3)
+    for f in range(9):
+        a = g.get_field(f).cpu().numpy()
+        b = o.get_field(f)
+        assert _rel(a, b) <= TOL, (I.FIELD_NAMES[f], _rel(a, b))
+    assert _rel(g.norms(), o.norms(3)) <= 1e-10
 
 
 def test_step_parity_convection(oracle_lib, yy):
