@@ -1,0 +1,120 @@
+"""GPU checks at the benchmarked sizes, in the launch configuration
+bench.py times (autotuned tiles).
+
+The 64x192x576 line-solve workload is compared element by element with the
+oracle (it finishes in seconds).  At 2x128x384x1152 the oracle cannot run a
+step in test time, so properties that hold at any size are checked: the
+discrete conductive state is steady, and identical data on the two patches
+stays bitwise identical (the Yin-Yang construction treats both alike).
+"""
+import numpy as np
+import pytest
+
+from paper_1905_02300_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def yy():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1905_02300_amd import yy as mod
+    mod.load()
+    return mod
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_line_solve_64x192x576(oracle_lib, yy, prec):
+    """(I - tau/2 Pr D) y = x along r, theta, phi on both patches, RHS
+    uniform[-1,1] (seed 2), tau = 1e-3, Pr = 1 (FP64 at 1e-12; FP32 at the
+    rounding of its inputs, 1e-5)."""
+    print(f"case: line solve 64x192x576 prec {prec}", flush=True)
+    g = I.Grid(64, 192, 576)
+    o = oracle_lib.Shell(64, 192, 576)
+    o.set_params(pr=1.0, tau=1e-3)
+    o.extrapolate()
+    s = yy.Shell(64, 192, 576, prec=prec)
+    s.set_params(pr=1.0, dt=1e-3)
+    s.autotune()
+    x = I.line_rhs(g, seed=2)
+    m = np.zeros(x.shape, bool)
+    m[:, 1:-1, 1:-1, 1:-1] = True
+    tol = 1e-12 if prec == 0 else 1e-5
+    for d in range(3):
+        ref = o.sweep(I.T, d, x)
+        yt = s.internal_tensor()
+        s.sweep_diffusion(d, s.to_internal(x), yt)
+        got = s.from_internal(yt).double().cpu().numpy()
+        err = np.max(np.abs(got[m] - ref[m])) / np.max(np.abs(ref[m]))
+        print(f"  dir {d}: relative error {err:.2e}", flush=True)
+        assert err <= tol
+
+
+def _discrete_conductive(g):
+    rf = g.r1 + np.arange(g.nr + 1) * g.dr
+    n = g.nr
+    A = np.zeros((n, n))
+    b = np.zeros(n)
+    for i in range(n):
+        am, ap = rf[i] ** 2, rf[i + 1] ** 2
+        A[i, i] = -(am + ap)
+        if i > 0:
+            A[i, i - 1] = am
+        else:
+            A[i, i] -= am
+            b[i] -= 2 * am
+        if i < n - 1:
+            A[i, i + 1] = ap
+        else:
+            A[i, i] -= ap
+    return np.linalg.solve(A, b)
+
+
+def test_conductive_state_steady_full_size(yy):
+    print("case: conductive state 128x384x1152", flush=True)
+    nr, nt, np_ = 128, 384, 1152
+    g = I.Grid(nr, nt, np_)
+    pr, ra = 1.0, 1e5
+    prof = _discrete_conductive(g)
+    T = torch.tensor(prof, dtype=torch.float64, device="cuda")[None, :, None, None].expand(2, nr, nt, np_).contiguous()
+    p = torch.zeros_like(T)
+    for i in range(1, nr):
+        p[:, i] = p[:, i - 1] + g.dr * pr * ra * 0.5 * (T[:, i - 1] + T[:, i])
+    s = yy.Shell(nr, nt, np_)
+    s.set_params(pr=pr, ra=ra, dt=2e-4, t_inner=1.0, t_outer=0.0)
+    s.autotune()
+    for f in range(9):
+        z = torch.zeros(s.mac_shape(f), dtype=torch.float64, device="cuda")
+        val = T if f == I.T else (p if f in (I.P1, I.P2) else z)
+        s.set_field(f, 0, val)
+        if f not in (I.P1, I.P2):
+            s.set_field(f, 1, val)
+    s.step(3)
+    assert float((s.get_field(I.T) - T).abs().max()) < 1e-12
+    assert float((s.get_field(I.P2) - p).abs().max()) < 1e-12 * float(p.abs().max())
+    for f in (I.U1R, I.U1T, I.U1P, I.U2R, I.U2T, I.U2P):
+        assert float(s.get_field(f).abs().max()) < 1e-9
+    nm = s.norms()
+    assert np.all(np.isfinite(nm))
+
+
+def test_patch_symmetry_full_size(yy):
+    print("case: patch symmetry 128x384x1152", flush=True)
+    nr, nt, np_ = 128, 384, 1152
+    s = yy.Shell(nr, nt, np_)
+    s.set_params(pr=1.0, ra=1e5, dt=2e-4, t_inner=1.0, t_outer=0.0)
+    s.autotune()
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    for f in range(9):
+        shape = s.mac_shape(f)
+        a = 1e-3 * torch.randn(shape[1:], dtype=torch.float64, device="cuda", generator=gen)
+        a = a[None].expand(2, *shape[1:]).contiguous()
+        s.set_field(f, 0, a)
+        if f not in (I.P1, I.P2):
+            s.set_field(f, 1, a)
+    s.step(3)
+    for f in range(9):
+        a = s.get_field(f)
+        assert torch.equal(a[0], a[1]), I.FIELD_NAMES[f]
