@@ -75,6 +75,7 @@ def main():
     ap.add_argument("--schwarz", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the line-solver tile autotuner")
+    ap.add_argument("--no-line", action="store_true", help="skip the line-solve benchmark")
     ap.add_argument("--cpu-grid", default="40,120,360")
     ap.add_argument("--ensemble", type=int, default=0,
                     help="batched ensemble of N shells (uneven sizes, seed 5), FP32-mixed, graph-captured")
@@ -148,6 +149,10 @@ def main():
         with open(tfile) as fh:
             roofline["traffic"] = json.load(fh).get("bytes_per_launch")
 
+    del sh
+    torch.cuda.empty_cache()
+    line = None if args.no_line else line_solve_bench()
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(args.cpu_grid, pr, ra, dt, K)
@@ -163,6 +168,7 @@ def main():
                    "Pr": pr, "Ra": ra, "dt": dt, "parallelism": "single-gpu"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "line_solve": line,
         "tiles": tiles,
         "kernels": kernels,
         "last_step_norms_k_last": {"div_u2": float(norms[-1, :, 9].max()),
@@ -255,6 +261,45 @@ def ensemble(args):
                       "graph_speedup_over_sequential": res["eager"]["ms_per_step"] / res["graph"]["ms_per_step"],
                       "autotune_seconds": tune_s, "tiles": tunes,
                       "shells": [list(s[:3]) + [round(s[3], 1)] for s in shapes]}), flush=True)
+
+
+def line_solve_bench(nr=64, nt=192, np_=576, reps=20, nbuf=6):
+    """The line-solve kernel alone: (I - tau/2 Pr D) y = x along r, theta,
+    phi on both patches of a 2x64x192x576 grid (D = D_rr, Dhat_thth,
+    Dhat_phph; tau = 1e-3, Pr = 1), FP64 and FP32, autotuned tiles.
+    Algorithmic bytes per sweep: x read + y written = 2 words per cell.
+    nbuf buffer pairs (> 1 GB in FP64) rotate so that the 256 MB
+    last-level cache cannot hold the working set."""
+    import torch
+    from paper_1905_02300_amd import inputs as I
+    from paper_1905_02300_amd import yy
+    g = I.Grid(nr, nt, np_)
+    x0 = I.line_rhs(g, seed=2)
+    out = {"grid": [nr, nt, np_], "cells": g.cells, "buffers": nbuf, "peak_gbs": HBM_PEAK_GBS}
+    for name, prec, wb in (("fp64", yy.YY_FP64, 8), ("fp32", yy.YY_FP32_MIXED, 4)):
+        sh = yy.Shell(nr, nt, np_, prec=prec)
+        sh.set_params(pr=1.0, dt=1e-3)
+        sh.autotune()
+        xs = [sh.to_internal(x0) for _ in range(nbuf)]
+        ys = [sh.internal_tensor() for _ in range(nbuf)]
+        res = {}
+        for d, dn in enumerate("rtp"):
+            for q in range(nbuf):
+                sh.sweep_diffusion(d, xs[q], ys[q])
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for r in range(reps):
+                sh.sweep_diffusion(d, xs[r % nbuf], ys[r % nbuf])
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            gbs = 2 * wb * g.cells / (ms * 1e-3) / 1e9
+            res[dn] = {"ms": ms, "gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
+        out[name] = res
+        del xs, ys, sh
+        torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(grid_s, pr, ra, dt, K):
