@@ -76,6 +76,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the line-solver tile autotuner")
     ap.add_argument("--no-line", action="store_true", help="skip the line-solve benchmark")
+    ap.add_argument("--line-only", action="store_true", help="run only the line-solve benchmark")
     ap.add_argument("--cpu-grid", default="40,120,360")
     ap.add_argument("--ensemble", type=int, default=0,
                     help="batched ensemble of N shells (uneven sizes, seed 5), FP32-mixed, graph-captured")
@@ -90,6 +91,9 @@ def main():
         return
     if args.ensemble:
         ensemble(args)
+        return
+    if args.line_only:
+        print(json.dumps({"metric": "line-solve HBM GB/s", "line_solve": line_solve_bench()}), flush=True)
         return
 
     import torch

@@ -98,7 +98,8 @@ template <typename R> struct State {
     R *cb;                   // Thomas scratch (c')
 };
 
-constexpr int NBMAX = 1024;      // blocks per patch of a norm-producing launch
+constexpr int NBMAX = 16384;     // partial-sum slots per patch (grid limit of norm launches)
+constexpr int SWEEP_BLOCKS = 1024;   // blocks per patch of a sweep (each loops over its tasks)
 constexpr int NSLOT = 10;        // norm slots
 
 // ---- launchers (yy_kernels.hip) ----

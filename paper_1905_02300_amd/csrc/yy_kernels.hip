@@ -993,7 +993,7 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
         const int nother = D == 0 ? d.nt - j0 : d.nr - i0;
         int64_t tasks = (int64_t)((nk + W - 1) / W) * nother;
         int64_t b = tasks;
-        if (b > NBMAX) b = NBMAX;
+        if (b > SWEEP_BLOCKS) b = SWEEP_BLOCKS;
         if (nblocks) *nblocks = (int)b;
         if (2 * P > n && n > 1) return false;
         const size_t lds = (size_t)4 * P * W * sizeof(R);
@@ -1026,7 +1026,7 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
         if ((want == 1 || want == 2 || want == 4) && want < lpb) lpb = want;
         const int64_t nlines = (int64_t)(d.nr - i0) * (d.nt - j0);
         int64_t b = (nlines + lpb - 1) / lpb;
-        if (b > NBMAX) b = NBMAX;
+        if (b > SWEEP_BLOCKS) b = SWEEP_BLOCKS;
         if (nblocks) *nblocks = (int)b;
         const size_t lds = per_line * lpb;
         const dim3 grid((unsigned)b, d.npatch), block(64 * lpb);
@@ -1055,7 +1055,7 @@ static void launch_sweep(const Dims &d, const Geo<R> &g, const Geo<double> &gd, 
     if (use_partitioned && launch_partitioned<R, L, D, MODE, DIFF>(d, g, gd, s, x, y, psi, partial, nblocks, st))
         return;
     int64_t b = ((int64_t)nA * nB + 255) / 256;
-    if (MODE == 1 && b > NBMAX) b = NBMAX;
+    if (MODE == 1 && b > SWEEP_BLOCKS) b = SWEEP_BLOCKS;
     if (nblocks) *nblocks = (int)b;
     hipLaunchKernelGGL((k_sweep<R, L, D, MODE, DIFF>), dim3((unsigned)b, d.npatch), dim3(256), 0, st, d, g,
                        gd, s, x, y, s.cb, psi, partial);
