@@ -90,7 +90,9 @@ typedef struct {
 typedef struct yy_shell yy_shell;
 
 /* Bytes of device workspace a shell needs.  prec: yy_precision.
- * Errors: YY_ERR_ARG (null, nr < 2, nt < 6, np < 6, r1 <= 0, r2 <= r1). */
+ * Errors: YY_ERR_ARG (null, nr < 2, nt < 6, np < 6, r1 <= 0, r2 <= r1, or
+ * one FP64 field -- 2 (nr+2)(nt+2) x (np+2 rounded up to 16) doubles -- of
+ * 4 GiB or more, about 2.6e8 cells per patch). */
 int yy_workspace_bytes(const yy_grid *g, int32_t prec, uint64_t *bytes);
 
 /* Create a shell on the current device inside the caller's workspace

@@ -41,9 +41,14 @@ constexpr int N_R_ARRAYS = 4 + 18 + 6 + 4 + 2;
 
 bool valid_grid(const yy_grid *g)
 {
-    return g && g->nr >= 2 && g->nt >= 6 && g->np >= 6 && g->nr <= 4096 && g->nt <= 4096 &&
-           g->np <= 8192 && g->r1 > 0.0 && g->r2 > g->r1 && std::isfinite(g->r1) &&
-           std::isfinite(g->r2);
+    if (!(g && g->nr >= 2 && g->nt >= 6 && g->np >= 6 && g->nr <= 4096 && g->nt <= 4096 &&
+          g->np <= 8192 && g->r1 > 0.0 && g->r2 > g->r1 && std::isfinite(g->r1) &&
+          std::isfinite(g->r2)))
+        return false;
+    // kernels address a field by a 32-bit byte offset: one FP64 field (both
+    // patches, ghosts and row padding) must stay below 4 GiB
+    const int64_t field = 2 * (int64_t)(g->nr + 2) * (g->nt + 2) * align_up(g->np + 2, 16) * 8;
+    return field < ((int64_t)1 << 32);
 }
 
 Layout make_layout(const yy_grid *g, int prec)
@@ -286,19 +291,19 @@ template <typename R> void host_tables(const Frame &F, const Dims &d, std::vecto
 template <typename R> void bind_geo(Geo<R> &g, const R *base, const Dims &d, const Frame &F)
 {
     g.rc = base;
-    g.rf = g.rc + (d.nr + 2);
-    g.sc = g.rf + (d.nr + 3);
-    g.cc = g.sc + (d.nt + 2);
-    g.sf = g.cc + (d.nt + 2);
-    g.cf = g.sf + (d.nt + 3);
-    const R *tr = g.cf + (d.nt + 3);
+    g.rf = base + (d.nr + 2);
+    g.sc = (const R *)g.rf + (d.nr + 3);
+    g.cc = (const R *)g.sc + (d.nt + 2);
+    g.sf = (const R *)g.cc + (d.nt + 2);
+    g.cf = (const R *)g.sf + (d.nt + 3);
+    const R *tr = (const R *)g.cf + (d.nt + 3);
     const int64_t lr = d.nr + 3, lt = d.nt + 3;
-    const R **rt[NTAB_R] = {&g.ir_c, &g.ir_f, &g.ir2_c, &g.ir2_f, &g.rc_lo, &g.rc_up,
+    CPtr<R> *rt[NTAB_R] = {&g.ir_c, &g.ir_f, &g.ir2_c, &g.ir2_f, &g.rc_lo, &g.rc_up,
                             &g.rf_lo, &g.rf_up, &g.rf_di, &g.gf_lo, &g.gf_up, &g.gf_di,
                             &g.dr_p, &g.dr_m};
     for (int q = 0; q < NTAB_R; q++) *rt[q] = tr + q * lr;
     const R *tt = tr + NTAB_R * lr;
-    const R **tp[NTAB_T] = {&g.tc_lo, &g.tc_up, &g.tf_lo, &g.tf_up, &g.ef_lo, &g.ef_up, &g.ef_di,
+    CPtr<R> *tp[NTAB_T] = {&g.tc_lo, &g.tc_up, &g.tf_lo, &g.tf_up, &g.ef_lo, &g.ef_up, &g.ef_di,
                             &g.gt_lo, &g.gt_up, &g.gt_di, &g.h2p_c, &g.h2p_f, &g.is2_c, &g.is2_f,
                             &g.cot_c, &g.dt_p, &g.dt_m, &g.dp_c, &g.cot_f, &g.is_c};
     for (int q = 0; q < NTAB_T; q++) *tp[q] = tt + q * lt;
@@ -336,7 +341,7 @@ int upload_param_tables(Geo<R> &g, const Frame &F, const Dims &d, const yy_param
     if (hipMemcpy(dev, v.data(), v.size() * sizeof(R), hipMemcpyHostToDevice) != hipSuccess) return YY_ERR_HIP;
     const R *b = (const R *)dev;
     g.fr_lo = b; g.fr_up = b + lr; g.fr_di = b + 2 * lr;
-    g.ft_lo = b + 3 * lr; g.ft_up = g.ft_lo + lt; g.ft_di = g.ft_lo + 2 * lt;
+    g.ft_lo = b + 3 * lr; g.ft_up = b + 3 * lr + lt; g.ft_di = b + 3 * lr + 2 * lt;
     return YY_OK;
 }
 

@@ -23,12 +23,27 @@ __host__ __device__ inline int64_t ix(const Dims &d, int p, int i, int j, int k)
     return (int64_t)p * d.sP + (int64_t)(i + 1) * d.sI + (int64_t)(j + 1) * d.sJ + (k + 1);
 }
 
+// Pointer to a read-only table.  Device reads go through the constant
+// address space: the tables are never written while a kernel runs, so the
+// compiler may use scalar loads where the index is wave-uniform (an r-table
+// indexed by the marching radial index) and may hoist loop-invariant reads
+// past stores to the fields.
+template <typename R> struct CPtr {
+    const R *p;
+    __host__ __device__ CPtr &operator=(const R *q) { p = q; return *this; }
+    __host__ __device__ operator const R *() const { return p; }
+    __device__ __forceinline__ R operator[](int64_t i) const
+    {
+        return ((const __attribute__((address_space(4))) R *)p)[i];
+    }
+};
+
 // metric tables and grid constants in compute precision R
 template <typename R> struct Geo {
-    const R *rc;    // r at centres, index i+1, i = -1..nr
-    const R *rf;    // r at faces, index f+1, f = -1..nr+1
-    const R *sc, *cc;   // sin, cos theta at centres, index j+1, j = -1..nt
-    const R *sf, *cf;   // sin, cos theta at faces, index f+1, f = -1..nt+1
+    CPtr<R> rc;     // r at centres, index i+1, i = -1..nr
+    CPtr<R> rf;    // r at faces, index f+1, f = -1..nr+1
+    CPtr<R> sc, cc;   // sin, cos theta at centres, index j+1, j = -1..nt
+    CPtr<R> sf, cf;   // sin, cos theta at faces, index f+1, f = -1..nt+1
     R dr, dth, dph, r1;
     R cphat;        // 1 / (R1^2 sin^2(theta_1) dphi^2), theta_1 = pi/4 - d
     R ht, tau, inv_tau;
@@ -37,25 +52,25 @@ template <typename R> struct Geo {
     // Coefficient tables of the split operators (unit viscosity, built in
     // FP64 on the host), index i+1 / f+1 / j+1 as above; they replace the
     // per-point divisions of the metric factors.
-    const R *ir_c, *ir_f, *ir2_c, *ir2_f;   // 1/r, 1/r^2 at r-centres, r-faces
-    const R *rc_lo, *rc_up;                 // D_rr at r-centres
-    const R *rf_lo, *rf_up, *rf_di;         // u_r radial viscous operator at r-faces
-    const R *gf_lo, *gf_up, *gf_di;         // D11 at r-faces
-    const R *tc_lo, *tc_up;                 // Dhat_thth at theta-centres
-    const R *tf_lo, *tf_up;                 // Dhat_thth at theta-faces
-    const R *ef_lo, *ef_up, *ef_di;         // u_theta extra viscous terms (x 1/r^2)
-    const R *gt_lo, *gt_up, *gt_di;         // D22 at theta-faces (x 1/r^2)
-    const R *h2p_c, *h2p_f;                 // 1/(2 sin(theta) dphi), centres / faces
-    const R *is2_c, *is2_f;                 // 1/sin^2(theta), centres / faces
-    const R *cot_c;                         // cot(theta) at centres
-    const R *dr_p, *dr_m;                   // Div_r at r-centre i: rf(i+1)^2, rf(i)^2 over rc^2 dr
-    const R *dt_p, *dt_m, *dp_c;            // Div_th at theta-centre j (x 1/r); 1/(sin dphi)
-    const R *cot_f, *is_c;                  // cot(theta) at faces, 1/sin(theta) at centres
+    CPtr<R> ir_c, ir_f, ir2_c, ir2_f;   // 1/r, 1/r^2 at r-centres, r-faces
+    CPtr<R> rc_lo, rc_up;                 // D_rr at r-centres
+    CPtr<R> rf_lo, rf_up, rf_di;         // u_r radial viscous operator at r-faces
+    CPtr<R> gf_lo, gf_up, gf_di;         // D11 at r-faces
+    CPtr<R> tc_lo, tc_up;                 // Dhat_thth at theta-centres
+    CPtr<R> tf_lo, tf_up;                 // Dhat_thth at theta-faces
+    CPtr<R> ef_lo, ef_up, ef_di;         // u_theta extra viscous terms (x 1/r^2)
+    CPtr<R> gt_lo, gt_up, gt_di;         // D22 at theta-faces (x 1/r^2)
+    CPtr<R> h2p_c, h2p_f;                 // 1/(2 sin(theta) dphi), centres / faces
+    CPtr<R> is2_c, is2_f;                 // 1/sin^2(theta), centres / faces
+    CPtr<R> cot_c;                         // cot(theta) at centres
+    CPtr<R> dr_p, dr_m;                   // Div_r at r-centre i: rf(i+1)^2, rf(i)^2 over rc^2 dr
+    CPtr<R> dt_p, dt_m, dp_c;            // Div_th at theta-centre j (x 1/r); 1/(sin dphi)
+    CPtr<R> cot_f, is_c;                  // cot(theta) at faces, 1/sin(theta) at centres
     R h2r, h2t, idph2;                      // 1/(2 dr), 1/(2 dtheta), 1/dphi^2
     R idr, idth, idph, r12;                 // 1/dr, 1/dtheta, 1/dphi, R1^2
     // parameter-dependent combinations (rebuilt when Pr or chi change):
     // Pr * rf_* + ic * gf_* (u_r radial operator) and Pr * ef_* + ic * gt_*
-    const R *fr_lo, *fr_up, *fr_di, *ft_lo, *ft_up, *ft_di;
+    CPtr<R> fr_lo, fr_up, fr_di, ft_lo, ft_up, ft_di;
 };
 constexpr int NTAB_R = 14;   // per-r coefficient tables (length nr+3)
 constexpr int NTAB_T = 20;   // per-theta coefficient tables (length nt+3)

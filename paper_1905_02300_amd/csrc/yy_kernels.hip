@@ -125,6 +125,41 @@ template <int L> __host__ __device__ constexpr int ulo(int dir) { return L == di
 __host__ __device__ inline int ncell(const Dims &d, int dir) { return dir == 0 ? d.nr : dir == 1 ? d.nt : d.np; }
 
 // ---------------------------------------------------------------------------
+// Field access by 32-bit element index: the byte offset is formed in 32 bits,
+// so a load is one wave-uniform 64-bit base (SGPRs) plus a 32-bit lane
+// offset, with no per-lane 64-bit address arithmetic.
+// ---------------------------------------------------------------------------
+template <typename T> struct FV {
+    const T *p;
+    __device__ __forceinline__ explicit FV(const T *q) : p(q) {}
+    __device__ __forceinline__ T operator[](uint32_t e) const
+    {
+        return *(const T *)((const char *)p + e * (uint32_t)sizeof(T));
+    }
+};
+template <typename T> __device__ __forceinline__ void st(T *b, uint32_t e, T v)
+{
+    *(T *)((char *)b + e * (uint32_t)sizeof(T)) = v;
+}
+
+// ---------------------------------------------------------------------------
+// XCD-aware block order.  Workgroups are handed to the 8 XCDs round-robin
+// in linear dispatch order, and each XCD has its own L2.  This bijection
+// gives XCD x the contiguous logical range [x*n/8, (x+1)*n/8) of the grid,
+// so that blocks which share stencil halos (neighbouring theta rows) run on
+// the same XCD and meet their neighbours' rows in its L2.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void xcd_block(unsigned &bx, unsigned &by)
+{
+    const unsigned gx = gridDim.x, n = gx * gridDim.y;
+    const unsigned b = blockIdx.x + blockIdx.y * gx;
+    const unsigned x = b & 7u, pos = b >> 3, q = n >> 3, r = n & 7u;
+    const unsigned l = (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + pos;
+    bx = l % gx;
+    by = l / gx;
+}
+
+// ---------------------------------------------------------------------------
 // block reduction of a double (blockDim.x multiple of 64, <= 1024)
 // ---------------------------------------------------------------------------
 __device__ double block_sum(double v)
@@ -377,19 +412,27 @@ template <typename R> struct Col {
 template <typename R, int L>
 __global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R> s, RhsIn<R> in, R *out)
 {
-    const int p = d.p0 + blockIdx.y;
+    unsigned bx, by;
+    xcd_block(bx, by);
+    const int p = d.p0 + (int)by;
     const int j0 = ulo<L>(1), k0 = ulo<L>(2), i0 = ulo<L>(0);
     const int nj = d.nt - j0, nk = d.np - k0;
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t t = bx * (int64_t)blockDim.x + threadIdx.x;
     if (t >= (int64_t)nj * nk) return;
     const int k = k0 + (int)(t % nk), j = j0 + (int)(t / nk);
-    const int64_t sI = d.sI, sJ = d.sJ;
+    // 32-bit element indices (each field is below 4 GiB: checked on the host)
+    const uint32_t sI = (uint32_t)d.sI, sJ = (uint32_t)d.sJ;
     const R nu = L == CC ? R(1) : g.pr;
-    const R *pn = in.pn, *pk = in.pk, *ps = in.ps;
-    const R *wr = s.us[1][0], *wt = s.us[1][1], *wp = s.us[1][2];
-    auto bar = [&](int64_t qq) { return R(0.5) * (pn[qq] + pk[qq]); };
-    auto ub0 = [&](int64_t qq) { return R(0.5) * (in.un[0][qq] + in.uk[0][qq]); };
-    int64_t q = ix(d, p, i0, j, k);
+    const FV<R> pn(in.pn), pk(in.pk), ps(in.ps), fin(in.f);
+    const FV<R> wr(s.us[1][0]), wt(s.us[1][1]), wp(s.us[1][2]);
+    const FV<R> un0(in.un[0]), uk0(in.uk[0]), un1(in.un[1]), uk1(in.uk[1]);
+    const FV<R> us1(in.us[1]), us2(in.us[2]), Tn(in.Tn), Tk(in.Tk);
+    const FV<double> psn(in.psn), p1n(in.p1n), p1k(in.p1k);
+    auto bar = [&](uint32_t qq) { return R(0.5) * (pn[qq] + pk[qq]); };
+    auto ptl = [&](uint32_t qq) {
+        return in.sys == 1 ? psn[qq] : psn[qq] + 0.5 * (p1k[qq] - p1n[qq]);
+    };
+    uint32_t q = (uint32_t)ix(d, p, i0, j, k);
     Col<R> w;
     w.bm = bar(q - sI);
     w.b0 = bar(q);
@@ -397,24 +440,24 @@ __global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R>
     if (L == FR) {
         w.a0 = wt[q - sI]; w.a1 = wt[q - sI + sJ];       // w_t at (i-1, j), (i-1, j+1)
         w.c0 = wp[q - sI]; w.c1 = wp[q - sI + 1];        // w_p at (i-1, k), (i-1, k+1)
-        w.e0 = in.us[1][q - sI]; w.e1 = in.us[1][q - sI + sJ];
-        w.f0 = in.us[2][q - sI]; w.f1 = in.us[2][q - sI + 1];
-        w.tg = (double)in.Tn[q - sI] + (double)in.Tk[q - sI];
-        w.pm = ptilde(in, q - sI);
+        w.e0 = us1[q - sI]; w.e1 = us1[q - sI + sJ];
+        w.f0 = us2[q - sI]; w.f1 = us2[q - sI + 1];
+        w.tg = (double)Tn[q - sI] + (double)Tk[q - sI];
+        w.pm = ptl(q - sI);
     } else if (L == CC) {
         w.a0 = wr[q];                                    // w_r at face i
     } else if (L == FT) {
         w.a0 = wr[q - sJ]; w.a1 = wr[q];                 // w_r at face i, (j-1) and j
-        w.c0 = in.un[0][q - sJ] + in.uk[0][q - sJ];      // 2 ubar_r at face i, j-1
-        w.c1 = in.un[0][q] + in.uk[0][q];                // 2 ubar_r at face i, j
+        w.c0 = un0[q - sJ] + uk0[q - sJ];      // 2 ubar_r at face i, j-1
+        w.c1 = un0[q] + uk0[q];                // 2 ubar_r at face i, j
     } else {
         w.a0 = wr[q - 1]; w.a1 = wr[q];                  // w_r at face i, (k-1) and k
-        w.c0 = in.un[0][q - 1] + in.uk[0][q - 1];
-        w.c1 = in.un[0][q] + in.uk[0][q];
+        w.c0 = un0[q - 1] + uk0[q - 1];
+        w.c1 = un0[q] + uk0[q];
     }
     for (int i = i0; i < d.nr; i++, q += sI) {
         w.bp = bar(q + sI);
-        R ar, at, ap, S = in.f ? in.f[q] : R(0);
+        R ar, at, ap, S = fin.p ? fin[q] : R(0);
         if (L == CC) {
             const R wr1 = wr[q + sI];
             ar = R(0.5) * (w.a0 + wr1);
@@ -426,7 +469,7 @@ __global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R>
             ar = wr[q];
             at = R(0.25) * ((w.a0 + w.a1) + (t0 + t1));
             ap = R(0.25) * ((w.c0 + w.c1) + (p0 + p1));
-            const R e0 = in.us[1][q], e1 = in.us[1][q + sJ], f0 = in.us[2][q], f1 = in.us[2][q + 1];
+            const R e0 = us1[q], e1 = us1[q + sJ], f0 = us2[q], f1 = us2[q + 1];
             // (D12 u_t* + D13 u_p*)/(2 chi)
             const R dtc = g.ir_c[i + 1] * (g.dt_p[j + 1] * e1 - g.dt_m[j + 1] * e0);
             const R dtm = g.ir_c[i] * (g.dt_p[j + 1] * w.e1 - g.dt_m[j + 1] * w.e0);
@@ -438,8 +481,8 @@ __global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R>
             S += (at * vt + ap * vp) * g.ir_f[i + 1];
             // -d_r p~ + Pr Ra T^{n+1/2}: the hydrostatic balance cancels
             // two large terms, so they are combined in FP64 before rounding
-            const double pt = ptilde(in, q);
-            const double tg = (double)in.Tn[q] + (double)in.Tk[q];
+            const double pt = ptl(q);
+            const double tg = (double)Tn[q] + (double)Tk[q];
             S += (R)(g.prra_d * 0.25 * (w.tg + tg) - (pt - w.pm) * (double)g.idr);
             w.a0 = t0; w.a1 = t1; w.c0 = p0; w.c1 = p1;
             w.e0 = e0; w.e1 = e1; w.f0 = f0; w.f1 = f1;
@@ -450,12 +493,12 @@ __global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R>
             at = wt[q];
             ap = R(0.25) * ((wp[q - sJ] + wp[q - sJ + 1]) + (wp[q] + wp[q + 1]));
             const R ir = g.ir_c[i + 1], ir2 = g.ir2_c[i + 1], cot = g.cot_f[j + 1];
-            const R u0 = in.un[0][q - sJ + sI] + in.uk[0][q - sJ + sI];    // 2 ubar_r at (i+1, j-1)
-            const R u1 = in.un[0][q + sI] + in.uk[0][q + sI];              // 2 ubar_r at (i+1, j)
+            const R u0 = un0[q - sJ + sI] + uk0[q - sJ + sI];    // 2 ubar_r at (i+1, j-1)
+            const R u1 = un0[q + sI] + uk0[q + sI];              // 2 ubar_r at (i+1, j)
             // Div_r of ubar at centres (i, j) and (i, j-1), times 2
             const R dj0 = g.dr_p[i + 1] * u1 - g.dr_m[i + 1] * w.c1;
             const R dj1 = g.dr_p[i + 1] * u0 - g.dr_m[i + 1] * w.c0;
-            const R *u2s = in.us[2];
+            const FV<R> &u2s = us2;
             const R d23 = g.ir_c[i + 1] * (g.dp_c[j + 1] * (u2s[q + 1] - u2s[q]) -
                                            g.dp_c[j] * (u2s[q - sJ + 1] - u2s[q - sJ]));
             S += g.ic * ir * g.idth * (R(0.5) * (dj0 - dj1) + d23);
@@ -466,7 +509,7 @@ __global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R>
             S += g.pr * R(2) * ir2 * (dth_ur + cot * ir * dr_r2ur);
             const R vp = R(0.25) * ((u2s[q - sJ] + u2s[q - sJ + 1]) + (u2s[q] + u2s[q + 1]));
             S += ap * vp * cot * ir;
-            S -= (R)((ptilde(in, q) - ptilde(in, q - sJ)) * (double)ir * (double)g.idth);
+            S -= (R)((ptl(q) - ptl(q - sJ)) * (double)ir * (double)g.idth);
             w.a0 = r0; w.a1 = r1; w.c0 = u0; w.c1 = u1;
         } else {
             const R r0 = wr[q - 1 + sI], r1 = wr[q + sI];
@@ -475,11 +518,11 @@ __global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R>
             ap = wp[q];
             const R ir = g.ir_c[i + 1], ir2 = g.ir2_c[i + 1], isn = g.is_c[j + 1], cot = g.cot_c[j + 1];
             const R igg = ir * g.dp_c[j + 1];
-            const R u0 = in.un[0][q - 1 + sI] + in.uk[0][q - 1 + sI];      // 2 ubar_r at (i+1, k-1)
-            const R u1 = in.un[0][q + sI] + in.uk[0][q + sI];              // 2 ubar_r at (i+1, k)
+            const R u0 = un0[q - 1 + sI] + uk0[q - 1 + sI];      // 2 ubar_r at (i+1, k-1)
+            const R u1 = un0[q + sI] + uk0[q + sI];              // 2 ubar_r at (i+1, k)
             const R a0 = g.dr_p[i + 1] * u1 - g.dr_m[i + 1] * w.c1;
             const R a1 = g.dr_p[i + 1] * u0 - g.dr_m[i + 1] * w.c0;
-            const R *tn = in.un[1], *tk = in.uk[1];
+            const FV<R> &tn = un1, &tk = uk1;
             const R th00 = tn[q] + tk[q], th01 = tn[q + sJ] + tk[q + sJ];
             const R thm0 = tn[q - 1] + tk[q - 1], thm1 = tn[q - 1 + sJ] + tk[q - 1 + sJ];
             const R b0 = ir * (g.dt_p[j + 1] * th01 - g.dt_m[j + 1] * th00);
@@ -488,7 +531,7 @@ __global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R>
             const R dph_ur = R(0.5) * ((R(0.5) * w.c1 - R(0.5) * w.c0) + (R(0.5) * u1 - R(0.5) * u0)) * g.idph;
             const R dph_ut = R(0.5) * ((R(0.5) * th00 - R(0.5) * thm0) + (R(0.5) * th01 - R(0.5) * thm1)) * g.idph;
             S += g.pr * R(2) * ir2 * isn * (dph_ur + cot * dph_ut);
-            S -= (R)((ptilde(in, q) - ptilde(in, q - 1)) * (double)igg);
+            S -= (R)((ptl(q) - ptl(q - 1)) * (double)igg);
             w.a0 = r0; w.a1 = r1; w.c0 = u0; w.c1 = u1;
         }
         const Tri<R> c0 = coef<L, 0>(g, i, j, ar, at, ap, nu);
@@ -507,7 +550,7 @@ __global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R>
         Rv += nu * ((g.r12 * ir2 - R(1)) * lt + (ir2 * is2 * g.idph2 - g.cphat) * lp);
         Rv += S;
         Rv -= (pk[q] - pn[q]) * g.inv_tau;
-        out[q] = g.tau * Rv;
+        st(out, q, g.tau * Rv);
         w.bm = w.b0;
         w.b0 = w.bp;
     }
@@ -1163,11 +1206,13 @@ template <typename R>
 __global__ void __launch_bounds__(256) k_pressure(Dims d, Geo<double> gd, State<R> s, int sys,
                                                   double *pinc, double *pdiv)
 {
-    const int p = d.p0 + blockIdx.y;
+    unsigned bx, by;
+    xcd_block(bx, by);
+    const int p = d.p0 + (int)by;
     const int y = sys - 1;
     const int64_t n = (int64_t)d.nr * d.nt * d.np;
     double ai = 0.0, ad = 0.0;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+    for (int64_t t = bx * (int64_t)blockDim.x + threadIdx.x; t < n;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int k = (int)(t % d.np);
         const int j = (int)((t / d.np) % d.nt);
@@ -1187,8 +1232,8 @@ __global__ void __launch_bounds__(256) k_pressure(Dims d, Geo<double> gd, State<
     const double ti = block_sum(ai);
     const double td = block_sum(ad);
     if (threadIdx.x == 0) {
-        pinc[p * NBMAX + blockIdx.x] = ti;
-        if (sys == 2) pdiv[p * NBMAX + blockIdx.x] = td;
+        pinc[p * NBMAX + bx] = ti;
+        if (sys == 2) pdiv[p * NBMAX + bx] = td;
     }
 }
 
@@ -1223,7 +1268,7 @@ void reduce_norms(const double *partial, const int *nblocks, double *out, hipStr
 {
     NB nb;
     for (int q = 0; q < NSLOT; q++) nb.n[q] = nblocks[q];
-    hipLaunchKernelGGL(k_reduce, dim3(2 * NSLOT), dim3(256), 0, st, partial, nb, out);
+    hipLaunchKernelGGL(k_reduce, dim3(2 * NSLOT), dim3(1024), 0, st, partial, nb, out);
 }
 
 __global__ void k_zero(double *p, int64_t n)

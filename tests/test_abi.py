@@ -48,6 +48,16 @@ def test_workspace_bytes_and_argument_errors(lib):
         yy.workspace_bytes(16, 24, 72, prec=7)
 
 
+def test_field_size_limit(lib):
+    # one FP64 field (2 patches, ghosts, rows padded to 16) must stay below
+    # 4 GiB, since kernels address fields by 32-bit byte offsets
+    assert yy.workspace_bytes(128, 384, 1152) > 0
+    assert yy.workspace_bytes(254, 766, 1342) > 0        # 2*256*768*1344*8 < 2^32
+    with pytest.raises(yy.YYError) as e:
+        yy.workspace_bytes(256, 768, 1360)               # 2*258*770*1376*8 > 2^32
+    assert e.value.status == yy.YY_ERR_ARG
+
+
 def _create(lib, g, ptr, nbytes):
     h = ctypes.c_void_p()
     st = lib.yy_create(ctypes.byref(g), 0, ctypes.c_void_p(ptr), nbytes, ctypes.byref(h))
