@@ -53,6 +53,9 @@ def class_words():
     for d, name in enumerate("rtp"):
         W["sweep_" + name] = (float(np.mean(sw[d])), 0.0)
         W["sweep_" + name + "_last"] = (float(np.mean(swl[d])), 0.0)
+    # the last phi sweep is timed apart for u_phi (sweep_p_last) and T
+    W["sweep_p_last"] = (3.0 + _ADV[("p", 2)], 0.0)
+    W["sweep_p_last_T"] = (3.0 + _ADV[("c", 2)], 0.0)
     # residuals: own levels n, k, *, u2* (3), write 1 (+ sources)
     W["residual_T"] = (7.0, 0.0)                          # Tn Tk T* w3 out
     W["residual_ur"] = (0.5 * (11 + 8), 0.5 * (1 + 3))    # s=1 / s=2 distinct arrays

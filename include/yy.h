@@ -224,7 +224,7 @@ int yy_ensemble_destroy(yy_ensemble *e);
 /* ---- live per-kernel timing (HIP events on the caller's stream) ---- */
 
 /* Kernel classes timed by the profiler. */
-#define YY_NPROF 16
+#define YY_NPROF 17
 
 /* enable != 0: start recording a hipEvent pair around every kernel launch
  * group of later calls (previous records are dropped); 0: stop. */

@@ -12,6 +12,24 @@ namespace yy {
 template <typename R> struct Tri { R lo, di, up; };
 
 // ---------------------------------------------------------------------------
+// Field access by 32-bit element index: the byte offset is formed in 32 bits,
+// so a load is one wave-uniform 64-bit base (SGPRs) plus a 32-bit lane
+// offset, with no per-lane 64-bit address arithmetic.
+// ---------------------------------------------------------------------------
+template <typename T> struct FV {
+    const T *p;
+    __device__ __forceinline__ explicit FV(const T *q) : p(q) {}
+    __device__ __forceinline__ T operator[](uint32_t e) const
+    {
+        return *(const T *)((const char *)p + e * (uint32_t)sizeof(T));
+    }
+};
+template <typename T> __device__ __forceinline__ void st(T *b, uint32_t e, T v)
+{
+    *(T *)((char *)b + e * (uint32_t)sizeof(T)) = v;
+}
+
+// ---------------------------------------------------------------------------
 // MAC averaging: component C (0 = r, 1 = theta, 2 = phi; stored on its own
 // faces) at location L of the point with storage index q.  Faces f, f+1 are
 // averaged where L is centred, centres f-1, f where L is a face.
@@ -125,24 +143,6 @@ template <int L> __host__ __device__ constexpr int ulo(int dir) { return L == di
 __host__ __device__ inline int ncell(const Dims &d, int dir) { return dir == 0 ? d.nr : dir == 1 ? d.nt : d.np; }
 
 // ---------------------------------------------------------------------------
-// Field access by 32-bit element index: the byte offset is formed in 32 bits,
-// so a load is one wave-uniform 64-bit base (SGPRs) plus a 32-bit lane
-// offset, with no per-lane 64-bit address arithmetic.
-// ---------------------------------------------------------------------------
-template <typename T> struct FV {
-    const T *p;
-    __device__ __forceinline__ explicit FV(const T *q) : p(q) {}
-    __device__ __forceinline__ T operator[](uint32_t e) const
-    {
-        return *(const T *)((const char *)p + e * (uint32_t)sizeof(T));
-    }
-};
-template <typename T> __device__ __forceinline__ void st(T *b, uint32_t e, T v)
-{
-    *(T *)((char *)b + e * (uint32_t)sizeof(T)) = v;
-}
-
-// ---------------------------------------------------------------------------
 // XCD-aware block order.  Workgroups are handed to the 8 XCDs round-robin
 // in linear dispatch order, and each XCD has its own L2.  This bijection
 // gives XCD x the contiguous logical range [x*n/8, (x+1)*n/8) of the grid,
@@ -159,19 +159,44 @@ __device__ __forceinline__ void xcd_block(unsigned &bx, unsigned &by)
     by = l / gx;
 }
 
+// Column kernels: a block of (COL_K, COL_J) threads owns a COL_K x COL_J tile
+// of (k, j) columns, so the theta neighbours j-1, j+1 of most columns are read
+// by waves of the same block.  (Holding the waves at one radial level with a
+// barrier per level cuts the re-fetched halo rows by a quarter but costs more
+// time than it saves, so the waves run free.)
+constexpr int COL_K = 64, COL_J = 4;
+
+// tile of block (bx) over nj x nk columns starting at (j0, k0); false if the
+// thread's column is outside
+__device__ __forceinline__ bool col_of(unsigned bx, int nj, int nk, int j0, int k0, int &j, int &k)
+{
+    const int ntk = (nk + COL_K - 1) / COL_K;
+    const int tk = (int)(bx % (unsigned)ntk), tj = (int)(bx / (unsigned)ntk);
+    k = k0 + tk * COL_K + (int)threadIdx.x;
+    j = j0 + tj * COL_J + (int)threadIdx.y;
+    return (k - k0) < nk && (j - j0) < nj;
+}
+__host__ __device__ inline int64_t col_blocks(int nj, int nk)
+{
+    return (int64_t)((nk + COL_K - 1) / COL_K) * ((nj + COL_J - 1) / COL_J);
+}
+
 // ---------------------------------------------------------------------------
-// block reduction of a double (blockDim.x multiple of 64, <= 1024)
+// block reduction of a double (blockDim.x * blockDim.y a multiple of 64,
+// <= 1024, blockDim.x a multiple of 64 or blockDim.y == 1); the sum is
+// returned on the block's first thread
 // ---------------------------------------------------------------------------
 __device__ double block_sum(double v)
 {
     __shared__ double red[16];
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int f = threadIdx.x + blockDim.x * threadIdx.y;
+    const int w = f >> 6, l = f & 63;
     if (l == 0) red[w] = v;
     __syncthreads();
     double t = 0.0;
-    if (threadIdx.x == 0) {
-        const int nw = blockDim.x >> 6;
+    if (f == 0) {
+        const int nw = (blockDim.x * blockDim.y) >> 6;
         for (int q = 0; q < nw; q++) t += red[q];
     }
     __syncthreads();
@@ -417,9 +442,8 @@ __global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R>
     const int p = d.p0 + (int)by;
     const int j0 = ulo<L>(1), k0 = ulo<L>(2), i0 = ulo<L>(0);
     const int nj = d.nt - j0, nk = d.np - k0;
-    const int64_t t = bx * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= (int64_t)nj * nk) return;
-    const int k = k0 + (int)(t % nk), j = j0 + (int)(t / nk);
+    int j, k;
+    if (!col_of(bx, nj, nk, j0, k0, j, k)) return;
     // 32-bit element indices (each field is below 4 GiB: checked on the host)
     const uint32_t sI = (uint32_t)d.sI, sJ = (uint32_t)d.sJ;
     const R nu = L == CC ? R(1) : g.pr;
@@ -1178,12 +1202,11 @@ void Ops<R>::residual(const Dims &d, const Geo<R> &g, const State<R> &s, int fie
     in.p1k = s.p[0][1];
     in.sys = sys;
     const int j0 = L == FT, k0 = L == FP;
-    const int64_t n = (int64_t)(d.nt - j0) * (d.np - k0);
-    dim3 gr((unsigned)((n + 255) / 256), d.npatch);
-    if (L == CC) hipLaunchKernelGGL((k_residual_col<R, CC>), gr, dim3(256), 0, st, d, g, s, in, out);
-    else if (L == FR) hipLaunchKernelGGL((k_residual_col<R, FR>), gr, dim3(256), 0, st, d, g, s, in, out);
-    else if (L == FT) hipLaunchKernelGGL((k_residual_col<R, FT>), gr, dim3(256), 0, st, d, g, s, in, out);
-    else hipLaunchKernelGGL((k_residual_col<R, FP>), gr, dim3(256), 0, st, d, g, s, in, out);
+    const dim3 gr((unsigned)col_blocks(d.nt - j0, d.np - k0), d.npatch), bl(COL_K, COL_J);
+    if (L == CC) hipLaunchKernelGGL((k_residual_col<R, CC>), gr, bl, 0, st, d, g, s, in, out);
+    else if (L == FR) hipLaunchKernelGGL((k_residual_col<R, FR>), gr, bl, 0, st, d, g, s, in, out);
+    else if (L == FT) hipLaunchKernelGGL((k_residual_col<R, FT>), gr, bl, 0, st, d, g, s, in, out);
+    else hipLaunchKernelGGL((k_residual_col<R, FP>), gr, bl, 0, st, d, g, s, in, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1192,16 +1215,8 @@ void Ops<R>::residual(const Dims &d, const Geo<R> &g, const State<R> &s, int fie
 //   p2^k = p2^n + (p1^k - p1^n) - Div_h u2^{n+1/2}/chi,
 // with the l2 norms of the increment and (system 2) of Div_h u2^k.
 // ---------------------------------------------------------------------------
-template <typename R>
-__device__ __forceinline__ double div_h(const Geo<double> &gd, const R *ur, const R *ut, const R *up,
-                                        int64_t q, const Dims &d, int i, int j)
-{
-    const double a = gd.dr_p[i + 1] * (double)ur[q + d.sI] - gd.dr_m[i + 1] * (double)ur[q];
-    const double b = gd.dt_p[j + 1] * (double)ut[q + d.sJ] - gd.dt_m[j + 1] * (double)ut[q];
-    const double c = gd.dp_c[j + 1] * ((double)up[q + 1] - (double)up[q]);
-    return a + gd.ir_c[i + 1] * (b + c);
-}
-
+// Column-marching form: a thread owns one (patch, j, k) column and walks i
+// upwards; the radial face value at i+1 is reused at the next i.
 template <typename R>
 __global__ void __launch_bounds__(256) k_pressure(Dims d, Geo<double> gd, State<R> s, int sys,
                                                   double *pinc, double *pdiv)
@@ -1210,28 +1225,44 @@ __global__ void __launch_bounds__(256) k_pressure(Dims d, Geo<double> gd, State<
     xcd_block(bx, by);
     const int p = d.p0 + (int)by;
     const int y = sys - 1;
-    const int64_t n = (int64_t)d.nr * d.nt * d.np;
     double ai = 0.0, ad = 0.0;
-    for (int64_t t = bx * (int64_t)blockDim.x + threadIdx.x; t < n;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int k = (int)(t % d.np);
-        const int j = (int)((t / d.np) % d.nt);
-        const int i = (int)(t / ((int64_t)d.np * d.nt));
-        const int64_t q = ix(d, p, i, j, k);
-        const double dn = div_h(gd, s.u[y][0][0], s.u[y][1][0], s.u[y][2][0], q, d, i, j);
-        const double dk = div_h(gd, s.u[y][0][2], s.u[y][1][2], s.u[y][2][2], q, d, i, j);
-        double nv = s.p[y][0][q] - 0.5 * (dn + dk) * gd.inv_chi;
-        if (sys == 2) nv += s.p[0][1][q] - s.p[0][0][q];
-        const double inc = nv - s.p[y][1][q];
-        s.p[y][1][q] = nv;
-        const double rc = gd.rc[i + 1];
-        const double w = rc * rc * gd.sc[j + 1] * gd.dr * gd.dth * gd.dph;
-        ai += w * inc * inc;
-        if (sys == 2) ad += w * dk * dk;
+    const unsigned ntile = (unsigned)col_blocks(d.nt, d.np);
+    for (unsigned tile = bx; tile < ntile; tile += gridDim.x) {
+        int j, k;
+        if (!col_of(tile, d.nt, d.np, 0, 0, j, k)) continue;
+        const uint32_t sI = (uint32_t)d.sI, sJ = (uint32_t)d.sJ;
+        const FV<R> rn(s.u[y][0][0]), tn(s.u[y][1][0]), pn(s.u[y][2][0]);
+        const FV<R> rk(s.u[y][0][2]), tk(s.u[y][1][2]), pk(s.u[y][2][2]);
+        const FV<double> pyn(s.p[y][0]), pyk(s.p[y][1]), p1n(s.p[0][0]), p1k(s.p[0][1]);
+        const double dtp = gd.dt_p[j + 1], dtm = gd.dt_m[j + 1], dpc = gd.dp_c[j + 1];
+        const double wj = gd.sc[j + 1] * gd.dr * gd.dth * gd.dph;
+        uint32_t q = (uint32_t)ix(d, p, 0, j, k);
+        double rn0 = (double)rn[q], rk0 = (double)rk[q];
+        for (int i = 0; i < d.nr; i++, q += sI) {
+            // Div_h of u^n and u^k at the centre (i, j, k)
+            const double rn1 = (double)rn[q + sI], rk1 = (double)rk[q + sI];
+            const double drp = gd.dr_p[i + 1], drm = gd.dr_m[i + 1], ir = gd.ir_c[i + 1];
+            const double dn = (drp * rn1 - drm * rn0) +
+                              ir * ((dtp * (double)tn[q + sJ] - dtm * (double)tn[q]) +
+                                    dpc * ((double)pn[q + 1] - (double)pn[q]));
+            const double dk = (drp * rk1 - drm * rk0) +
+                              ir * ((dtp * (double)tk[q + sJ] - dtm * (double)tk[q]) +
+                                    dpc * ((double)pk[q + 1] - (double)pk[q]));
+            rn0 = rn1;
+            rk0 = rk1;
+            double nv = pyn[q] - 0.5 * (dn + dk) * gd.inv_chi;
+            if (sys == 2) nv += p1k[q] - p1n[q];
+            const double inc = nv - pyk[q];
+            st(s.p[y][1], q, nv);
+            const double rc = gd.rc[i + 1];
+            const double w = rc * rc * wj;
+            ai += w * inc * inc;
+            if (sys == 2) ad += w * dk * dk;
+        }
     }
     const double ti = block_sum(ai);
     const double td = block_sum(ad);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
         pinc[p * NBMAX + bx] = ti;
         if (sys == 2) pdiv[p * NBMAX + bx] = td;
     }
@@ -1242,11 +1273,11 @@ void Ops<R>::pressure(const Dims &d, const Geo<R> &g, const Geo<double> &gd, con
                       int sys, double *pinc, double *pdiv, int *nb, hipStream_t st)
 {
     (void)g;
-    const int64_t n = (int64_t)d.nr * d.nt * d.np;
-    int64_t b = (n + 255) / 256;
-    if (b > NBMAX) b = NBMAX;
+    int64_t b = col_blocks(d.nt, d.np);        // one thread per (j, k) column
+    if (b > NBMAX) b = NBMAX;                   // then blocks loop over tiles
     *nb = (int)b;
-    hipLaunchKernelGGL(k_pressure<R>, dim3((unsigned)b, d.npatch), dim3(256), 0, st, d, gd, s, sys, pinc, pdiv);
+    hipLaunchKernelGGL(k_pressure<R>, dim3((unsigned)b, d.npatch), dim3(COL_K, COL_J), 0, st, d, gd, s, sys,
+                       pinc, pdiv);
 }
 
 // ---------------------------------------------------------------------------

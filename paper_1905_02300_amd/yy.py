@@ -26,7 +26,7 @@ EXPORTS = ["yy_workspace_bytes", "yy_create", "yy_set_params", "yy_set_field", "
            "yy_residual", "yy_profile", "yy_profile_read", "yy_profile_name",
            "yy_ensemble_workspace_bytes", "yy_ensemble_create", "yy_ensemble_shell",
            "yy_ensemble_step", "yy_ensemble_destroy", "yy_autotune", "yy_set_tuning"]
-NPROF = 16
+NPROF = 17
 
 
 class YYError(RuntimeError):
