@@ -1029,9 +1029,22 @@ static void solve_all(yyo *h, int p0, int p1, int kk)
 }
 
 /* One time step n -> n+1 with K Schwarz iterations. */
-int yyo_step(yyo *h, int K)
+/* largest increment norm of iteration kk over the computed quantities
+ * (T, u1, p1, u2, p2) and both patches; the divergence slot is not one */
+static double max_increment(const yyo *h, int kk)
 {
-    if (!h || K < 1) return -1;
+    double m = 0.0;
+    for (int p = 0; p < 2; p++)
+        for (int q = 0; q < 9; q++)
+            if (h->norms[kk][p][q] > m || h->norms[kk][p][q] != h->norms[kk][p][q]) m = h->norms[kk][p][q];
+    return m;
+}
+
+/* One time step.  tol < 0: exactly K Schwarz iterations.  tol >= 0: stop
+ * after the first iteration whose increments are all below tol (the stop
+ * test of the numerical-tests section), at most K.  Returns the count. */
+static int step_run(yyo *h, int K, double tol)
+{
     size_t bytes = sizeof(double) * 2 * (size_t)h->npatch;
     if (!h->filled) {
         yyo_fill(h, YYO_LEV_N);
@@ -1041,6 +1054,7 @@ int yyo_step(yyo *h, int K)
     yyo_extrapolate(h);
     for (int f = 0; f < YYO_NF; f++) memcpy(h->lev[f][YYO_LEV_K], h->lev[f][YYO_LEV_N], bytes);
     memset(h->norms, 0, sizeof(h->norms));
+    int done = 0;
     for (int kk = 0; kk < K; kk++) {
         if (h->mode == 0) {
             yyo_fill(h, YYO_LEV_K);
@@ -1051,14 +1065,29 @@ int yyo_step(yyo *h, int K)
                 solve_all(h, p, p + 1, kk);
             }
         }
+        done = kk + 1;
+        if (tol >= 0.0 && kk < MAXK && max_increment(h, kk) < tol) break;
     }
-    h->nk = K < MAXK ? K : MAXK;
+    h->nk = done < MAXK ? done : MAXK;
     yyo_fill(h, YYO_LEV_K);
     for (int f = 0; f < YYO_NF; f++) {
         memcpy(h->lev[f][YYO_LEV_NM1], h->lev[f][YYO_LEV_N], bytes);
         memcpy(h->lev[f][YYO_LEV_N], h->lev[f][YYO_LEV_K], bytes);
     }
+    return done;
+}
+
+int yyo_step(yyo *h, int K)
+{
+    if (!h || K < 1) return -1;
+    step_run(h, K, -1.0);
     return 0;
+}
+
+int yyo_step_tol(yyo *h, int kmax, double tol)
+{
+    if (!h || kmax < 1 || kmax > MAXK || !(tol >= 0.0)) return -1;
+    return step_run(h, kmax, tol);
 }
 
 int yyo_get_norms(const yyo *h, double *out, int cap)

@@ -54,6 +54,10 @@ int yyo_get_field(const yyo *h, int field, int level, int layout, double *dst);
 int yyo_set_forcing(yyo *h, int field, const double *src);
 /* Advance one time step with K Schwarz iterations. */
 int yyo_step(yyo *h, int K);
+/* Advance one time step, iterating until every increment norm of an
+ * iteration (T, u1, p1, u2, p2, both patches) is below tol, at most kmax
+ * (<= 64) iterations.  Returns the iteration count, or -1 on bad input. */
+int yyo_step_tol(yyo *h, int kmax, double tol);
 /* norms of the last step: out[k][patch][10] = per-field l2 norms of the
  * iterate increment (T,u1r,u1t,u1p,p1,u2r,u2t,u2p,p2) and of Div_h u2^k */
 int yyo_get_norms(const yyo *h, double *out, int cap);

@@ -39,6 +39,7 @@ def lib():
         L.yyo_get_field.argtypes = [vp, i, i, i, dp]
         L.yyo_set_forcing.argtypes = [vp, i, dp]
         L.yyo_step.argtypes = [vp, i]
+        L.yyo_step_tol.argtypes = [vp, i, d]
         L.yyo_get_norms.argtypes = [vp, dp, i]
         L.yyo_fill.argtypes = [vp, i]
         L.yyo_sweep.argtypes = [vp, i, i, dp, dp]
@@ -145,6 +146,14 @@ class Shell:
     def step(self, K):
         if lib().yyo_step(self.h, K) != 0:
             raise RuntimeError("step failed")
+
+    def step_tol(self, kmax, tol):
+        """one step, Schwarz iterations until every increment norm < tol
+        (at most kmax); returns the iteration count"""
+        k = lib().yyo_step_tol(self.h, kmax, tol)
+        if k < 1:
+            raise RuntimeError("step_tol failed")
+        return k
 
     def norms(self, K):
         out = np.zeros(K * 2 * 10)

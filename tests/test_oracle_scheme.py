@@ -112,6 +112,8 @@ def test_conductive_state_is_steady(oracle_lib, mode):
         sh.set_field(f, y.LEV_NM1, st[f])
     for _ in range(3):
         sh.step(2)
+    # a steady state converges in one Schwarz iteration of the tolerance loop
+    assert sh.step_tol(10, 1e-9) == 1
     assert np.max(np.abs(sh.get_field(I.T) - T)) < 1e-12
     assert np.max(np.abs(sh.get_field(I.P2) - p)) < 1e-12 * np.max(np.abs(p))
     for f in (I.U1R, I.U1T, I.U1P, I.U2R, I.U2T, I.U2P):
@@ -170,6 +172,42 @@ def test_walls_and_schwarz_contraction(oracle_lib):
             seq = nm[:, p, q]
             assert np.all(seq[1:] < seq[:-1]), (q, seq)
         assert nm[-1, :, q].max() < 0.1 * nm[0, :, q].max()
+
+
+def test_tolerance_loop_stops_at_first_converged_iteration(oracle_lib):
+    """The tolerance-driven Schwarz loop (numerical-tests section: iterate
+    until the l2 difference of two successive iterates of every computed
+    quantity is below the tolerance) stops at the first iteration whose
+    increments, as a fixed-K run of the same step reports them, are all
+    below tol, and leaves exactly the state of that fixed-K run."""
+    y = oracle_lib
+    g = I.Grid(6, 12, 36)
+    tau, pr, ra = 0.02, 1.0, 10.0
+
+    def fresh():
+        sh = _mms_shell(y, g, tau, pr, ra)
+        for f in (I.T, I.U1R, I.U1T, I.U1P):
+            sh.set_forcing(f, I.mms_forcing(g, 0.5 * tau, f, pr, ra))
+        return sh
+
+    ref = fresh()
+    ref.step(8)
+    mx = ref.norms(8)[:, :, :9].max(axis=(1, 2))      # per iteration; slot 9 is div u2
+    assert np.all(mx[1:] < mx[:-1])
+    for j in (1, 3):
+        tol = math.sqrt(mx[j - 1] * mx[j])               # between iterations j and j+1
+        sh = fresh()
+        k = sh.step_tol(8, tol)
+        assert k == j + 1, (k, j, mx)
+        fixed = fresh()
+        fixed.step(k)
+        for f in range(9):
+            assert np.array_equal(sh.get_field(f), fixed.get_field(f)), I.FIELD_NAMES[f]
+        assert np.array_equal(sh.norms(k), fixed.norms(k))
+    # tolerance 0 is never met: kmax iterations
+    assert fresh().step_tol(5, 0.0) == 5
+    with pytest.raises(RuntimeError):
+        fresh().step_tol(0, 1e-3)
 
 
 def test_divergence_decays(oracle_lib):
