@@ -133,6 +133,19 @@ int yy_set_forcing(yy_shell *s, int32_t field, const double *dev_src, hipStream_
  * (params not set), YY_ERR_HIP. */
 int yy_step(yy_shell *s, int32_t n_schwarz, hipStream_t stream);
 
+/* One time step with the paper's tolerance-driven Schwarz loop (Sec. 5.1:
+ * iterate until the l2 norm of the difference of two successive iterates
+ * of every computed quantity is below a tolerance).  After each iteration
+ * the increment norms of T, u1, p1, u2, p2 on both patches come to the
+ * host (the stream is synchronised once per iteration); the loop stops at
+ * the first iteration whose norms are all below tol, or after kmax.
+ * *k_done receives the number of iterations run; yy_get_norms returns
+ * their norms.  Not for use under stream capture.
+ * Errors: YY_ERR_ARG (null, kmax < 1 or > 64, tol < 0 or not finite),
+ * YY_ERR_STATE, YY_ERR_NONFINITE (a norm is NaN/Inf: the step is abandoned
+ * and the handle keeps the error), YY_ERR_HIP. */
+int yy_step_tol(yy_shell *s, int32_t kmax, double tol, int32_t *k_done, hipStream_t stream);
+
 /* Norms of the last step, synchronising the stream: out[k][patch][slot]
  * for k < n_schwarz, slot order T,u1r,u1t,u1p,p1,u2r,u2t,u2p,p2,div(u2).
  * Returns the number of values available (it writes at most cap), or

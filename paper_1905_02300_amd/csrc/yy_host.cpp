@@ -498,7 +498,12 @@ template <typename R> void solve_field(yy_shell *s, const Dims &d, int f, hipStr
 
 template <typename R> void rotate_levels(yy_shell *s);
 
-template <typename R> int step_impl(yy_shell *s, int K, hipStream_t st)
+// one time step: extrapolation, Schwarz iterations, post-step fill, level
+// rotation.  tol < 0: exactly K iterations.  tol >= 0: after each iteration
+// the increment norms come to the host (a stream synchronisation) and the
+// loop stops at the first iteration whose increments of every computed
+// quantity (T, u1, p1, u2, p2; both patches) are below tol, at most K.
+template <typename R> int step_impl(yy_shell *s, int K, double tol, int *k_done, hipStream_t st)
 {
     State<R> &S = state_of<R>(s);
     if (s->need_fill) {
@@ -514,6 +519,7 @@ template <typename R> int step_impl(yy_shell *s, int K, hipStream_t st)
         Timed tm(s, PC_COPY, st);
         Ops<R>::copy_levels(s->L.d, S, 0, 2, st);
     }
+    int done = 0;
     for (int k = 0; k < K; k++) {
         // additive: both patches at once from the other's iterate k-1;
         // multiplicative (Algorithm of Sec. 4): Yin, then Yang from Yin's k
@@ -546,12 +552,34 @@ template <typename R> int step_impl(yy_shell *s, int K, hipStream_t st)
             }
         }
         s->nblocks[9] = s->nblocks[YY_P2];
-        Timed tm(s, PC_REDUCE, st);
-        reduce_norms(s->partial, s->nblocks, s->norms + (int64_t)k * 2 * NSLOT, st);
+        {
+            Timed tm(s, PC_REDUCE, st);
+            reduce_norms(s->partial, s->nblocks, s->norms + (int64_t)k * 2 * NSLOT, st);
+        }
+        done = k + 1;
+        if (tol >= 0.0) {
+            double h[2 * NSLOT];
+            hipError_t e = hipMemcpyAsync(h, s->norms + (int64_t)k * 2 * NSLOT, sizeof h,
+                                          hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return YY_ERR_HIP;
+            double m = 0.0;
+            for (int p = 0; p < 2; p++)
+                for (int q = 0; q < NSLOT - 1; q++) {
+                    const double v = h[p * NSLOT + q];
+                    if (!std::isfinite(v)) {
+                        s->sticky = YY_ERR_NONFINITE;
+                        return YY_ERR_NONFINITE;
+                    }
+                    m = std::max(m, v);
+                }
+            if (m < tol) break;
+        }
     }
     do_fill<R>(s, 2, 3, st);
     rotate_levels<R>(s);
-    s->last_k = K;
+    s->last_k = done;
+    if (k_done) *k_done = done;
     return hip_status(hipGetLastError());
 }
 
@@ -759,7 +787,21 @@ int yy_step(yy_shell *s, int32_t K, hipStream_t st)
     if (!s || K < 1 || K > MAXK) return YY_ERR_ARG;
     if (!s->have_params) return YY_ERR_STATE;
     if (s->sticky != YY_OK) return s->sticky;
-    return s->L.prec == YY_FP64 ? step_impl<double>(s, K, st) : step_impl<float>(s, K, st);
+    return s->L.prec == YY_FP64 ? step_impl<double>(s, K, -1.0, nullptr, st)
+                                : step_impl<float>(s, K, -1.0, nullptr, st);
+}
+
+int yy_step_tol(yy_shell *s, int32_t kmax, double tol, int32_t *k_done, hipStream_t st)
+{
+    if (!s || !k_done || kmax < 1 || kmax > MAXK || !(tol >= 0.0) || !std::isfinite(tol)) return YY_ERR_ARG;
+    *k_done = 0;
+    if (!s->have_params) return YY_ERR_STATE;
+    if (s->sticky != YY_OK) return s->sticky;
+    int k = 0;
+    const int r = s->L.prec == YY_FP64 ? step_impl<double>(s, kmax, tol, &k, st)
+                                       : step_impl<float>(s, kmax, tol, &k, st);
+    *k_done = k;
+    return r;
 }
 
 int yy_get_norms(yy_shell *s, double *out, int32_t cap, hipStream_t st)
@@ -1055,7 +1097,7 @@ int shell_step(yy_shell *s, int K, hipStream_t st)
 {
     if (!s->have_params) return YY_ERR_STATE;
     if (s->sticky != YY_OK) return s->sticky;
-    return s->L.prec == YY_FP64 ? step_impl<double>(s, K, st) : step_impl<float>(s, K, st);
+    return s->L.prec == YY_FP64 ? step_impl<double>(s, K, -1.0, nullptr, st) : step_impl<float>(s, K, -1.0, nullptr, st);
 }
 
 void shell_rotate(yy_shell *s)

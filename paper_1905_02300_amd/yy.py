@@ -25,7 +25,7 @@ EXPORTS = ["yy_workspace_bytes", "yy_create", "yy_set_params", "yy_set_field", "
            "yy_internal_dims", "yy_fill", "yy_extrapolate", "yy_sweep", "yy_sweep_diffusion",
            "yy_residual", "yy_profile", "yy_profile_read", "yy_profile_name",
            "yy_ensemble_workspace_bytes", "yy_ensemble_create", "yy_ensemble_shell",
-           "yy_ensemble_step", "yy_ensemble_destroy", "yy_autotune", "yy_set_tuning"]
+           "yy_ensemble_step", "yy_ensemble_destroy", "yy_autotune", "yy_set_tuning", "yy_step_tol"]
 NPROF = 17
 
 
@@ -66,6 +66,7 @@ def load():
     L.yy_get_field.argtypes = [vp, i32, i32, i32, vp, vp]
     L.yy_set_forcing.argtypes = [vp, i32, vp, vp]
     L.yy_step.argtypes = [vp, i32, vp]
+    L.yy_step_tol.argtypes = [vp, i32, ctypes.c_double, P(i32), vp]
     L.yy_get_norms.argtypes = [vp, P(ctypes.c_double), i32, vp]
     L.yy_destroy.argtypes = [vp]
     L.yy_strerror.argtypes = [ctypes.c_int]
@@ -215,6 +216,15 @@ class Shell:
     def step(self, K, stream=None):
         _check(load().yy_step(self.h, K, _stream_ptr(stream)), "yy_step")
         self.K = K
+
+    def step_tol(self, kmax, tol, stream=None):
+        """one step, Schwarz iterations until every increment norm < tol
+        (at most kmax); returns the iteration count"""
+        k = ctypes.c_int32(0)
+        _check(load().yy_step_tol(self.h, kmax, ctypes.c_double(tol), ctypes.byref(k),
+                                  _stream_ptr(stream)), "yy_step_tol")
+        self.K = k.value
+        return k.value
 
     def norms(self, stream=None):
         n = max(self.K, 1) * 2 * NNORMS

@@ -81,6 +81,8 @@ def test_create_rejects_before_touching_the_device(lib):
 
 def test_null_handle_errors(lib):
     assert lib.yy_step(None, 2, None) == yy.YY_ERR_ARG
+    k = ctypes.c_int32(-1)
+    assert lib.yy_step_tol(None, 4, ctypes.c_double(1e-6), ctypes.byref(k), None) == yy.YY_ERR_ARG
     assert lib.yy_set_params(None, None) == yy.YY_ERR_ARG
     assert lib.yy_destroy(None) == yy.YY_ERR_ARG
     assert lib.yy_strerror(yy.YY_ERR_GEOMETRY).decode().startswith("overlap")

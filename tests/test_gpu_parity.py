@@ -205,6 +205,32 @@ def test_step_parity_multiplicative(oracle_lib, yy):
     assert _rel(g.norms(), o.norms(3)) <= 1e-10
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_step_tol_parity(oracle_lib, yy, mode):
+    """Tolerance-driven Schwarz loop (stop when every increment norm of an
+    iteration is below tol): the GPU takes the same iteration counts as the
+    oracle and matches its fields; manufactured run 12x24x72, 4 steps."""
+    print("case: step_tol mode %d 12x24x72 x4" % mode, flush=True)
+    dt, tol = 2e-3, 3e-7
+    o, g, grid = _mms_pair(oracle_lib, yy, 12, 24, 72, dt, mode=mode)
+    for s in range(4):
+        for f in (I.T, I.U1R, I.U1T, I.U1P):
+            a = I.mms_forcing(grid, (s + 0.5) * dt, f, 1.0, 1e3)
+            o.set_forcing(f, a)
+            g.set_forcing(f, a)
+        ko = o.step_tol(12, tol)
+        kg = g.step_tol(12, tol)
+        mx = o.norms(ko)[:, :, :9].max(axis=(1, 2))
+        # the stop decision is far from the tolerance on both sides
+        assert mx[-1] < 0.9 * tol and (ko == 1 or mx[-2] > 1.1 * tol), mx
+        assert kg == ko, (s, kg, ko)
+        assert _rel(g.norms(), o.norms(ko)) <= 1e-10
+    for f in range(9):
+        a = g.get_field(f).cpu().numpy()
+        b = o.get_field(f)
+        assert _rel(a, b) <= TOL, (I.FIELD_NAMES[f], _rel(a, b))
+
+
 def test_step_parity_convection(oracle_lib, yy):
     """Convection start (conductive T + seeded noise, hydrostatic p, T(R1)=1)
     at Ra=1e5, dt=2e-4, 3 Schwarz iterations, 2 steps."""
