@@ -193,11 +193,14 @@ int yy_residual(yy_shell *s, int32_t field, void *dev_out, hipStream_t stream);
 /* ---- line-solver autotuning ---- */
 
 /* Time every tile variant of the partitioned line solves of this shell
- * (strided r/theta sweeps: rows per chunk 8/12/16 x lane width 64/32/16;
- * phi sweeps: lines per block 1/2/4), each on the shell's own scratch
- * buffer with its current advecting velocity, keep the fastest per
- * (unknown, direction), and write the choices as a JSON object (a
- * NUL-terminated string of at most cap bytes) to json_out if not NULL.
+ * (strided r/theta sweeps: rows per chunk 8/12/16 x lane width 64/32/16,
+ * "m<rows>w<lanes>"; phi sweeps: one wave per line with 1/2/4 lines per
+ * block, "l<lines>", or 2/4 waves per line, "v<waves>"), each on the
+ * shell's own scratch buffer with its current advecting velocity and in
+ * the form the step launches it (the last factor of an unknown fused with
+ * its update and norm), keep the fastest per (unknown, direction), and
+ * write the choices as a JSON object (a NUL-terminated string of at most
+ * cap bytes) to json_out if not NULL.
  * Synchronises the stream.  Needs params.  Errors: YY_ERR_ARG,
  * YY_ERR_STATE, YY_ERR_HIP. */
 int yy_autotune(yy_shell *s, char *json_out, int32_t cap, hipStream_t stream);

@@ -1015,16 +1015,21 @@ extern "C" int yy_autotune(yy_shell *s, char *json_out, int32_t cap, hipStream_t
                 T.w[L][dir] = (int8_t)bw;
                 std::snprintf(val, sizeof val, "m%dw%d", bm, bw);
             } else {
-                int bl = 0;
+                // one wave per line with 1, 2 or 4 lines per block, or 2 or 4
+                // waves per line
+                int bl = 0, bv = 0;
                 double best = 1e30;
-                const int ls[3] = {1, 2, 4};
-                for (int il = 0; il < 3; il++) {
+                const int ls[5] = {1, 2, 4, 1, 1}, vs[5] = {0, 0, 0, 2, 4};
+                for (int il = 0; il < 5; il++) {
                     T.lpb[L] = (int8_t)ls[il];
+                    T.wpl[L] = (int8_t)vs[il];
                     const double t = time_sweep(s, tune_field_id[L], dir, st, a, b);
-                    if (t < best) { best = t; bl = ls[il]; }
+                    if (t < best) { best = t; bl = ls[il]; bv = vs[il]; }
                 }
                 T.lpb[L] = (int8_t)bl;
-                std::snprintf(val, sizeof val, "l%d", bl);
+                T.wpl[L] = (int8_t)bv;
+                if (bv) std::snprintf(val, sizeof val, "v%d", bv);
+                else std::snprintf(val, sizeof val, "l%d", bl);
             }
             if (js.size() > 1) js += ",";
             js += "\"";
@@ -1065,8 +1070,15 @@ extern "C" int yy_set_tuning(yy_shell *s, const char *json)
                 T.m[L][dir] = (int8_t)m;
                 T.w[L][dir] = (int8_t)w;
             } else {
-                if (std::sscanf(v, "l%d", &l) != 1 || (l != 1 && l != 2 && l != 4)) return YY_ERR_ARG;
-                T.lpb[L] = (int8_t)l;
+                if (std::sscanf(v, "l%d", &l) == 1 && (l == 1 || l == 2 || l == 4)) {
+                    T.lpb[L] = (int8_t)l;
+                    T.wpl[L] = 0;
+                } else if (std::sscanf(v, "v%d", &l) == 1 && (l == 2 || l == 4)) {
+                    T.lpb[L] = 1;
+                    T.wpl[L] = (int8_t)l;
+                } else {
+                    return YY_ERR_ARG;
+                }
             }
         }
     s->version++;

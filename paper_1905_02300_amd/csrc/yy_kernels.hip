@@ -1031,6 +1031,119 @@ __global__ void __launch_bounds__(256) k_sweep_contig(Dims d, Geo<R> g, Geo<doub
     }
 }
 
+// Contiguous lines, V = blockDim.x / 64 waves per line (one line per block
+// at a time): P = 64 V chunks of mc rows, so each lane holds a few rows
+// (fewer registers, more waves per SIMD).  Phases as in k_sweep_contig; the
+// reduced system spans the waves, so its PCR goes through LDS, reusing the
+// staging arrays of the coefficients once the chunks have consumed them.
+template <typename R, int L, int MODE, bool DIFF, int M>
+__global__ void __launch_bounds__(256) k_sweep_contig_mw(Dims d, Geo<R> g, Geo<double> gd, State<R> s,
+                                                         const R *x, R *y, R *psi, double *partial,
+                                                         int P, int mc)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int p = d.p0 + blockIdx.y;
+    const int i0 = ulo<L>(0), j0 = ulo<L>(1), k0 = ulo<L>(2);
+    const int n = d.np - k0;
+    const int ni = d.nr - i0, nj = d.nt - j0;
+    const int64_t nlines = (int64_t)ni * nj;
+    const int ld = P + 1;                      // padded row length of the transposed arrays
+    R *tlo = reinterpret_cast<R *>(smem_raw);
+    R *tdi = tlo + mc * ld, *tup = tlo + 2 * mc * ld, *tx = tlo + 3 * mc * ld;
+    // reduced rows (after the chunks are eliminated): aliases of tlo/tdi/tup
+    R *sA = tlo, *sB = tdi, *sC = tup, *sD = tlo + ld;
+    const R nu = (L == CC && !DIFF) ? R(1) : g.pr;
+    const int mt = tid < P ? (tid < P - 1 ? mc : n - (P - 1) * mc) : 0;
+    double acc = 0.0;
+    for (int64_t line = blockIdx.x; line < nlines; line += gridDim.x) {
+        const int i = i0 + (int)(line / nj), j = j0 + (int)(line % nj);
+        const int64_t q0 = ix(d, p, i, j, k0);
+        for (int e = tid; e < n; e += nthr) {
+            R lo, di, up;
+            line_row<R, L, 2, DIFF>(d, g, s, q0 + e, i, j, e, n, nu, lo, di, up);
+            const int cc = e / mc, rr = e - cc * mc;
+            const int o = rr * ld + cc;
+            tlo[o] = lo;
+            tdi[o] = di;
+            tup[o] = up;
+            tx[o] = x[q0 + e];
+        }
+        __syncthreads();
+        R a[M], c[M], dd[M];
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            a[m] = R(0); c[m] = R(0); dd[m] = R(0);
+            if (m < mt) {
+                const int o = m * ld + tid;
+                chunk_forward<R, M>(a, c, dd, m, tlo[o], tdi[o], tup[o], tx[o]);
+            }
+        }
+        if (mt > 0) chunk_backward<R, M>(a, c, dd, mt);
+        R ga = R(0), gc = R(0), gdv = R(0);
+        if (mt > 0) chunk_last<R, M>(a, c, dd, mt, ga, gc, gdv);
+        __syncthreads();                       // staging arrays are free from here
+        if (tid < P) {
+            sA[tid] = a[0];
+            sB[tid] = c[0];
+            sC[tid] = dd[0];
+        }
+        __syncthreads();
+        Row4<R> row = {R(0), R(1), R(0), R(0)};
+        if (tid < P) {
+            const bool nx = tid + 1 < P;
+            row = erow<R>(a[0], c[0], dd[0], ga, gc, gdv, nx ? sA[tid + 1] : R(0), nx ? sB[tid + 1] : R(0),
+                          nx ? sC[tid + 1] : R(0));
+        }
+        for (int h = 1; h < P; h <<= 1) {
+            __syncthreads();
+            if (tid < P) {
+                sA[tid] = row.a;
+                sB[tid] = row.b;
+                sC[tid] = row.c;
+                sD[tid] = row.d;
+            }
+            __syncthreads();
+            if (tid < P) {
+                Row4<R> rm = {R(0), R(1), R(0), R(0)}, rp = {R(0), R(1), R(0), R(0)};
+                if (tid - h >= 0) { rm.a = sA[tid - h]; rm.b = sB[tid - h]; rm.c = sC[tid - h]; rm.d = sD[tid - h]; }
+                if (tid + h < P) { rp.a = sA[tid + h]; rp.b = sB[tid + h]; rp.c = sC[tid + h]; rp.d = sD[tid + h]; }
+                row = pcr_level<R>(row, rm, rp);
+            }
+        }
+        const R xe = tid < P ? row.d / row.b : R(0);
+        __syncthreads();
+        if (tid < P) sA[tid] = xe;
+        __syncthreads();
+        const R xem = (tid > 0 && tid < P) ? sA[tid - 1] : R(0);
+        const R xs = dd[0] - a[0] * xem - c[0] * xe;
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            if (m < mt) {
+                const R v = (m == 0) ? xs : (m == mt - 1 ? xe : dd[m] - a[m] * xs - c[m] * xe);
+                tx[m * ld + tid] = v;
+            }
+        }
+        __syncthreads();
+        const double vol = MODE == 1 ? vol_at<L, 2>(gd, i, j) : 0.0;
+        for (int e = tid; e < n; e += nthr) {
+            const int cc = e / mc, rr = e - cc * mc;
+            const R v = tx[rr * ld + cc];
+            if (MODE == 0) {
+                y[q0 + e] = v;
+            } else {
+                psi[q0 + e] += v;
+                acc += vol * (double)v * (double)v;
+            }
+        }
+        __syncthreads();
+    }
+    if (MODE == 1) {
+        const double tot = block_sum(acc);
+        if (tid == 0) partial[p * NBMAX + blockIdx.x] = tot;
+    }
+}
+
 // Launch the partitioned solver when the line fits the register chunks,
 // else the per-line Thomas kernel.  Returns false if it fell back.
 template <typename R, int L, int D, int MODE, bool DIFF>
@@ -1085,13 +1198,44 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
             P = (n + mc - 1) / mc;
         }
         if (mc > 32 || P > 64) return false;
+        const int64_t nlines = (int64_t)(d.nr - i0) * (d.nt - j0);
+        const int V = s.tune.wpl[L];
+        if ((V == 2 || V == 4) && n >= 64 * V) {
+            // V waves per line: uniform chunks of mcv rows (last >= 2)
+            int mcv = (n + 64 * V - 1) / (64 * V);
+            if (mcv < 2) mcv = 2;
+            int Pv = (n + mcv - 1) / mcv;
+            while (Pv > 1 && n - (Pv - 1) * mcv < 2) {
+                mcv++;
+                Pv = (n + mcv - 1) / mcv;
+            }
+            if (mcv <= 8 && Pv <= 64 * V) {
+                int64_t b = nlines;
+                if (b > SWEEP_BLOCKS) b = SWEEP_BLOCKS;
+                if (nblocks) *nblocks = (int)b;
+                const size_t lds = (size_t)4 * mcv * (Pv + 1) * sizeof(R);
+                const dim3 grid((unsigned)b, d.npatch), block(64 * V);
+                hipLaunchKernelGGL((k_sweep_contig_mw<R, L, MODE, DIFF, 8>), grid, block, lds, st, d, g, gd, s, x, y,
+                                   psi, partial, Pv, mcv);
+                return true;
+            }
+            if (mcv <= 12 && Pv <= 64 * V) {
+                int64_t b = nlines;
+                if (b > SWEEP_BLOCKS) b = SWEEP_BLOCKS;
+                if (nblocks) *nblocks = (int)b;
+                const size_t lds = (size_t)4 * mcv * (Pv + 1) * sizeof(R);
+                const dim3 grid((unsigned)b, d.npatch), block(64 * V);
+                hipLaunchKernelGGL((k_sweep_contig_mw<R, L, MODE, DIFF, 12>), grid, block, lds, st, d, g, gd, s, x, y,
+                                   psi, partial, Pv, mcv);
+                return true;
+            }
+        }
         const size_t per_line = (size_t)4 * mc * (P + 1) * sizeof(R);
         int lpb = (int)(65536 / per_line);
         if (lpb > 4) lpb = 4;
         if (lpb < 1) return false;
         const int want = s.tune.lpb[L];
         if ((want == 1 || want == 2 || want == 4) && want < lpb) lpb = want;
-        const int64_t nlines = (int64_t)(d.nr - i0) * (d.nt - j0);
         int64_t b = (nlines + lpb - 1) / lpb;
         if (b > SWEEP_BLOCKS) b = SWEEP_BLOCKS;
         if (nblocks) *nblocks = (int)b;

@@ -341,9 +341,9 @@ def test_sweep_parity_every_tile(oracle_lib, yy, variant):
     _set_random(o, g, rng, [0, 1], scale=0.5)
     o.extrapolate()
     g.extrapolate()
-    lpb = {"m8w64": 1, "m8w16": 2, "m12w32": 4, "m16w64": 1, "m16w16": 2}[variant]
+    phi = {"m8w64": "l1", "m8w16": "l2", "m12w32": "l4", "m16w64": "v2", "m16w16": "v4"}[variant]
     js = "{" + ",".join(f'"{f}.{d}":"{variant}"' for f in ("T", "u_r", "u_t", "u_p") for d in "rt")
-    js += "," + ",".join(f'"{f}.p":"l{lpb}"' for f in ("T", "u_r", "u_t", "u_p")) + "}"
+    js += "," + ",".join(f'"{f}.p":"{phi}"' for f in ("T", "u_r", "u_t", "u_p")) + "}"
     g.set_tuning(js)
     for field in (I.T, I.U2R, I.U2T, I.U2P):
         m = _unknown_mask(o.padded_shape(), field)
@@ -354,6 +354,37 @@ def test_sweep_parity_every_tile(oracle_lib, yy, variant):
             g.sweep(field, d, g.to_internal(x), yt)
             got = g.from_internal(yt).cpu().numpy()
             assert _rel(got[m], ref[m]) <= TOL, (field, d, _rel(got[m], ref[m]))
+
+
+@pytest.mark.parametrize("variant", ["v2", "v4"])
+def test_phi_multiwave_parity(oracle_lib, yy, variant):
+    """phi lines spread over 2 or 4 waves (reduced system through LDS):
+    every unknown's phi sweep on lines of 300 and 1152 points, then whole
+    manufactured steps (the last phi factor fused with the update)."""
+    print(f"case: phi {variant}", flush=True)
+    js = "{" + ",".join(f'"{f}.p":"{variant}"' for f in ("T", "u_r", "u_t", "u_p")) + "}"
+    for shape in [(6, 10, 300), (4, 8, 1152)]:
+        o, g = _pair(oracle_lib, yy, *shape, pr=1.2, dt=1e-3, chi=0.9)
+        g.set_tuning(js)
+        rng = np.random.default_rng(41 + shape[2])
+        _set_random(o, g, rng, [0, 1], scale=0.5)
+        o.extrapolate()
+        g.extrapolate()
+        for field in (I.T, I.U2R, I.U2T, I.U2P):
+            m = _unknown_mask(o.padded_shape(), field)
+            x = rng.uniform(-1, 1, o.padded_shape())
+            ref = o.sweep(field, 2, x)
+            yt = g.internal_tensor()
+            g.sweep(field, 2, g.to_internal(x), yt)
+            got = g.from_internal(yt).cpu().numpy()
+            assert _rel(got[m], ref[m]) <= TOL, (shape, field, _rel(got[m], ref[m]))
+    o, g, grid = _mms_pair(oracle_lib, yy, 8, 24, 288, 1e-3)
+    g.set_tuning(js)
+    _mms_steps(o, g, grid, 1e-3, 3, 2)
+    for f in range(9):
+        a = g.get_field(f).cpu().numpy()
+        b = o.get_field(f)
+        assert _rel(a, b) <= TOL, (I.FIELD_NAMES[f], _rel(a, b))
 
 
 def test_autotune_round_trip(yy):
