@@ -1015,12 +1015,12 @@ extern "C" int yy_autotune(yy_shell *s, char *json_out, int32_t cap, hipStream_t
                 T.w[L][dir] = (int8_t)bw;
                 std::snprintf(val, sizeof val, "m%dw%d", bm, bw);
             } else {
-                // one wave per line with 1, 2 or 4 lines per block, or 2 or 4
-                // waves per line
+                // one wave per line with 1, 2 or 4 lines per block, or 2, 4 or
+                // 8 waves per line
                 int bl = 0, bv = 0;
                 double best = 1e30;
-                const int ls[5] = {1, 2, 4, 1, 1}, vs[5] = {0, 0, 0, 2, 4};
-                for (int il = 0; il < 5; il++) {
+                const int ls[6] = {1, 2, 4, 1, 1, 1}, vs[6] = {0, 0, 0, 2, 4, 8};
+                for (int il = 0; il < 6; il++) {
                     T.lpb[L] = (int8_t)ls[il];
                     T.wpl[L] = (int8_t)vs[il];
                     const double t = time_sweep(s, tune_field_id[L], dir, st, a, b);
@@ -1073,7 +1073,7 @@ extern "C" int yy_set_tuning(yy_shell *s, const char *json)
                 if (std::sscanf(v, "l%d", &l) == 1 && (l == 1 || l == 2 || l == 4)) {
                     T.lpb[L] = (int8_t)l;
                     T.wpl[L] = 0;
-                } else if (std::sscanf(v, "v%d", &l) == 1 && (l == 2 || l == 4)) {
+                } else if (std::sscanf(v, "v%d", &l) == 1 && (l == 2 || l == 4 || l == 8)) {
                     T.lpb[L] = 1;
                     T.wpl[L] = (int8_t)l;
                 } else {

@@ -1037,7 +1037,7 @@ __global__ void __launch_bounds__(256) k_sweep_contig(Dims d, Geo<R> g, Geo<doub
 // reduced system spans the waves, so its PCR goes through LDS, reusing the
 // staging arrays of the coefficients once the chunks have consumed them.
 template <typename R, int L, int MODE, bool DIFF, int M>
-__global__ void __launch_bounds__(256) k_sweep_contig_mw(Dims d, Geo<R> g, Geo<double> gd, State<R> s,
+__global__ void __launch_bounds__(512) k_sweep_contig_mw(Dims d, Geo<R> g, Geo<double> gd, State<R> s,
                                                          const R *x, R *y, R *psi, double *partial,
                                                          int P, int mc)
 {
@@ -1200,7 +1200,7 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
         if (mc > 32 || P > 64) return false;
         const int64_t nlines = (int64_t)(d.nr - i0) * (d.nt - j0);
         const int V = s.tune.wpl[L];
-        if ((V == 2 || V == 4) && n >= 64 * V) {
+        if ((V == 2 || V == 4 || V == 8) && n >= 64 * V) {
             // V waves per line: uniform chunks of mcv rows (last >= 2)
             int mcv = (n + 64 * V - 1) / (64 * V);
             if (mcv < 2) mcv = 2;
@@ -1209,24 +1209,20 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
                 mcv++;
                 Pv = (n + mcv - 1) / mcv;
             }
-            if (mcv <= 8 && Pv <= 64 * V) {
-                int64_t b = nlines;
-                if (b > SWEEP_BLOCKS) b = SWEEP_BLOCKS;
-                if (nblocks) *nblocks = (int)b;
-                const size_t lds = (size_t)4 * mcv * (Pv + 1) * sizeof(R);
-                const dim3 grid((unsigned)b, d.npatch), block(64 * V);
-                hipLaunchKernelGGL((k_sweep_contig_mw<R, L, MODE, DIFF, 8>), grid, block, lds, st, d, g, gd, s, x, y,
-                                   psi, partial, Pv, mcv);
-                return true;
-            }
             if (mcv <= 12 && Pv <= 64 * V) {
                 int64_t b = nlines;
                 if (b > SWEEP_BLOCKS) b = SWEEP_BLOCKS;
                 if (nblocks) *nblocks = (int)b;
                 const size_t lds = (size_t)4 * mcv * (Pv + 1) * sizeof(R);
                 const dim3 grid((unsigned)b, d.npatch), block(64 * V);
-                hipLaunchKernelGGL((k_sweep_contig_mw<R, L, MODE, DIFF, 12>), grid, block, lds, st, d, g, gd, s, x, y,
-                                   psi, partial, Pv, mcv);
+#define YY_MW(MM)                                                                                      \
+    hipLaunchKernelGGL((k_sweep_contig_mw<R, L, MODE, DIFF, MM>), grid, block, lds, st, d, g, gd, s, x, y, \
+                       psi, partial, Pv, mcv)
+                if (mcv <= 4) YY_MW(4);
+                else if (mcv <= 6) YY_MW(6);
+                else if (mcv <= 8) YY_MW(8);
+                else YY_MW(12);
+#undef YY_MW
                 return true;
             }
         }

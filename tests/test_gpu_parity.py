@@ -356,14 +356,14 @@ def test_sweep_parity_every_tile(oracle_lib, yy, variant):
             assert _rel(got[m], ref[m]) <= TOL, (field, d, _rel(got[m], ref[m]))
 
 
-@pytest.mark.parametrize("variant", ["v2", "v4"])
+@pytest.mark.parametrize("variant", ["v2", "v4", "v8"])
 def test_phi_multiwave_parity(oracle_lib, yy, variant):
-    """phi lines spread over 2 or 4 waves (reduced system through LDS):
+    """phi lines spread over 2, 4 or 8 waves (reduced system through LDS):
     every unknown's phi sweep on lines of 300 and 1152 points, then whole
     manufactured steps (the last phi factor fused with the update)."""
     print(f"case: phi {variant}", flush=True)
     js = "{" + ",".join(f'"{f}.p":"{variant}"' for f in ("T", "u_r", "u_t", "u_p")) + "}"
-    for shape in [(6, 10, 300), (4, 8, 1152)]:
+    for shape in [(6, 10, 300), (5, 9, 600), (4, 8, 1152)]:
         o, g = _pair(oracle_lib, yy, *shape, pr=1.2, dt=1e-3, chi=0.9)
         g.set_tuning(js)
         rng = np.random.default_rng(41 + shape[2])
@@ -378,7 +378,7 @@ def test_phi_multiwave_parity(oracle_lib, yy, variant):
             g.sweep(field, 2, g.to_internal(x), yt)
             got = g.from_internal(yt).cpu().numpy()
             assert _rel(got[m], ref[m]) <= TOL, (shape, field, _rel(got[m], ref[m]))
-    o, g, grid = _mms_pair(oracle_lib, yy, 8, 24, 288, 1e-3)
+    o, g, grid = _mms_pair(oracle_lib, yy, 8, 24, 576, 1e-3)
     g.set_tuning(js)
     _mms_steps(o, g, grid, 1e-3, 3, 2)
     for f in range(9):
