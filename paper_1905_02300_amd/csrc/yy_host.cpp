@@ -1003,8 +1003,8 @@ extern "C" int yy_autotune(yy_shell *s, char *json_out, int32_t cap, hipStream_t
             if (dir < 2) {
                 int bm = 0, bw = 0;
                 double best = 1e30;
-                const int ms[3] = {8, 12, 16}, ws[3] = {64, 32, 16};
-                for (int im = 0; im < 3; im++)
+                const int ms[5] = {4, 6, 8, 12, 16}, ws[3] = {64, 32, 16};
+                for (int im = 0; im < 5; im++)
                     for (int iw = 0; iw < 3; iw++) {
                         T.m[L][dir] = (int8_t)ms[im];
                         T.w[L][dir] = (int8_t)ws[iw];
@@ -1066,7 +1066,8 @@ extern "C" int yy_set_tuning(yy_shell *s, const char *json)
             int m = 0, w = 0, l = 0;
             if (dir < 2) {
                 if (std::sscanf(v, "m%dw%d", &m, &w) != 2) return YY_ERR_ARG;
-                if ((m != 8 && m != 12 && m != 16) || (w != 16 && w != 32 && w != 64)) return YY_ERR_ARG;
+                if ((m != 4 && m != 6 && m != 8 && m != 12 && m != 16) || (w != 16 && w != 32 && w != 64))
+                    return YY_ERR_ARG;
                 T.m[L][dir] = (int8_t)m;
                 T.w[L][dir] = (int8_t)w;
             } else {

@@ -94,7 +94,7 @@ struct FillVector {
 };
 
 // line-solver tile choices per location (CC, FR, FT, FP); 0 = built-in
-// default.  Strided r/theta sweeps: rows per chunk m (8, 12, 16) and the
+// default.  Strided r/theta sweeps: rows per chunk m (4, 6, 8, 12, 16) and the
 // largest lane width w (64, 32, 16); phi sweeps: one wave per line and
 // lines per block lpb (1, 2, 4), or wpl (2, 4, 8) waves per line.
 struct Tune {

@@ -1156,7 +1156,7 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
         // rows per chunk: tuned, else 12 for the u_theta polar sweep (the
         // most per-row data) and 16 otherwise
         int M = s.tune.m[L][D];
-        if (M != 8 && M != 12 && M != 16) M = (L == FT && D == 1) ? 12 : 16;
+        if (M != 4 && M != 6 && M != 8 && M != 12 && M != 16) M = (L == FT && D == 1) ? 12 : 16;
         const int n = ncell(d, D) - (D == 0 ? i0 : j0);
         int P = (n + M - 1) / M;
         if (P < 1) P = 1;
@@ -1177,7 +1177,13 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
         if (nblocks) *nblocks = (int)b;
         if (2 * P > n && n > 1) return false;
         const size_t lds = (size_t)4 * P * W * sizeof(R);
-        if (M == 8)
+        if (M == 4)
+            hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, 4>), dim3((unsigned)b, d.npatch), dim3(W, P),
+                               lds, st, d, g, gd, s, x, y, psi, partial);
+        else if (M == 6)
+            hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, 6>), dim3((unsigned)b, d.npatch), dim3(W, P),
+                               lds, st, d, g, gd, s, x, y, psi, partial);
+        else if (M == 8)
             hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, 8>), dim3((unsigned)b, d.npatch), dim3(W, P),
                                lds, st, d, g, gd, s, x, y, psi, partial);
         else if (M == 12)
