@@ -48,6 +48,10 @@ struct yyo {
     double *lev[YYO_NF][NLEV];   /* levels n, n-1, working iterate k */
     double *star[YYO_NF];        /* 1.5 psi^n - 0.5 psi^{n-1} */
     double *force[4];            /* T, u_r, u_theta, u_phi (padded) */
+    /* wall data of T, u_r, u_theta, u_phi per level and wall (0: r = R1,
+     * 1: r = R2): [patch][j+1][k+1] at the field's own (theta, phi)
+     * positions, or NULL (T = t_in / t_out, u = 0) */
+    double *wall[4][NLEV][2];
     double *res, *wa, *wb;
     double norms[MAXK][2][NNORM];
     int nk, filled;
@@ -260,6 +264,8 @@ yyo *yyo_create(int nr, int nt, int np, double r1, double r2, double delta)
         h->star[f] = (double *)calloc(1, bytes);
     }
     for (int c = 0; c < 4; c++) h->force[c] = NULL;
+    for (int c = 0; c < 4; c++)
+        for (int l = 0; l < NLEV; l++) h->wall[c][l][0] = h->wall[c][l][1] = NULL;
     h->res = (double *)calloc(1, bytes);
     h->wa = (double *)calloc(1, bytes);
     h->wb = (double *)calloc(1, bytes);
@@ -274,6 +280,8 @@ void yyo_destroy(yyo *h)
         free(h->star[f]);
     }
     for (int c = 0; c < 4; c++) free(h->force[c]);
+    for (int c = 0; c < 4; c++)
+        for (int l = 0; l < NLEV; l++) { free(h->wall[c][l][0]); free(h->wall[c][l][1]); }
     free(h->res); free(h->wa); free(h->wb);
     free(h);
 }
@@ -352,6 +360,35 @@ int yyo_set_forcing(yyo *h, int field, const double *src)
     return 0;
 }
 
+/* Dirichlet data on the walls (the boundary conditions of eq. eq_ns and
+ * eq_heat_convec with given values) for one field and level; NULL clears. */
+int yyo_set_wall(yyo *h, int field, int level, int wall, const double *src)
+{
+    int c;
+    switch (field) {
+    case YYO_T: c = 0; break;
+    case YYO_U1R: c = 1; break;
+    case YYO_U1T: c = 2; break;
+    case YYO_U1P: c = 3; break;
+    default: return -1;
+    }
+    if (!h || level < 0 || level >= NLEV || wall < 0 || wall > 1) return -1;
+    double **w = &h->wall[c][level][wall];
+    if (!src) { free(*w); *w = NULL; return 0; }
+    size_t n = 2 * (size_t)(h->nt + 2) * (size_t)(h->np + 2);
+    if (!*w) *w = (double *)malloc(n * sizeof(double));
+    memcpy(*w, src, n * sizeof(double));
+    return 0;
+}
+
+/* wall value of wall-data slot c at (patch, j, k), or the default */
+static double wall_value(const yyo *h, int c, int level, int wall, int p, int j, int k, double dflt)
+{
+    const double *w = h->wall[c][level][wall];
+    if (!w) return dflt;
+    return w[((size_t)p * (h->nt + 2) + (size_t)(j + 1)) * (size_t)(h->np + 2) + (size_t)(k + 1)];
+}
+
 /* ------------------------------------------------------------------ */
 /* overlap interpolation and wall rules (Sec. 4, Algorithm steps 1,3,7) */
 /* ------------------------------------------------------------------ */
@@ -397,28 +434,32 @@ static void fill_vector_target(const yyo *h, int loc, int j, int k, void *vctx)
     }
 }
 
-/* Wall rules (eq. eq_ns, eq_heat_convec boundary conditions): u = 0 and
- * T = T_wall on r = R1, R2.  u_r lives on the wall faces; centre-type
- * fields get a reflection ghost psi_{-1} = 2 psi_wall - psi_0.  Pressure
- * needs no wall values. */
+/* Wall rules (eq. eq_ns, eq_heat_convec boundary conditions): u = u_wall
+ * and T = T_wall on r = R1, R2 (u_wall = 0 and the constant wall
+ * temperatures unless wall data is given).  u_r lives on the wall faces;
+ * centre-type fields get a reflection ghost psi_{-1} = 2 psi_wall - psi_0.
+ * Pressure needs no wall values.  Both velocity systems take the same
+ * wall data. */
 static void wall_rules(const yyo *h, int level, int p)
 {
     int nr = h->nr;
     for (int j = -1; j <= h->nt; j++)
         for (int k = -1; k <= h->np; k++) {
             double *T = h->lev[YYO_T][level];
-            T[ix(h, p, -1, j, k)] = 2.0 * h->t_in - T[ix(h, p, 0, j, k)];
-            T[ix(h, p, nr, j, k)] = 2.0 * h->t_out - T[ix(h, p, nr - 1, j, k)];
+            T[ix(h, p, -1, j, k)] = 2.0 * wall_value(h, 0, level, 0, p, j, k, h->t_in) - T[ix(h, p, 0, j, k)];
+            T[ix(h, p, nr, j, k)] = 2.0 * wall_value(h, 0, level, 1, p, j, k, h->t_out) - T[ix(h, p, nr - 1, j, k)];
             static const int tang[4] = { YYO_U1T, YYO_U1P, YYO_U2T, YYO_U2P };
             for (int q = 0; q < 4; q++) {
+                const int c = (q % 2 == 0) ? 2 : 3;
                 double *a = h->lev[tang[q]][level];
-                a[ix(h, p, -1, j, k)] = -a[ix(h, p, 0, j, k)];
-                a[ix(h, p, nr, j, k)] = -a[ix(h, p, nr - 1, j, k)];
+                a[ix(h, p, -1, j, k)] = 2.0 * wall_value(h, c, level, 0, p, j, k, 0.0) - a[ix(h, p, 0, j, k)];
+                a[ix(h, p, nr, j, k)] = 2.0 * wall_value(h, c, level, 1, p, j, k, 0.0) - a[ix(h, p, nr - 1, j, k)];
             }
-            h->lev[YYO_U1R][level][ix(h, p, 0, j, k)] = 0.0;
-            h->lev[YYO_U1R][level][ix(h, p, nr, j, k)] = 0.0;
-            h->lev[YYO_U2R][level][ix(h, p, 0, j, k)] = 0.0;
-            h->lev[YYO_U2R][level][ix(h, p, nr, j, k)] = 0.0;
+            const double w0 = wall_value(h, 1, level, 0, p, j, k, 0.0), w1 = wall_value(h, 1, level, 1, p, j, k, 0.0);
+            h->lev[YYO_U1R][level][ix(h, p, 0, j, k)] = w0;
+            h->lev[YYO_U1R][level][ix(h, p, nr, j, k)] = w1;
+            h->lev[YYO_U2R][level][ix(h, p, 0, j, k)] = w0;
+            h->lev[YYO_U2R][level][ix(h, p, nr, j, k)] = w1;
         }
 }
 
@@ -1074,6 +1115,15 @@ static int step_run(yyo *h, int K, double tol)
         memcpy(h->lev[f][YYO_LEV_NM1], h->lev[f][YYO_LEV_N], bytes);
         memcpy(h->lev[f][YYO_LEV_N], h->lev[f][YYO_LEV_K], bytes);
     }
+    /* wall data moves with its level: n-1 <- n <- k; the k slot keeps the
+     * old n-1 data until the caller sets the next step's values */
+    for (int c = 0; c < 4; c++)
+        for (int w = 0; w < 2; w++) {
+            double *t = h->wall[c][YYO_LEV_NM1][w];
+            h->wall[c][YYO_LEV_NM1][w] = h->wall[c][YYO_LEV_N][w];
+            h->wall[c][YYO_LEV_N][w] = h->wall[c][YYO_LEV_K][w];
+            h->wall[c][YYO_LEV_K][w] = t;
+        }
     return done;
 }
 

@@ -52,6 +52,13 @@ int yyo_get_field(const yyo *h, int field, int level, int layout, double *dst);
 /* forcing of T, u_r, u_theta, u_phi (fields YYO_T, YYO_U1R, YYO_U1T,
  * YYO_U1P; it applies to both velocity systems), MAC layout; NULL clears */
 int yyo_set_forcing(yyo *h, int field, const double *src);
+/* Dirichlet wall data of T, u_r, u_theta or u_phi (field YYO_T, YYO_U1R,
+ * YYO_U1T, YYO_U1P; both velocity systems take it) for one level (n, n-1,
+ * or the iterate k, i.e. time t^{n+1}) and wall (0: r = R1, 1: r = R2):
+ * doubles [patch][j+1][k+1], j = -1..nt, k = -1..np, at the field's own
+ * (theta, phi) positions.  NULL clears (T = t_inner / t_outer, u = 0).
+ * The data rotates with the levels at the end of a step. */
+int yyo_set_wall(yyo *h, int field, int level, int wall, const double *src);
 /* Advance one time step with K Schwarz iterations. */
 int yyo_step(yyo *h, int K);
 /* Advance one time step, iterating until every increment norm of an

@@ -38,6 +38,7 @@ def lib():
         L.yyo_set_field.argtypes = [vp, i, i, i, dp]
         L.yyo_get_field.argtypes = [vp, i, i, i, dp]
         L.yyo_set_forcing.argtypes = [vp, i, dp]
+        L.yyo_set_wall.argtypes = [vp, i, i, i, dp]
         L.yyo_step.argtypes = [vp, i]
         L.yyo_step_tol.argtypes = [vp, i, d]
         L.yyo_get_norms.argtypes = [vp, dp, i]
@@ -142,6 +143,18 @@ class Shell:
         a = _f64(a)
         assert a.shape == self.mac_shape(field)
         lib().yyo_set_forcing(self.h, field, _ptr(a))
+
+    def set_wall(self, field, level, wall, a):
+        """Dirichlet wall data (2, nt+2, np+2) of T, u_r, u_theta or u_phi
+        for a level and a wall (0: R1, 1: R2); None clears"""
+        if a is None:
+            if lib().yyo_set_wall(self.h, field, level, wall, None) != 0:
+                raise RuntimeError("set_wall failed")
+            return
+        a = _f64(a)
+        assert a.shape == (2, self.nt + 2, self.np + 2)
+        if lib().yyo_set_wall(self.h, field, level, wall, _ptr(a)) != 0:
+            raise RuntimeError("set_wall failed")
 
     def step(self, K):
         if lib().yyo_step(self.h, K) != 0:

@@ -78,6 +78,10 @@ def points(grid, field, patch, padded=False):
     """Global Cartesian coordinates and the local unit vectors (global
     frame) of a field's MAC (or padded-layout) points on one patch."""
     r, t, p = grid.axes(field, padded)
+    return _frame_points(r, t, p, patch)
+
+
+def _frame_points(r, t, p, patch):
     R, TH, PH = np.meshgrid(r, t, p, indexing="ij")
     st, ct, sp, cp = np.sin(TH), np.cos(TH), np.sin(PH), np.cos(PH)
     X = _patch_frame(patch, np.stack([R * st * cp, R * st * sp, R * ct]))
@@ -188,17 +192,53 @@ def _mms_values(X, r1, r2):
     return U, xyz / r, a * b * z / r
 
 
-def mms_fields(grid, t, field, padded=False):
-    """Exact value of a field of the manufactured solution at time t on its
-    MAC points (both patches), or on every slot of the padded layout.
-    Velocity fields are the same for systems 1 and 2, pressure fields for
-    p1 and p2."""
+def _paper_jets(X):
+    """Spatial parts of the manufactured solution of the numerical-tests
+    section (eq. Exact): u = cos t (2x^2yz, -xy^2z, -xyz^2), p = cos t xyz,
+    T = 2 cos t x^2yz.  It is divergence-free and non-zero on the walls."""
+    x, y, z = (Jet.var(X, d) for d in range(3))
+    r = (x * x + y * y + z * z).sqrt()
+    U = [x * x * y * z * 2.0, -(x * y * y * z), -(x * y * z * z)]
+    return U, x * y * z, x * x * y * z * 2.0, r
+
+
+def _paper_values(X):
+    x, y, z = X
+    return [2.0 * x * x * y * z, -x * y * y * z, -x * y * z * z], x * y * z, 2.0 * x * x * y * z
+
+
+# time factor a(t) and a'(t) of each manufactured solution: "shell" (ours,
+# zero on the walls) and "paper" (eq. Exact)
+_TIME = {"shell": (math.sin, math.cos), "paper": (math.cos, lambda t: -math.sin(t))}
+
+
+def _values(kind, X, r1, r2):
+    return _mms_values(X, r1, r2) if kind == "shell" else _paper_values(X)
+
+
+def _jets(kind, X, r1, r2):
+    return _mms_jets(X, r1, r2) if kind == "shell" else _paper_jets(X)
+
+
+def _field_value(field, U, P, TH, e):
+    loc = LOC[field]
+    if loc == "c":
+        return TH if field == T else P
+    ev = {"r": e[0], "t": e[1], "p": e[2]}[loc]
+    return U[0] * ev[0] + U[1] * ev[1] + U[2] * ev[2]
+
+
+def mms_fields(grid, t, field, padded=False, kind="shell"):
+    """Exact value of a field of a manufactured solution ("shell": ours,
+    "paper": eq. Exact) at time t on its MAC points (both patches), or on
+    every slot of the padded layout.  Velocity fields are the same for
+    systems 1 and 2, pressure fields for p1 and p2."""
     shape = (2, grid.nr + 2, grid.nt + 2, grid.np + 2) if padded else grid.mac_shape(field)
     out = np.zeros(shape)
-    s = math.sin(t)
+    s = _TIME[kind][0](t)
     for patch in range(2):
         X, (er, et, ep) = points(grid, field, patch, padded)
-        U, P, TH = _mms_values(X, grid.r1, grid.r2)
+        U, P, TH = _values(kind, X, grid.r1, grid.r2)
         loc = LOC[field]
         if loc == "c":
             out[patch] = s * (TH if field == T else P)
@@ -208,16 +248,16 @@ def mms_fields(grid, t, field, padded=False):
     return out
 
 
-def mms_forcing(grid, t, field, pr, ra, padded=False):
+def mms_forcing(grid, t, field, pr, ra, padded=False, kind="shell"):
     """Forcing at time t that makes the manufactured solution exact:
     f_u = du/dt + (u.grad)u + grad p - Pr lap u - Pr Ra T e_r,
     f_T = dT/dt + u.grad T - lap T  (field T, U1R, U1T or U1P)."""
     shape = (2, grid.nr + 2, grid.nt + 2, grid.np + 2) if padded else grid.mac_shape(field)
     out = np.zeros(shape)
-    s, c = math.sin(t), math.cos(t)
+    s, c = _TIME[kind][0](t), _TIME[kind][1](t)
     for patch in range(2):
         X, (er, et, ep) = points(grid, field, patch, padded)
-        U, P, TH, r = _mms_jets(X, grid.r1, grid.r2)
+        U, P, TH, r = _jets(kind, X, grid.r1, grid.r2)
         if field == T:
             adv = sum(U[d].v * TH.g[d] for d in range(3))
             out[patch] = c * TH.v + s * s * adv - s * TH.lap()
@@ -233,12 +273,28 @@ def mms_forcing(grid, t, field, pr, ra, padded=False):
     return out
 
 
-def mms_state(grid, t, padded=False):
+def mms_state(grid, t, padded=False, kind="shell"):
     """All nine fields of the manufactured solution at time t."""
-    st = {f: mms_fields(grid, t, f, padded) for f in (T, U1R, U1T, U1P, P1)}
+    st = {f: mms_fields(grid, t, f, padded, kind) for f in (T, U1R, U1T, U1P, P1)}
     for f, base in ((U2R, U1R), (U2T, U1T), (U2P, U1P), (P2, P1)):
         st[f] = st[base].copy()
     return st
+
+
+def wall_values(grid, t, field, kind="paper"):
+    """Exact Dirichlet data of T, u_r, u_theta or u_phi (field T, U1R, U1T
+    or U1P) at time t on the walls r = R1 (index 0) and r = R2 (index 1), at
+    the field's own (theta, phi) positions of the padded layout: shape
+    (2 walls, 2 patches, nt+2, np+2)."""
+    _, th, ph = grid.axes(field, padded=True)
+    out = np.zeros((2, 2, grid.nt + 2, grid.np + 2))
+    s = _TIME[kind][0](t)
+    for w, r in enumerate((grid.r1, grid.r2)):
+        for patch in range(2):
+            X, e = _frame_points(np.array([r]), th, ph, patch)
+            U, P, TH = _values(kind, X, grid.r1, grid.r2)
+            out[w, patch] = s * _field_value(field, U, P, TH, e)[0]
+    return out
 
 
 # ---------------------------------------------------------------------------
