@@ -124,13 +124,32 @@ int yy_get_field(yy_shell *s, int32_t field, int32_t level, int32_t layout,
  * Errors: YY_ERR_ARG. */
 int yy_set_forcing(yy_shell *s, int32_t field, const double *dev_src, hipStream_t stream);
 
+/* Dirichlet wall data (the boundary conditions u = u_wall, T = T_wall on
+ * r = R1, R2 of eq. eq_ns / eq_heat_convec with given, possibly
+ * time-dependent values) of T, u_r, u_theta or u_phi (field = YY_T,
+ * YY_U1R, YY_U1T, YY_U1P; both velocity systems take it) for one time
+ * level (YY_LEVEL_N: t^n, YY_LEVEL_NM1: t^{n-1}, YY_LEVEL_K: the step's
+ * target t^{n+1}) and wall (0: r = R1, 1: r = R2).  dev_src: device doubles
+ * [patch][j+1][k+1], j = -1..nt, k = -1..np (2 (nt+2)(np+2) values), at the
+ * field's own (theta, phi) positions (theta-faces for u_theta, phi-faces
+ * for u_phi, centres otherwise); copied on `stream`.  NULL clears the slot
+ * (then T = t_inner / t_outer and u = 0 on that wall).  The fills apply
+ * u_r = u_wall on its wall faces and reflection ghosts
+ * psi_{-1} = 2 psi_wall - psi_0 for the others.  The slots rotate with the
+ * levels at the end of a step; while a field uses wall data, its
+ * YY_LEVEL_K slots must be set again before every step (else yy_step
+ * returns YY_ERR_STATE).  Errors: YY_ERR_ARG, YY_ERR_HIP. */
+int yy_set_wall(yy_shell *s, int32_t field, int32_t level, int32_t wall, const double *dev_src,
+                hipStream_t stream);
+
 /* Advance one time step n -> n+1 with n_schwarz Schwarz iterations
  * (Sec. 4 Algorithm with the splitting-error reduction eq. er): per
  * iteration, refresh every field's ghosts from the other patch, solve T,
  * u1 (r, theta, phi), p1, u2 (r, theta, phi), p2, each velocity/T solve as
  * a residual and three direction-split tridiagonal sweeps (Sec. 4).
  * Asynchronous.  Errors: YY_ERR_ARG (n_schwarz < 1 or > 64), YY_ERR_STATE
- * (params not set), YY_ERR_HIP. */
+ * (params not set, or wall data in use without this step's YY_LEVEL_K
+ * values), YY_ERR_HIP. */
 int yy_step(yy_shell *s, int32_t n_schwarz, hipStream_t stream);
 
 /* One time step with the paper's tolerance-driven Schwarz loop (Sec. 5.1:

@@ -27,7 +27,8 @@ struct Layout {
     int64_t ncc, nvt, nvp;   // interpolation targets per class
     // byte offsets
     int64_t off_fields, off_p, off_tab_r, off_tab_d, off_ptab_r, off_ptab_d, off_fill, off_partial,
-        off_norms, total;
+        off_norms, off_wall, total;
+    int64_t wall_elems;      // doubles of one wall-data slot: 2 (nt+2)(np+2)
     int64_t elem;            // bytes per compute element
     int nR;                  // compute-precision arrays
 };
@@ -87,6 +88,10 @@ Layout make_layout(const yy_grid *g, int prec)
     o += align_up((int64_t)NSLOT * 2 * NBMAX * 8, ALIGN);
     L.off_norms = o;
     o += align_up((int64_t)MAXK * 2 * NSLOT * 8, ALIGN);
+    // wall data: T, u_r, u_theta, u_phi x 3 levels x 2 walls
+    L.wall_elems = 2 * (int64_t)(g->nt + 2) * (g->np + 2);
+    L.off_wall = o;
+    o += 24 * align_up(L.wall_elems * 8, ALIGN);
     L.total = o;
     return L;
 }
@@ -395,6 +400,12 @@ struct yy_shell {
     int nblocks[NSLOT];
     bool has_force[4] = {false, false, false, false};
     void *force_ptr[4];
+    // Dirichlet wall data per (T, u_r, u_theta, u_phi) x level x wall: device
+    // slot, whether it holds data, and whether the iterate's (level k) data
+    // was set since the last step; slots rotate with the levels
+    double *wall[4][3][2];
+    bool wall_on[4][3][2] = {};
+    bool wall_fresh[4][2] = {};
 };
 
 namespace {
@@ -471,11 +482,20 @@ struct Timed {
     }
 };
 
+WallLev walls_of(const yy_shell *s, int lev)
+{
+    WallLev w;
+    for (int c = 0; c < 4; c++)
+        for (int side = 0; side < 2; side++)
+            w.v[c][side] = s->wall_on[c][lev][side] ? s->wall[c][lev][side] : nullptr;
+    return w;
+}
+
 template <typename R> void do_fill(yy_shell *s, int lev, int pmask, hipStream_t st)
 {
     Timed tm(s, PC_FILL, st);
     Ops<R>::fill(s->L.d, state_of<R>(s), lev, s->fcc, (int)s->L.ncc, s->fvt, (int)s->L.nvt, s->fvp,
-                 (int)s->L.nvp, s->prm.t_inner, s->prm.t_outer, pmask, st);
+                 (int)s->L.nvp, s->prm.t_inner, s->prm.t_outer, walls_of(s, lev), pmask, st);
 }
 
 template <typename R> void solve_field(yy_shell *s, const Dims &d, int f, hipStream_t st)
@@ -602,6 +622,29 @@ template <typename R> void rotate_levels(yy_shell *s)
         S.p[y][0] = S.p[y][1];
         S.p[y][1] = p;
     }
+    // wall data moves with its level (n-1 <- n <- k); the k slot keeps the
+    // old n-1 data, which the caller must replace before the next step
+    for (int c = 0; c < 4; c++)
+        for (int w = 0; w < 2; w++) {
+            double *t = s->wall[c][1][w];
+            const bool o = s->wall_on[c][1][w];
+            s->wall[c][1][w] = s->wall[c][0][w];
+            s->wall_on[c][1][w] = s->wall_on[c][0][w];
+            s->wall[c][0][w] = s->wall[c][2][w];
+            s->wall_on[c][0][w] = s->wall_on[c][2][w];
+            s->wall[c][2][w] = t;
+            s->wall_on[c][2][w] = o;
+            s->wall_fresh[c][w] = false;
+        }
+}
+
+// wall data in use for a field but not set for the step's iterate
+bool walls_stale(const yy_shell *s)
+{
+    for (int c = 0; c < 4; c++)
+        for (int w = 0; w < 2; w++)
+            if ((s->wall_on[c][0][w] || s->wall_on[c][2][w]) && !s->wall_fresh[c][w]) return true;
+    return false;
 }
 
 }  // namespace
@@ -686,6 +729,10 @@ int yy_create(const yy_grid *g, int32_t prec, void *dev_ws, uint64_t ws_bytes, y
     }
     s->partial = (double *)(s->ws + L.off_partial);
     s->norms = (double *)(s->ws + L.off_norms);
+    for (int c = 0; c < 4; c++)
+        for (int l = 0; l < 3; l++)
+            for (int w = 0; w < 2; w++)
+                s->wall[c][l][w] = (double *)(s->ws + L.off_wall + ((c * 3 + l) * 2 + w) * align_up(L.wall_elems * 8, ALIGN));
     for (int q = 0; q < NSLOT; q++) s->nblocks[q] = 0;
     *out = s;
     return YY_OK;
@@ -782,10 +829,32 @@ int yy_set_forcing(yy_shell *s, int32_t field, const double *src, hipStream_t st
     return hip_status(hipGetLastError());
 }
 
+int yy_set_wall(yy_shell *s, int32_t field, int32_t level, int32_t wall, const double *src, hipStream_t st)
+{
+    int c;
+    switch (field) {
+    case YY_T: c = 0; break;
+    case YY_U1R: c = 1; break;
+    case YY_U1T: c = 2; break;
+    case YY_U1P: c = 3; break;
+    default: return YY_ERR_ARG;
+    }
+    if (!s || level < 0 || level > 2 || wall < 0 || wall > 1) return YY_ERR_ARG;
+    const bool on = src != nullptr;
+    if (on && hipMemcpyAsync(s->wall[c][level][wall], src, s->L.wall_elems * 8, hipMemcpyDeviceToDevice,
+                             st) != hipSuccess)
+        return YY_ERR_HIP;
+    if (on != s->wall_on[c][level][wall]) s->version++;   // kernel arguments change
+    s->wall_on[c][level][wall] = on;
+    if (level == YY_LEVEL_K) s->wall_fresh[c][wall] = true;
+    else s->need_fill = true;
+    return YY_OK;
+}
+
 int yy_step(yy_shell *s, int32_t K, hipStream_t st)
 {
     if (!s || K < 1 || K > MAXK) return YY_ERR_ARG;
-    if (!s->have_params) return YY_ERR_STATE;
+    if (!s->have_params || walls_stale(s)) return YY_ERR_STATE;
     if (s->sticky != YY_OK) return s->sticky;
     return s->L.prec == YY_FP64 ? step_impl<double>(s, K, -1.0, nullptr, st)
                                 : step_impl<float>(s, K, -1.0, nullptr, st);
@@ -795,7 +864,7 @@ int yy_step_tol(yy_shell *s, int32_t kmax, double tol, int32_t *k_done, hipStrea
 {
     if (!s || !k_done || kmax < 1 || kmax > MAXK || !(tol >= 0.0) || !std::isfinite(tol)) return YY_ERR_ARG;
     *k_done = 0;
-    if (!s->have_params) return YY_ERR_STATE;
+    if (!s->have_params || walls_stale(s)) return YY_ERR_STATE;
     if (s->sticky != YY_OK) return s->sticky;
     int k = 0;
     const int r = s->L.prec == YY_FP64 ? step_impl<double>(s, kmax, tol, &k, st)
@@ -1108,7 +1177,7 @@ namespace {
 
 int shell_step(yy_shell *s, int K, hipStream_t st)
 {
-    if (!s->have_params) return YY_ERR_STATE;
+    if (!s->have_params || walls_stale(s)) return YY_ERR_STATE;
     if (s->sticky != YY_OK) return s->sticky;
     return s->L.prec == YY_FP64 ? step_impl<double>(s, K, -1.0, nullptr, st) : step_impl<float>(s, K, -1.0, nullptr, st);
 }
@@ -1286,6 +1355,8 @@ int yy_ensemble_step(yy_ensemble *e, int32_t K, int32_t graph, hipStream_t strea
         const int st = capture(e, K);
         if (st != YY_OK) return st;
     }
+    for (yy_shell *s : e->sh)
+        if (walls_stale(s)) return YY_ERR_STATE;
     if (hipGraphLaunch(e->exec[e->phase], stream) != hipSuccess) return YY_ERR_HIP;
     for (yy_shell *s : e->sh) shell_rotate(s);
     e->phase = (e->phase + 1) % 6;

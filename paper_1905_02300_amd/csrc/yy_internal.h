@@ -114,6 +114,13 @@ template <typename R> struct State {
     R *cb;                   // Thomas scratch (c')
 };
 
+// Dirichlet wall data of one level: T, u_r, u_theta, u_phi x (wall at R1,
+// wall at R2), each [patch][j+1][k+1] doubles at the field's own (theta,
+// phi) positions, or null (T = the constant wall temperature, u = 0)
+struct WallLev {
+    const double *v[4][2];
+};
+
 constexpr int NBMAX = 16384;     // partial-sum slots per patch (grid limit of norm launches)
 constexpr int SWEEP_BLOCKS = 1024;   // blocks per patch of a sweep (each loops over its tasks)
 constexpr int NSLOT = 10;        // norm slots
@@ -124,7 +131,7 @@ template <typename R> struct Ops {
     static void copy_levels(const Dims &d, const State<R> &s, int from, int to, hipStream_t st);
     static void fill(const Dims &d, const State<R> &s, int level, const FillScalar *cc, int ncc,
                      const FillVector *vt, int nvt, const FillVector *vp, int nvp,
-                     double t_in, double t_out, int patch_mask, hipStream_t st);
+                     double t_in, double t_out, const WallLev &walls, int patch_mask, hipStream_t st);
     static void residual(const Dims &d, const Geo<R> &g, const State<R> &s, int field, R *out,
                          hipStream_t st);
     // one sweep; mode 0: y = solve(x); mode 1: psi_k += solve(x) and norm

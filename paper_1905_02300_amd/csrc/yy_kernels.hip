@@ -327,9 +327,12 @@ __global__ void k_fill_vector(Dims d, const FillVector *__restrict__ tab, int nt
 
 // Walls r = R1, R2 (eq. eq_ns, eq_heat_convec): u_r = 0 on the wall faces;
 // reflection ghosts psi_{-1} = 2 psi_wall - psi_0 for T and the tangential
-// velocities.  Thread = padded (j, k) point of patch blockIdx.y.
+// velocities, psi_wall from the level's wall data where given (else the
+// constant wall temperature, zero velocity); u_r takes the wall value on
+// its wall faces.  Both velocity systems take the same data.  Thread =
+// padded (j, k) point of patch blockIdx.y.
 template <typename R>
-__global__ void k_walls(Dims d, State<R> s, int lev, R t_in, R t_out, int pmask)
+__global__ void k_walls(Dims d, State<R> s, int lev, R t_in, R t_out, WallLev w, int pmask)
 {
     const int p = blockIdx.y;
     if (!((pmask >> p) & 1)) return;
@@ -339,24 +342,28 @@ __global__ void k_walls(Dims d, State<R> s, int lev, R t_in, R t_out, int pmask)
     const int j = t / nk - 1, k = t % nk - 1;
     const int64_t q0 = ix(d, p, 0, j, k), qm = q0 - d.sI;
     const int64_t q1 = ix(d, p, d.nr - 1, j, k), qp = q1 + d.sI;
+    const int64_t wq = ((int64_t)p * nj + (j + 1)) * nk + (k + 1);
+    auto wv = [&](int c, int side, R dflt) { return w.v[c][side] ? (R)w.v[c][side][wq] : dflt; };
     R *T = s.T[lev];
-    T[qm] = R(2) * t_in - T[q0];
-    T[qp] = R(2) * t_out - T[q1];
+    T[qm] = R(2) * wv(0, 0, t_in) - T[q0];
+    T[qp] = R(2) * wv(0, 1, t_out) - T[q1];
+    const R a0 = wv(2, 0, R(0)), a1 = wv(2, 1, R(0)), b0 = wv(3, 0, R(0)), b1 = wv(3, 1, R(0));
+    const R c0 = wv(1, 0, R(0)), c1 = wv(1, 1, R(0));
     for (int y = 0; y < 2; y++) {
         R *a = s.u[y][1][lev], *b = s.u[y][2][lev], *c = s.u[y][0][lev];
-        a[qm] = -a[q0];
-        a[qp] = -a[q1];
-        b[qm] = -b[q0];
-        b[qp] = -b[q1];
-        c[q0] = R(0);
-        c[ix(d, p, d.nr, j, k)] = R(0);
+        a[qm] = R(2) * a0 - a[q0];
+        a[qp] = R(2) * a1 - a[q1];
+        b[qm] = R(2) * b0 - b[q0];
+        b[qp] = R(2) * b1 - b[q1];
+        c[q0] = c0;
+        c[ix(d, p, d.nr, j, k)] = c1;
     }
 }
 
 template <typename R>
 void Ops<R>::fill(const Dims &d, const State<R> &s, int lev, const FillScalar *cc, int ncc,
                   const FillVector *vt, int nvt, const FillVector *vp, int nvp, double t_in,
-                  double t_out, int pmask, hipStream_t st)
+                  double t_out, const WallLev &walls, int pmask, hipStream_t st)
 {
     const int pl = lev == 0 ? 0 : 1;     // pressure keeps levels n and k
     // centre-type scalars: T, p1, p2 (radial 0..nr-1); u_r (faces 1..nr-1)
@@ -381,7 +388,7 @@ void Ops<R>::fill(const Dims &d, const State<R> &s, int lev, const FillScalar *c
     }
     n = (d.np + 2) * (d.nt + 2);
     hipLaunchKernelGGL(k_walls<R>, dim3((n + 255) / 256, 2), dim3(256), 0, st, d, s, lev, (R)t_in,
-                       (R)t_out, pmask);
+                       (R)t_out, walls, pmask);
 }
 
 // ---------------------------------------------------------------------------

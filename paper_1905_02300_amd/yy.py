@@ -25,7 +25,8 @@ EXPORTS = ["yy_workspace_bytes", "yy_create", "yy_set_params", "yy_set_field", "
            "yy_internal_dims", "yy_fill", "yy_extrapolate", "yy_sweep", "yy_sweep_diffusion",
            "yy_residual", "yy_profile", "yy_profile_read", "yy_profile_name",
            "yy_ensemble_workspace_bytes", "yy_ensemble_create", "yy_ensemble_shell",
-           "yy_ensemble_step", "yy_ensemble_destroy", "yy_autotune", "yy_set_tuning", "yy_step_tol"]
+           "yy_ensemble_step", "yy_ensemble_destroy", "yy_autotune", "yy_set_tuning", "yy_step_tol",
+           "yy_set_wall"]
 NPROF = 17
 
 
@@ -65,6 +66,7 @@ def load():
     L.yy_set_field.argtypes = [vp, i32, i32, i32, vp, vp]
     L.yy_get_field.argtypes = [vp, i32, i32, i32, vp, vp]
     L.yy_set_forcing.argtypes = [vp, i32, vp, vp]
+    L.yy_set_wall.argtypes = [vp, i32, i32, i32, vp, vp]
     L.yy_step.argtypes = [vp, i32, vp]
     L.yy_step_tol.argtypes = [vp, i32, ctypes.c_double, P(i32), vp]
     L.yy_get_norms.argtypes = [vp, P(ctypes.c_double), i32, vp]
@@ -129,6 +131,7 @@ class Shell:
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: libyy.so runs on MI355X only")
         self.nr, self.nt, self.np, self.prec = nr, nt, np_, prec
+        self._keep_w = {}
         self.grid = Grid(nr, nt, np_, r1, r2, delta)
         self._owned = _handle is None
         if _handle is None:
@@ -212,6 +215,21 @@ class Shell:
         _check(load().yy_set_forcing(self.h, field, ctypes.c_void_p(t.data_ptr()),
                                      _stream_ptr(stream)), "yy_set_forcing")
         self._keep_f = t
+
+    def set_wall(self, field, level, wall, a, stream=None):
+        """Dirichlet wall data (2, nt+2, np+2) of T, u_r, u_theta or u_phi
+        (field T, U1R, U1T, U1P) for a level (0: n, 1: n-1, 2: the step's
+        target) and wall (0: R1, 1: R2); None clears the slot"""
+        import torch
+        if a is None:
+            _check(load().yy_set_wall(self.h, field, level, wall, None, _stream_ptr(stream)), "yy_set_wall")
+            return
+        t = torch.as_tensor(a, dtype=torch.float64).to(self.ws.device).contiguous()
+        if tuple(t.shape) != (2, self.nt + 2, self.np + 2):
+            raise ValueError("wall data shape")
+        _check(load().yy_set_wall(self.h, field, level, wall, ctypes.c_void_p(t.data_ptr()),
+                                  _stream_ptr(stream)), "yy_set_wall")
+        self._keep_w[(field, level, wall)] = t    # alive until the stream has copied it
 
     def step(self, K, stream=None):
         _check(load().yy_step(self.h, K, _stream_ptr(stream)), "yy_step")

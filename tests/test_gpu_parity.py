@@ -231,6 +231,63 @@ def test_step_tol_parity(oracle_lib, yy, mode):
         assert _rel(a, b) <= TOL, (I.FIELD_NAMES[f], _rel(a, b))
 
 
+_WALLF = (I.T, I.U1R, I.U1T, I.U1P)
+
+
+def _set_paper_walls(o, g, grid, level, t):
+    for f in _WALLF:
+        w = I.wall_values(grid, t, f, "paper")
+        for side in (0, 1):
+            o.set_wall(f, level, side, w[side])
+            g.set_wall(f, level, side, w[side])
+
+
+@pytest.mark.parametrize("mode,tol", [(0, None), (1, None), (0, 2.6e-7)])
+def test_step_parity_paper_mms_walls(oracle_lib, yy, mode, tol):
+    """The paper's manufactured solution (eq. Exact: R1=1, R2=2, Ra=Pr=1)
+    with its time-dependent, non-zero wall data: 12x24x72, tau = 2e-3,
+    4 steps, fixed K=3 (additive and multiplicative) or the tolerance loop."""
+    print(f"case: paper mms walls mode {mode} tol {tol}", flush=True)
+    nr, nt, np_, dt, pr, ra = 12, 24, 72, 2e-3, 1.0, 1.0
+    o = oracle_lib.Shell(nr, nt, np_, 1.0, 2.0)
+    g = yy.Shell(nr, nt, np_, 1.0, 2.0)
+    o.set_params(pr=pr, ra=ra, tau=dt, chi=1.0, t_inner=0.0, t_outer=0.0)
+    o.set_mode(mode)
+    g.set_params(pr=pr, ra=ra, dt=dt, chi=1.0, t_inner=0.0, t_outer=0.0, mode=mode)
+    grid = I.Grid(nr, nt, np_, 1.0, 2.0)
+    for lev, t in ((0, 0.0), (1, -dt)):
+        st = I.mms_state(grid, t, kind="paper")
+        for f in range(9):
+            if lev == 1 and f in (I.P1, I.P2):
+                continue
+            o.set_field(f, lev, st[f])
+            g.set_field(f, lev, st[f])
+        _set_paper_walls(o, g, grid, lev, t)
+    for s in range(4):
+        for f in _WALLF:
+            a = I.mms_forcing(grid, (s + 0.5) * dt, f, pr, ra, kind="paper")
+            o.set_forcing(f, a)
+            g.set_forcing(f, a)
+        _set_paper_walls(o, g, grid, 2, (s + 1) * dt)
+        if tol is None:
+            o.step(3)
+            g.step(3)
+        else:
+            ko = o.step_tol(20, tol)
+            kg = g.step_tol(20, tol)
+            mx = o.norms(ko)[:, :, :9].max(axis=(1, 2))
+            assert mx[-1] < 0.9 * tol and (ko == 1 or mx[-2] > 1.1 * tol), mx
+            assert kg == ko, (s, kg, ko)
+    for f in range(9):
+        a = g.get_field(f).cpu().numpy()
+        b = o.get_field(f)
+        assert _rel(a, b) <= TOL, (I.FIELD_NAMES[f], _rel(a, b))
+    # wall data in use: the next step needs the iterate's wall values first
+    with pytest.raises(yy.YYError) as e:
+        g.step(3)
+    assert e.value.status == yy.YY_ERR_STATE
+
+
 def test_step_parity_convection(oracle_lib, yy):
     """Convection start (conductive T + seeded noise, hydrostatic p, T(R1)=1)
     at Ra=1e5, dt=2e-4, 3 Schwarz iterations, 2 steps."""
