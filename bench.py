@@ -12,6 +12,7 @@ from HIP events, the roofline of the dominant kernel, and the oracle's
 CPU baseline on a bounded sample).
 """
 import argparse
+import math
 import json
 import os
 import sys
@@ -85,12 +86,21 @@ def main():
                     help="batched ensemble of N shells (uneven sizes, seed 5), FP32-mixed, graph-captured")
     ap.add_argument("--mixed-error", type=int, default=0,
                     help="run FP64 and FP32-mixed side by side for N steps and report their difference")
+    ap.add_argument("--paper-mms", action="store_true",
+                    help="time and space convergence on the paper's manufactured solution with its wall data")
+    ap.add_argument("--mms-taus", default="0.01,0.005,0.0025", help="time steps of the --paper-mms time study")
+    ap.add_argument("--mms-delta", type=float, default=0.0,
+                    help="overlap of the --paper-mms grids (radians; 0: one cell)")
+    ap.add_argument("--mms-tf", type=float, default=1.0, help="final time of the --paper-mms time study")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     if args.mixed_error:
         mixed_error(args)
+        return
+    if args.paper_mms:
+        paper_mms(args)
         return
     if args.ensemble:
         ensemble(args)
@@ -181,6 +191,95 @@ def main():
         "last_step_norms_k_last": {"div_u2": float(norms[-1, :, 9].max()),
                                    "dT": float(norms[-1, :, 0].max())},
     }
+    print(json.dumps(out), flush=True)
+
+
+def _paper_run(nr, nt, np_, tau, tf, delta, tol=1e-6, kmax=64):
+    """The manufactured solution of the paper's numerical tests (eq. Exact:
+    R1=1, R2=2, Ra=Pr=1, chi=1, FP64, additive Schwarz) from its exact
+    levels at t=0 and -tau, with its time-dependent wall data and forcing,
+    Schwarz iterations until every increment norm < tol (the paper's stop
+    test with its 1e-6); returns the l2 and max errors of u2, p2, T at tf."""
+    import torch
+    from paper_1905_02300_amd import inputs as I
+    from paper_1905_02300_amd import yy
+    pr, ra, kind = 1.0, 1.0, "paper"
+    grid = I.Grid(nr, nt, np_, 1.0, 2.0, delta)
+    sh = yy.Shell(nr, nt, np_, 1.0, 2.0, delta)
+    sh.set_params(pr=pr, ra=ra, dt=tau, chi=1.0, t_inner=0.0, t_outer=0.0)
+    dev = sh.ws.device
+    wf = (I.T, I.U1R, I.U1T, I.U1P)
+    walls = {f: torch.as_tensor(I.wall_parts(grid, f, kind), device=dev) for f in wf}
+    parts = {f: [torch.as_tensor(x, device=dev) for x in I.forcing_parts(grid, f, pr, ra, kind=kind)]
+             for f in wf}
+    for lev, t in ((0, 0.0), (1, -tau)):
+        st = I.mms_state(grid, t, kind=kind)
+        for f in range(9):
+            if lev == 1 and f in (I.P1, I.P2):
+                continue
+            sh.set_field(f, lev, st[f])
+        a = I.time_factor(kind, t)[0]
+        for f in wf:
+            for side in (0, 1):
+                sh.set_wall(f, lev, side, a * walls[f][side])
+    nsteps = int(round(tf / tau))
+    iters = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(nsteps):
+        a, da = I.time_factor(kind, (s + 0.5) * tau)
+        for f in wf:
+            A, B, C = parts[f]
+            sh.set_forcing(f, a * A + da * B + (a * a) * C)
+        a1 = I.time_factor(kind, (s + 1) * tau)[0]
+        for f in wf:
+            for side in (0, 1):
+                sh.set_wall(f, 2, side, a1 * walls[f][side])
+        iters.append(sh.step_tol(kmax, tol))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    r, th, _ = grid.axes(I.T)
+    vol = (r[None, :, None, None] ** 2 * np.sin(th)[None, None, :, None] * grid.dr * grid.dth * grid.dph)
+    err = {}
+    for f, name in ((I.U2R, "u_r"), (I.U2T, "u_theta"), (I.U2P, "u_phi"), (I.P2, "p"), (I.T, "T")):
+        e = sh.get_field(f).cpu().numpy() - I.mms_fields(grid, tf, f, kind=kind)
+        # midpoint l2 with the cell-centre volume of the nearest cell
+        ec = e[:, :grid.nr, :grid.nt, :grid.np]
+        err[name] = {"l2": float(np.sqrt(np.sum(vol * ec * ec))), "max": float(np.abs(e).max())}
+    return {"grid": [nr, nt, np_], "overlap": delta, "tau": tau, "steps": nsteps,
+            "iterations": [min(iters), max(iters)],
+            "mean_iterations": float(np.mean(iters)), "seconds": el,
+            "mcell_steps_s": grid.cells * nsteps / el / 1e6, "errors": err}
+
+
+def paper_mms(args):
+    """Second workload: the paper's manufactured solution (eq. Exact) on the
+    paper's grid 20x92x192 -- time convergence at Tf = 10 -- and a space
+    convergence study (tau = 1e-3, Tf = 0.1) on 10x46x96, 20x92x192,
+    40x184x384; prints the errors and the observed orders."""
+    out = {"workload": "paper_mms_eq_exact_R1_1_R2_2", "tol": 1e-6, "overlap": args.mms_delta,
+           "time_tf": args.mms_tf, "time": [], "space": []}
+    from paper_1905_02300_amd import yy
+
+    def run(*a):
+        try:
+            res = _paper_run(*a)
+        except yy.YYError as e:
+            res = {"grid": list(a[:3]), "tau": a[3], "overlap": a[5], "error": str(e)}
+        print(json.dumps(res), file=sys.stderr, flush=True)
+        return res
+
+    taus = [float(x) for x in args.mms_taus.split(",")]
+    out["time"] = [run(20, 92, 192, tau, args.mms_tf, args.mms_delta) for tau in taus]
+    out["space"] = [run(10 * m, 46 * m, 96 * m, 1e-3, 0.1, args.mms_delta) for m in (1, 2, 4)]
+    for key in ("time", "space"):
+        runs = [r for r in out[key] if "errors" in r]
+        if len(runs) < 2:
+            continue
+        out[key + "_orders"] = {
+            name: [math.log2(runs[q]["errors"][name]["l2"] / runs[q + 1]["errors"][name]["l2"])
+                   for q in range(len(runs) - 1)]
+            for name in runs[0]["errors"]}
     print(json.dumps(out), flush=True)
 
 

@@ -248,29 +248,42 @@ def mms_fields(grid, t, field, padded=False, kind="shell"):
     return out
 
 
-def mms_forcing(grid, t, field, pr, ra, padded=False, kind="shell"):
-    """Forcing at time t that makes the manufactured solution exact:
-    f_u = du/dt + (u.grad)u + grad p - Pr lap u - Pr Ra T e_r,
+def time_factor(kind, t):
+    """(a(t), a'(t)): every field of a manufactured solution is a(t) times
+    its spatial part"""
+    return _TIME[kind][0](t), _TIME[kind][1](t)
+
+
+def forcing_parts(grid, field, pr, ra, padded=False, kind="shell"):
+    """Spatial parts (A, B, C) of the forcing that makes the manufactured
+    solution exact, f(t) = a(t) A + a'(t) B + a(t)^2 C, from
+    f_u = du/dt + (u.grad)u + grad p - Pr lap u - Pr Ra T e_r and
     f_T = dT/dt + u.grad T - lap T  (field T, U1R, U1T or U1P)."""
     shape = (2, grid.nr + 2, grid.nt + 2, grid.np + 2) if padded else grid.mac_shape(field)
-    out = np.zeros(shape)
-    s, c = _TIME[kind][0](t), _TIME[kind][1](t)
+    A, B, C = np.zeros(shape), np.zeros(shape), np.zeros(shape)
     for patch in range(2):
         X, (er, et, ep) = points(grid, field, patch, padded)
         U, P, TH, r = _jets(kind, X, grid.r1, grid.r2)
         if field == T:
-            adv = sum(U[d].v * TH.g[d] for d in range(3))
-            out[patch] = c * TH.v + s * s * adv - s * TH.lap()
+            A[patch] = -TH.lap()
+            B[patch] = TH.v
+            C[patch] = sum(U[d].v * TH.g[d] for d in range(3))
             continue
         rhat = [X[d] / r.v for d in range(3)]
-        F = []
-        for comp in range(3):
-            adv = sum(U[d].v * U[comp].g[d] for d in range(3))
-            F.append(c * U[comp].v + s * s * adv
-                     + s * (P.g[comp] - pr * U[comp].lap() - pr * ra * TH.v * rhat[comp]))
         e = {U1R: er, U1T: et, U1P: ep}[field]
-        out[patch] = F[0] * e[0] + F[1] * e[1] + F[2] * e[2]
-    return out
+        for comp in range(3):
+            A[patch] += e[comp] * (P.g[comp] - pr * U[comp].lap() - pr * ra * TH.v * rhat[comp])
+            B[patch] += e[comp] * U[comp].v
+            C[patch] += e[comp] * sum(U[d].v * U[comp].g[d] for d in range(3))
+    return A, B, C
+
+
+def mms_forcing(grid, t, field, pr, ra, padded=False, kind="shell"):
+    """Forcing at time t that makes the manufactured solution exact (see
+    forcing_parts)."""
+    a, da = time_factor(kind, t)
+    A, B, C = forcing_parts(grid, field, pr, ra, padded, kind)
+    return a * A + da * B + (a * a) * C
 
 
 def mms_state(grid, t, padded=False, kind="shell"):
@@ -286,14 +299,18 @@ def wall_values(grid, t, field, kind="paper"):
     or U1P) at time t on the walls r = R1 (index 0) and r = R2 (index 1), at
     the field's own (theta, phi) positions of the padded layout: shape
     (2 walls, 2 patches, nt+2, np+2)."""
+    return _TIME[kind][0](t) * wall_parts(grid, field, kind)
+
+
+def wall_parts(grid, field, kind="paper"):
+    """Spatial part of wall_values (the values at a(t) = 1)."""
     _, th, ph = grid.axes(field, padded=True)
     out = np.zeros((2, 2, grid.nt + 2, grid.np + 2))
-    s = _TIME[kind][0](t)
     for w, r in enumerate((grid.r1, grid.r2)):
         for patch in range(2):
             X, e = _frame_points(np.array([r]), th, ph, patch)
             U, P, TH = _values(kind, X, grid.r1, grid.r2)
-            out[w, patch] = s * _field_value(field, U, P, TH, e)[0]
+            out[w, patch] = _field_value(field, U, P, TH, e)[0]
     return out
 
 
