@@ -44,6 +44,7 @@ struct yyo {
     double dr, dth, dph, th0, ph0, th1;
     double pr, ra, tau, chi, t_in, t_out;
     int mode;
+    int mass_fix;                /* Algorithm step 4 on every velocity fill */
     int64_t npatch;              /* doubles per patch array */
     double *lev[YYO_NF][NLEV];   /* levels n, n-1, working iterate k */
     double *star[YYO_NF];        /* 1.5 psi^n - 0.5 psi^{n-1} */
@@ -302,6 +303,14 @@ int yyo_set_mode(yyo *h, int mode)
     return 0;
 }
 
+int yyo_set_mass_fix(yyo *h, int on)
+{
+    if (!h || (on != 0 && on != 1)) return -1;
+    h->mass_fix = on;
+    h->filled = 0;
+    return 0;
+}
+
 int64_t yyo_field_count(const yyo *h, int field, int layout)
 {
     if (!h || field < 0 || field >= YYO_NF) return -1;
@@ -463,6 +472,61 @@ static void wall_rules(const yyo *h, int level, int p)
         }
 }
 
+/* Algorithm step 4 (mass-flux correction of the interpolated boundary
+ * data).  With F(v) the net outward flux of the patch's interpolated
+ * boundary normal velocities v (u_theta on the theta-boundary faces, u_phi
+ * on the phi-boundary faces) and F_r that of the wall data, the functional
+ *   J(v) = |v - u_bd|^2 / 2 + (F(v) + F_r)^2 / (2 eps |dOmega|^2)
+ * is quadratic with the Hessian I + c a a^T (a = the faces' flux weights
+ * with their outward signs).  Its minimiser, the limit of the conjugate
+ * gradient iteration, is v = u_bd - kappa a with
+ *   kappa = (F(u_bd) + F_r) / (eps |dOmega|^2 + a.a);
+ * here eps -> 0, so the corrected data carry no net flux.  The flux weights
+ * are the face areas of the discrete divergence: r-face r_f^2 sin(theta_j)
+ * dtheta dphi, theta-face r_i sin(theta_f) dr dphi, phi-face r_i dr dtheta,
+ * so that the volume-weighted sum of Div_h over the patch telescopes to
+ * exactly this boundary flux. */
+static void mass_fix(yyo *h, int level, int p)
+{
+    const int nr = h->nr, nt = h->nt, np = h->np;
+    for (int s = 0; s < 2; s++) {
+        double *ur = h->lev[s == 0 ? YYO_U1R : YYO_U2R][level];
+        double *ut = h->lev[s == 0 ? YYO_U1T : YYO_U2T][level];
+        double *up = h->lev[s == 0 ? YYO_U1P : YYO_U2P][level];
+        double F = 0.0, S = 0.0;
+        for (int j = 0; j < nt; j++)
+            for (int k = 0; k < np; k++) {
+                const double a0 = rf(h, 0) * rf(h, 0) * sin(tc(h, j)) * h->dth * h->dph;
+                const double a1 = rf(h, nr) * rf(h, nr) * sin(tc(h, j)) * h->dth * h->dph;
+                F += a1 * ur[ix(h, p, nr, j, k)] - a0 * ur[ix(h, p, 0, j, k)];
+            }
+        for (int i = 0; i < nr; i++) {
+            for (int k = 0; k < np; k++) {
+                const double a0 = rc(h, i) * sin(tf(h, 0)) * h->dr * h->dph;
+                const double a1 = rc(h, i) * sin(tf(h, nt)) * h->dr * h->dph;
+                F += a1 * ut[ix(h, p, i, nt, k)] - a0 * ut[ix(h, p, i, 0, k)];
+                S += a0 * a0 + a1 * a1;
+            }
+            for (int j = 0; j < nt; j++) {
+                const double a = rc(h, i) * h->dr * h->dth;
+                F += a * (up[ix(h, p, i, j, np)] - up[ix(h, p, i, j, 0)]);
+                S += 2.0 * a * a;
+            }
+        }
+        const double kappa = F / S;
+        for (int i = 0; i < nr; i++) {
+            for (int k = 0; k < np; k++) {
+                ut[ix(h, p, i, 0, k)] += kappa * rc(h, i) * sin(tf(h, 0)) * h->dr * h->dph;
+                ut[ix(h, p, i, nt, k)] -= kappa * rc(h, i) * sin(tf(h, nt)) * h->dr * h->dph;
+            }
+            for (int j = 0; j < nt; j++) {
+                up[ix(h, p, i, j, 0)] += kappa * rc(h, i) * h->dr * h->dth;
+                up[ix(h, p, i, j, np)] -= kappa * rc(h, i) * h->dr * h->dth;
+            }
+        }
+    }
+}
+
 static void fill_patch(yyo *h, int level, int pa)
 {
     struct fill_ctx c = { h, level, pa };
@@ -471,6 +535,7 @@ static void fill_patch(yyo *h, int level, int pa)
     for_targets(h, FT, fill_vector_target, &c);
     for_targets(h, FP, fill_vector_target, &c);
     wall_rules(h, level, pa);
+    if (h->mass_fix) mass_fix(h, level, pa);
 }
 
 /* Additive: both patches read the other's values of the same iterate.

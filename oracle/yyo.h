@@ -46,6 +46,10 @@ int yyo_set_params(yyo *h, double pr, double ra, double tau, double chi,
                    double t_inner, double t_outer);
 /* 0 = additive Schwarz (default), 1 = multiplicative (Yin then Yang) */
 int yyo_set_mode(yyo *h, int mode);
+/* 1: correct the interpolated boundary normal velocities of every velocity
+ * fill so that each patch's boundary carries no net mass flux (Algorithm
+ * step 4, optional in the paper); 0 (default): off */
+int yyo_set_mass_fix(yyo *h, int on);
 int64_t yyo_field_count(const yyo *h, int field, int layout);
 int yyo_set_field(yyo *h, int field, int level, int layout, const double *src);
 int yyo_get_field(const yyo *h, int field, int level, int layout, double *dst);

@@ -33,6 +33,7 @@ def lib():
         L.yyo_destroy.argtypes = [vp]
         L.yyo_set_params.argtypes = [vp, d, d, d, d, d, d]
         L.yyo_set_mode.argtypes = [vp, i]
+        L.yyo_set_mass_fix.argtypes = [vp, i]
         L.yyo_field_count.restype = ctypes.c_int64
         L.yyo_field_count.argtypes = [vp, i, i]
         L.yyo_set_field.argtypes = [vp, i, i, i, dp]
@@ -143,6 +144,10 @@ class Shell:
         a = _f64(a)
         assert a.shape == self.mac_shape(field)
         lib().yyo_set_forcing(self.h, field, _ptr(a))
+
+    def set_mass_fix(self, on):
+        if lib().yyo_set_mass_fix(self.h, 1 if on else 0) != 0:
+            raise RuntimeError("set_mass_fix failed")
 
     def set_wall(self, field, level, wall, a):
         """Dirichlet wall data (2, nt+2, np+2) of T, u_r, u_theta or u_phi
