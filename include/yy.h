@@ -142,6 +142,17 @@ int yy_set_forcing(yy_shell *s, int32_t field, const double *dev_src, hipStream_
 int yy_set_wall(yy_shell *s, int32_t field, int32_t level, int32_t wall, const double *dev_src,
                 hipStream_t stream);
 
+/* Algorithm step 4 (Sec. 4, optional in the paper): on = 1 corrects, after
+ * every velocity fill and for both systems, the interpolated boundary
+ * normal velocities of each patch (u_theta on its theta-boundary faces,
+ * u_phi on its phi-boundary faces) so that, with the wall data, the
+ * patch's boundary carries no net mass flux.  The correction is the
+ * minimiser of the paper's functional J in the limit of a vanishing
+ * penalty parameter: v = u_bd - (F / a.a) a, with a the faces' outward
+ * flux weights (the face areas of Div_h) and F the net flux.  on = 0
+ * (default) turns it off.  Errors: YY_ERR_ARG. */
+int yy_set_mass_fix(yy_shell *s, int32_t on);
+
 /* Advance one time step n -> n+1 with n_schwarz Schwarz iterations
  * (Sec. 4 Algorithm with the splitting-error reduction eq. er): per
  * iteration, refresh every field's ghosts from the other patch, solve T,

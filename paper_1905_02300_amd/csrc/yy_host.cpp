@@ -27,7 +27,7 @@ struct Layout {
     int64_t ncc, nvt, nvp;   // interpolation targets per class
     // byte offsets
     int64_t off_fields, off_p, off_tab_r, off_tab_d, off_ptab_r, off_ptab_d, off_fill, off_partial,
-        off_norms, off_wall, total;
+        off_norms, off_wall, off_mf, total;
     int64_t wall_elems;      // doubles of one wall-data slot: 2 (nt+2)(np+2)
     int64_t elem;            // bytes per compute element
     int nR;                  // compute-precision arrays
@@ -92,6 +92,8 @@ Layout make_layout(const yy_grid *g, int prec)
     L.wall_elems = 2 * (int64_t)(g->nt + 2) * (g->np + 2);
     L.off_wall = o;
     o += 24 * align_up(L.wall_elems * 8, ALIGN);
+    L.off_mf = o;
+    o += align_up((int64_t)4 * MF_BLOCKS * 8, ALIGN);
     L.total = o;
     return L;
 }
@@ -406,6 +408,10 @@ struct yy_shell {
     double *wall[4][3][2];
     bool wall_on[4][3][2] = {};
     bool wall_fresh[4][2] = {};
+    // Algorithm step 4 on every velocity fill
+    bool mass_fix = false;
+    double mf_S = 0.0;           // sum of the squared boundary flux weights
+    double *mfp = nullptr;       // partial net fluxes
 };
 
 namespace {
@@ -496,6 +502,7 @@ template <typename R> void do_fill(yy_shell *s, int lev, int pmask, hipStream_t 
     Timed tm(s, PC_FILL, st);
     Ops<R>::fill(s->L.d, state_of<R>(s), lev, s->fcc, (int)s->L.ncc, s->fvt, (int)s->L.nvt, s->fvp,
                  (int)s->L.nvp, s->prm.t_inner, s->prm.t_outer, walls_of(s, lev), pmask, st);
+    if (s->mass_fix) Ops<R>::mass_fix(s->L.d, s->gd, state_of<R>(s), lev, s->mf_S, s->mfp, pmask, st);
 }
 
 template <typename R> void solve_field(yy_shell *s, const Dims &d, int f, hipStream_t st)
@@ -733,6 +740,19 @@ int yy_create(const yy_grid *g, int32_t prec, void *dev_ws, uint64_t ws_bytes, y
         for (int l = 0; l < 3; l++)
             for (int w = 0; w < 2; w++)
                 s->wall[c][l][w] = (double *)(s->ws + L.off_wall + ((c * 3 + l) * 2 + w) * align_up(L.wall_elems * 8, ALIGN));
+    s->mfp = (double *)(s->ws + L.off_mf);
+    {
+        // squared flux weights of the interpolated boundary faces (theta- and
+        // phi-boundary), the same for both patches
+        double S = 0.0;
+        const double s0 = std::sin(F.th0), s1 = std::sin(F.th0 + L.d.nt * F.dth);
+        for (int i = 0; i < L.d.nr; i++) {
+            const double rc = F.r1 + (i + 0.5) * F.dr;
+            const double a0 = rc * s0 * F.dr * F.dph, a1 = rc * s1 * F.dr * F.dph, a2 = rc * F.dr * F.dth;
+            S += L.d.np * (a0 * a0 + a1 * a1) + 2.0 * L.d.nt * a2 * a2;
+        }
+        s->mf_S = S;
+    }
     for (int q = 0; q < NSLOT; q++) s->nblocks[q] = 0;
     *out = s;
     return YY_OK;
@@ -827,6 +847,15 @@ int yy_set_forcing(yy_shell *s, int32_t field, const double *src, hipStream_t st
         if (src) Ops<float>::io(s->L.d, (float *)s->force_ptr[c], src, nullptr, loc, YY_MAC, st);
     }
     return hip_status(hipGetLastError());
+}
+
+int yy_set_mass_fix(yy_shell *s, int32_t on)
+{
+    if (!s || (on != 0 && on != 1)) return YY_ERR_ARG;
+    if ((on != 0) != s->mass_fix) s->version++;
+    s->mass_fix = on != 0;
+    s->need_fill = true;
+    return YY_OK;
 }
 
 int yy_set_wall(yy_shell *s, int32_t field, int32_t level, int32_t wall, const double *src, hipStream_t st)

@@ -121,6 +121,7 @@ struct WallLev {
     const double *v[4][2];
 };
 
+constexpr int MF_BLOCKS = 128;       // partial sums per (system, patch) of the mass-flux step
 constexpr int NBMAX = 16384;     // partial-sum slots per patch (grid limit of norm launches)
 constexpr int SWEEP_BLOCKS = 1024;   // blocks per patch of a sweep (each loops over its tasks)
 constexpr int NSLOT = 10;        // norm slots
@@ -143,6 +144,11 @@ template <typename R> struct Ops {
                          hipStream_t st);
     static void io(const Dims &d, R *internal, const double *ext, double *ext_out, int field_loc,
                    int layout, hipStream_t st);
+    // Algorithm step 4 on a filled velocity level: make each patch's boundary
+    // normal data carry no net mass flux (both systems); partial: 4 * MF_BLOCKS
+    // doubles of scratch; S = sum of the squared boundary flux weights
+    static void mass_fix(const Dims &d, const Geo<double> &gd, const State<R> &s, int level,
+                         double S, double *partial, int patch_mask, hipStream_t st);
 };
 void io_double(const Dims &d, double *internal, const double *ext, double *ext_out, int field_loc,
                int layout, hipStream_t st);

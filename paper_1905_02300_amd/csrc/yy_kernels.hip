@@ -1504,6 +1504,108 @@ void io_double(const Dims &d, double *internal, const double *src, double *dst, 
     hipLaunchKernelGGL(k_io<double>, dim3(grid_for(n)), dim3(256), 0, st, d, internal, src, dst, loc, layout);
 }
 
+// ---------------------------------------------------------------------------
+// Algorithm step 4 (mass-flux correction of the interpolated boundary data).
+// The net outward flux F of a patch's boundary normal data -- u_r on the
+// wall faces (Dirichlet data), u_theta on the theta-boundary faces and u_phi
+// on the phi-boundary faces (interpolated) -- with the face areas of Div_h
+// as weights (r-face r_f^2 sin(theta_j) dtheta dphi, theta-face r_i
+// sin(theta_f) dr dphi, phi-face r_i dr dtheta) is removed by the least
+// change of the interpolated faces: v = u - (F / S) a, a = outward weights,
+// S = a.a.  This is the minimiser of the paper's functional J (quadratic,
+// Hessian I + c a a^T, so its conjugate-gradient iteration ends there) in
+// the limit of its penalty parameter going to zero.
+// ---------------------------------------------------------------------------
+struct MfFace {
+    int kind, i, j, k;   // 0: r-wall, 1: theta-boundary, 2: phi-boundary face
+    double w;            // outward flux weight
+};
+
+__device__ __forceinline__ MfFace mf_face(const Dims &d, const Geo<double> &g, int64_t t)
+{
+    MfFace f;
+    const int64_t nA = 2 * (int64_t)d.nt * d.np, nB = 2 * (int64_t)d.nr * d.np;
+    if (t < nA) {
+        const int side = (int)(t / ((int64_t)d.nt * d.np));
+        const int64_t u = t % ((int64_t)d.nt * d.np);
+        f.kind = 0; f.j = (int)(u / d.np); f.k = (int)(u % d.np); f.i = side ? d.nr : 0;
+        const double rf = g.rf[f.i + 1];
+        f.w = (side ? 1.0 : -1.0) * rf * rf * g.sc[f.j + 1] * g.dth * g.dph;
+    } else if (t < nA + nB) {
+        t -= nA;
+        const int side = (int)(t / ((int64_t)d.nr * d.np));
+        const int64_t u = t % ((int64_t)d.nr * d.np);
+        f.kind = 1; f.i = (int)(u / d.np); f.k = (int)(u % d.np); f.j = side ? d.nt : 0;
+        f.w = (side ? 1.0 : -1.0) * g.rc[f.i + 1] * g.sf[f.j + 1] * g.dr * g.dph;
+    } else {
+        t -= nA + nB;
+        const int side = (int)(t / ((int64_t)d.nr * d.nt));
+        const int64_t u = t % ((int64_t)d.nr * d.nt);
+        f.kind = 2; f.i = (int)(u / d.nt); f.j = (int)(u % d.nt); f.k = side ? d.np : 0;
+        f.w = (side ? 1.0 : -1.0) * g.rc[f.i + 1] * g.dr * g.dth;
+    }
+    return f;
+}
+
+__device__ __forceinline__ int64_t mf_count(const Dims &d)
+{
+    return 2 * ((int64_t)d.nt * d.np + (int64_t)d.nr * d.np + (int64_t)d.nr * d.nt);
+}
+
+// blockIdx.y = patch, blockIdx.z = system: partial net fluxes
+template <typename R>
+__global__ void __launch_bounds__(256) k_mflux(Dims d, Geo<double> g, State<R> s, int lev, double *partial,
+                                               int pmask)
+{
+    const int p = blockIdx.y, y = blockIdx.z;
+    if (!((pmask >> p) & 1)) return;
+    const R *ur = s.u[y][0][lev], *ut = s.u[y][1][lev], *up = s.u[y][2][lev];
+    const int64_t n = mf_count(d);
+    double acc = 0.0;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const MfFace f = mf_face(d, g, t);
+        const R *a = f.kind == 0 ? ur : (f.kind == 1 ? ut : up);
+        acc += f.w * (double)a[ix(d, p, f.i, f.j, f.k)];
+    }
+    const double tot = block_sum(acc);
+    if (threadIdx.x == 0) partial[(y * 2 + p) * MF_BLOCKS + blockIdx.x] = tot;
+}
+
+// every block sums the partials (fixed order), then corrects its faces
+template <typename R>
+__global__ void __launch_bounds__(256) k_mfix(Dims d, Geo<double> g, State<R> s, int lev, double S,
+                                              const double *partial, int pmask)
+{
+    const int p = blockIdx.y, y = blockIdx.z;
+    if (!((pmask >> p) & 1)) return;
+    __shared__ double kap;
+    if (threadIdx.x < 64) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < MF_BLOCKS; b += 64) v += partial[(y * 2 + p) * MF_BLOCKS + b];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if (threadIdx.x == 0) kap = v / S;
+    }
+    __syncthreads();
+    R *ut = s.u[y][1][lev], *up = s.u[y][2][lev];
+    const int64_t nA = 2 * (int64_t)d.nt * d.np, n = mf_count(d);
+    for (int64_t t = nA + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const MfFace f = mf_face(d, g, t);
+        R *a = f.kind == 1 ? ut : up;
+        const int64_t q = ix(d, p, f.i, f.j, f.k);
+        a[q] = (R)((double)a[q] - kap * f.w);
+    }
+}
+
+template <typename R>
+void Ops<R>::mass_fix(const Dims &d, const Geo<double> &gd, const State<R> &s, int lev, double S,
+                      double *partial, int pmask, hipStream_t st)
+{
+    const dim3 g(MF_BLOCKS, 2, 2);
+    hipLaunchKernelGGL(k_mflux<R>, g, dim3(256), 0, st, d, gd, s, lev, partial, pmask);
+    hipLaunchKernelGGL(k_mfix<R>, dim3(64, 2, 2), dim3(256), 0, st, d, gd, s, lev, S, (const double *)partial,
+                       pmask);
+}
+
 template struct Ops<double>;
 template struct Ops<float>;
 

@@ -76,6 +76,32 @@ def test_fill_parity(oracle_lib, yy):
         assert _rel(a, b) <= 1e-14, I.FIELD_NAMES[f]
 
 
+def test_mass_fix_parity(oracle_lib, yy):
+    """Algorithm step 4 (boundary mass-flux correction after each velocity
+    fill): one fill of random data, then 3 manufactured steps (K=2), with
+    the correction on in both stacks."""
+    print("case: mass fix 6x16x48 and 12x24x72", flush=True)
+    o, g = _pair(oracle_lib, yy, 6, 16, 48, t_inner=1.0, t_outer=0.3)
+    o.set_mass_fix(True)
+    g.set_mass_fix(True)
+    rng = np.random.default_rng(23)
+    _set_random(o, g, rng, [0])
+    o.fill(0)
+    g.fill(0)
+    for f in range(9):
+        a = g.get_field(f, 0, layout=1).cpu().numpy()
+        b = o.get_field(f, 0, layout=1)
+        assert _rel(a, b) <= 1e-13, I.FIELD_NAMES[f]
+    o, g, grid = _mms_pair(oracle_lib, yy, 12, 24, 72, 1e-3)
+    o.set_mass_fix(True)
+    g.set_mass_fix(True)
+    _mms_steps(o, g, grid, 1e-3, 3, 2)
+    for f in range(9):
+        a = g.get_field(f).cpu().numpy()
+        b = o.get_field(f)
+        assert _rel(a, b) <= TOL, (I.FIELD_NAMES[f], _rel(a, b))
+
+
 @pytest.mark.parametrize("field", [I.T, I.U1R, I.U1T, I.U1P, I.U2R, I.U2T, I.U2P])
 @pytest.mark.parametrize("d", [0, 1, 2])
 def test_sweep_parity(oracle_lib, yy, field, d):
