@@ -1099,11 +1099,18 @@ extern "C" int yy_autotune(yy_shell *s, char *json_out, int32_t cap, hipStream_t
             std::snprintf(key, sizeof key, "%s.%c", tune_field_name[L], dir_name[dir]);
             char val[32];
             if (dir < 2) {
-                int bm = 0, bw = 0;
-                double best = 1e30;
+                // the per-line Thomas kernel, then every partitioned tile
+                // that fits the lines
+                const int n = (dir == 0 ? s->L.d.nr : s->L.d.nt) - (L == dir + 1 ? 1 : 0);
+                T.m[L][dir] = 1;
+                T.w[L][dir] = 0;
+                int bm = 1, bw = 0;
+                double best = time_sweep(s, tune_field_id[L], dir, st, a, b);
                 const int ms[5] = {4, 6, 8, 12, 16}, ws[3] = {64, 32, 16};
                 for (int im = 0; im < 5; im++)
                     for (int iw = 0; iw < 3; iw++) {
+                        int W = 0, P = 0;
+                        if (!strided_tile(n, ms[im], ws[iw], W, P)) continue;
                         T.m[L][dir] = (int8_t)ms[im];
                         T.w[L][dir] = (int8_t)ws[iw];
                         const double t = time_sweep(s, tune_field_id[L], dir, st, a, b);
@@ -1111,7 +1118,8 @@ extern "C" int yy_autotune(yy_shell *s, char *json_out, int32_t cap, hipStream_t
                     }
                 T.m[L][dir] = (int8_t)bm;
                 T.w[L][dir] = (int8_t)bw;
-                std::snprintf(val, sizeof val, "m%dw%d", bm, bw);
+                if (bm == 1) std::snprintf(val, sizeof val, "t");
+                else std::snprintf(val, sizeof val, "m%dw%d", bm, bw);
             } else {
                 // one wave per line with 1, 2 or 4 lines per block, or 2, 4 or
                 // 8 waves per line
@@ -1163,6 +1171,11 @@ extern "C" int yy_set_tuning(yy_shell *s, const char *json)
             const char *v = js.c_str() + at + std::strlen(key);
             int m = 0, w = 0, l = 0;
             if (dir < 2) {
+                if (v[0] == 't' && v[1] == '"') {
+                    T.m[L][dir] = 1;
+                    T.w[L][dir] = 0;
+                    continue;
+                }
                 if (std::sscanf(v, "m%dw%d", &m, &w) != 2) return YY_ERR_ARG;
                 if ((m != 4 && m != 6 && m != 8 && m != 12 && m != 16) || (w != 16 && w != 32 && w != 64))
                     return YY_ERR_ARG;

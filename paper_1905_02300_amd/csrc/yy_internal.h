@@ -94,7 +94,8 @@ struct FillVector {
 };
 
 // line-solver tile choices per location (CC, FR, FT, FP); 0 = built-in
-// default.  Strided r/theta sweeps: rows per chunk m (4, 6, 8, 12, 16) and the
+// default.  Strided r/theta sweeps: rows per chunk m (4, 6, 8, 12, 16; 1 =
+// the per-line Thomas kernel) and the
 // largest lane width w (64, 32, 16); phi sweeps: one wave per line and
 // lines per block lpb (1, 2, 4), or wpl (2, 4, 8) waves per line.
 struct Tune {
@@ -157,5 +158,8 @@ void zero_doubles(double *p, int64_t n, hipStream_t st);
 // choose the register-resident partitioned line solver (default) or the
 // per-line Thomas kernel
 void set_partitioned(bool on);
+// block shape of a strided partitioned solve (lines of n, chunks <= M rows,
+// at most wmax lanes); false if it does not fit
+bool strided_tile(int n, int M, int wmax, int &W, int &P);
 
 }  // namespace yy

@@ -1151,6 +1151,24 @@ __global__ void __launch_bounds__(512) k_sweep_contig_mw(Dims d, Geo<R> g, Geo<d
     }
 }
 
+// Block shape of a strided partitioned solve of lines of n unknowns with
+// chunks of <= M rows: W lanes (consecutive k) x P chunks, W * P <= 512 and
+// a whole number of 64-lane waves, every chunk >= 2 rows.  False if the
+// line does not fit (then the per-line Thomas kernel runs).
+bool strided_tile(int n, int M, int wmax, int &W, int &P)
+{
+    P = (n + M - 1) / M;
+    if (P < 1) P = 1;
+    if (wmax != 16 && wmax != 32 && wmax != 64) wmax = 64;
+    W = wmax;
+    while (W * P > 512 && W > 8) W >>= 1;
+    const int q = 64 / W;
+    P = (P + q - 1) / q * q;
+    if (W * P > 512 || P > n) return false;
+    if (2 * P > n && n > 1) return false;
+    return true;
+}
+
 // Launch the partitioned solver when the line fits the register chunks,
 // else the per-line Thomas kernel.  Returns false if it fell back.
 template <typename R, int L, int D, int MODE, bool DIFF>
@@ -1160,29 +1178,20 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
 {
     const int i0 = ulo<L>(0), j0 = ulo<L>(1), k0 = ulo<L>(2);
     if (D < 2) {
-        // rows per chunk: tuned, else 12 for the u_theta polar sweep (the
-        // most per-row data) and 16 otherwise
+        // rows per chunk: tuned (1 = per-line Thomas), else 12 for the
+        // u_theta polar sweep (the most per-row data) and 16 otherwise
         int M = s.tune.m[L][D];
+        if (M == 1) return false;
         if (M != 4 && M != 6 && M != 8 && M != 12 && M != 16) M = (L == FT && D == 1) ? 12 : 16;
         const int n = ncell(d, D) - (D == 0 ? i0 : j0);
-        int P = (n + M - 1) / M;
-        if (P < 1) P = 1;
-        // W lanes (consecutive k) per chunk row; W * P <= 512 and a whole
-        // number of 64-lane waves
-        int wmax = s.tune.w[L][D];
-        if (wmax != 16 && wmax != 32 && wmax != 64) wmax = 64;
-        int W = wmax;
-        while (W * P > 512 && W > 8) W >>= 1;
-        const int q = 64 / W;
-        P = (P + q - 1) / q * q;
-        if (W * P > 512 || P > n) return false;
+        int W = 0, P = 0;
+        if (!strided_tile(n, M, s.tune.w[L][D], W, P)) return false;
         const int nk = d.np - k0;
         const int nother = D == 0 ? d.nt - j0 : d.nr - i0;
         int64_t tasks = (int64_t)((nk + W - 1) / W) * nother;
         int64_t b = tasks;
         if (b > SWEEP_BLOCKS) b = SWEEP_BLOCKS;
         if (nblocks) *nblocks = (int)b;
-        if (2 * P > n && n > 1) return false;
         const size_t lds = (size_t)4 * P * W * sizeof(R);
         if (M == 4)
             hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, 4>), dim3((unsigned)b, d.npatch), dim3(W, P),

@@ -414,7 +414,7 @@ def test_ensemble_graph_matches_eager(yy):
         assert np.array_equal(ens[0].shells[q].norms(), ens[1].shells[q].norms())
 
 
-@pytest.mark.parametrize("variant", ["m4w16", "m6w32", "m8w64", "m8w16", "m12w32", "m16w64", "m16w16"])
+@pytest.mark.parametrize("variant", ["t", "m4w16", "m6w32", "m8w64", "m8w16", "m12w32", "m16w64", "m16w16"])
 def test_sweep_parity_every_tile(oracle_lib, yy, variant):
     """Every tile choice the autotuner can make gives the oracle's answer."""
     print(f"case: tile {variant}", flush=True)
@@ -424,7 +424,7 @@ def test_sweep_parity_every_tile(oracle_lib, yy, variant):
     _set_random(o, g, rng, [0, 1], scale=0.5)
     o.extrapolate()
     g.extrapolate()
-    phi = {"m4w16": "v2", "m6w32": "l1", "m8w64": "l1", "m8w16": "l2", "m12w32": "l4", "m16w64": "v2",
+    phi = {"t": "v4", "m4w16": "v2", "m6w32": "l1", "m8w64": "l1", "m8w16": "l2", "m12w32": "l4", "m16w64": "v2",
            "m16w16": "v4"}[variant]
     js = "{" + ",".join(f'"{f}.{d}":"{variant}"' for f in ("T", "u_r", "u_t", "u_p") for d in "rt")
     js += "," + ",".join(f'"{f}.p":"{phi}"' for f in ("T", "u_r", "u_t", "u_p")) + "}"
