@@ -45,6 +45,7 @@ struct yyo {
     double pr, ra, tau, chi, t_in, t_out;
     int mode;
     int mass_fix;                /* Algorithm step 4 on every velocity fill */
+    double t_bc[2][2];           /* T walls: a T + b dT/dn = g, (a, b) per wall */
     int64_t npatch;              /* doubles per patch array */
     double *lev[YYO_NF][NLEV];   /* levels n, n-1, working iterate k */
     double *star[YYO_NF];        /* 1.5 psi^n - 0.5 psi^{n-1} */
@@ -265,6 +266,7 @@ yyo *yyo_create(int nr, int nt, int np, double r1, double r2, double delta)
         h->star[f] = (double *)calloc(1, bytes);
     }
     for (int c = 0; c < 4; c++) h->force[c] = NULL;
+    for (int w = 0; w < 2; w++) { h->t_bc[w][0] = 1.0; h->t_bc[w][1] = 0.0; }
     for (int c = 0; c < 4; c++)
         for (int l = 0; l < NLEV; l++) h->wall[c][l][0] = h->wall[c][l][1] = NULL;
     h->res = (double *)calloc(1, bytes);
@@ -301,6 +303,29 @@ int yyo_set_mode(yyo *h, int mode)
     if (!h || (mode != 0 && mode != 1)) return -1;
     h->mode = mode;
     return 0;
+}
+
+int yyo_set_t_bc(yyo *h, int wall, double a, double b)
+{
+    if (!h || wall < 0 || wall > 1 || !(a >= 0.0) || !(b >= 0.0) || !(a + b > 0.0)) return -1;
+    h->t_bc[wall][0] = a;
+    h->t_bc[wall][1] = b;
+    h->filled = 0;
+    return 0;
+}
+
+/* Robin condition a T + b dT/dn = g on a wall (n the outward normal) with
+ * T_wall = (T_ghost + T_in)/2 and dT/dn = (T_ghost - T_in)/dr on the cell
+ * pair across it: T_ghost = cg g - rho T_in, cg = 1/(a/2 + b/dr),
+ * rho = (a/2 - b/dr)/(a/2 + b/dr).  Dirichlet (1, 0): 2 g - T_in. */
+static double t_rho(const yyo *h, int wall)
+{
+    const double a = h->t_bc[wall][0], b = h->t_bc[wall][1];
+    return (0.5 * a - b / h->dr) / (0.5 * a + b / h->dr);
+}
+static double t_cg(const yyo *h, int wall)
+{
+    return 1.0 / (0.5 * h->t_bc[wall][0] + h->t_bc[wall][1] / h->dr);
 }
 
 int yyo_set_mass_fix(yyo *h, int on)
@@ -455,8 +480,8 @@ static void wall_rules(const yyo *h, int level, int p)
     for (int j = -1; j <= h->nt; j++)
         for (int k = -1; k <= h->np; k++) {
             double *T = h->lev[YYO_T][level];
-            T[ix(h, p, -1, j, k)] = 2.0 * wall_value(h, 0, level, 0, p, j, k, h->t_in) - T[ix(h, p, 0, j, k)];
-            T[ix(h, p, nr, j, k)] = 2.0 * wall_value(h, 0, level, 1, p, j, k, h->t_out) - T[ix(h, p, nr - 1, j, k)];
+            T[ix(h, p, -1, j, k)] = t_cg(h, 0) * wall_value(h, 0, level, 0, p, j, k, h->t_in) - t_rho(h, 0) * T[ix(h, p, 0, j, k)];
+            T[ix(h, p, nr, j, k)] = t_cg(h, 1) * wall_value(h, 0, level, 1, p, j, k, h->t_out) - t_rho(h, 1) * T[ix(h, p, nr - 1, j, k)];
             static const int tang[4] = { YYO_U1T, YYO_U1P, YYO_U2T, YYO_U2P };
             for (int q = 0; q < 4; q++) {
                 const int c = (q % 2 == 0) ? 2 : 3;
@@ -920,6 +945,9 @@ static void sweep_range(yyo *h, int field, int d, const double *x, double *y, in
     int n = uhi(h, loc, d) - ulo(loc, d) + 1;
     int a0 = ulo(loc, d1), a1 = uhi(h, loc, d1), b0 = ulo(loc, d2), b1 = uhi(h, loc, d2);
     int reflect = (d == 0 && !is_face(loc, 0));
+    /* homogeneous wall rule of the correction: c_ghost = -rho c_in (rho = 1
+     * for Dirichlet data, T's Robin rule otherwise) */
+    const double rho0 = field == YYO_T ? t_rho(h, 0) : 1.0, rho1 = field == YYO_T ? t_rho(h, 1) : 1.0;
     double ht = 0.5 * h->tau;
     for (int p = p0; p < p1; p++) {
 #pragma omp parallel for collapse(2) schedule(static)
@@ -933,8 +961,8 @@ static void sweep_range(yyo *h, int field, int d, const double *x, double *y, in
                     lo[m] = -ht * c.lo;
                     di[m] = 1.0 - ht * c.di;
                     up[m] = -ht * c.up;
-                    if (reflect && m == 0) di[m] = 1.0 - ht * (c.di - c.lo);
-                    if (reflect && m == n - 1) di[m] = 1.0 - ht * (c.di - c.up);
+                    if (reflect && m == 0) di[m] = 1.0 - ht * (c.di - rho0 * c.lo);
+                    if (reflect && m == n - 1) di[m] = 1.0 - ht * (c.di - rho1 * c.up);
                     rhs[m] = x[ix(h, p, idx[0], idx[1], idx[2])];
                 }
                 yyo_thomas(n, lo, di, up, rhs, sol);
@@ -982,11 +1010,12 @@ int yyo_apply_op(yyo *h, int field, int op, const double *x, double *y)
                     int idx[3] = { i, j, k };
                     int lo_i = ulo(loc, d), hi_i = uhi(h, loc, d), m = idx[d];
                     int reflect = (d == 0 && !is_face(loc, 0));
+                    const double rho0 = field == YYO_T ? t_rho(h, 0) : 1.0, rho1 = field == YYO_T ? t_rho(h, 1) : 1.0;
                     double xm, xp, x0 = x[ix(h, p, i, j, k)];
                     int im[3] = { i, j, k }, ip[3] = { i, j, k };
                     im[d]--; ip[d]++;
-                    xm = (m > lo_i) ? x[ix(h, p, im[0], im[1], im[2])] : (reflect ? -x0 : 0.0);
-                    xp = (m < hi_i) ? x[ix(h, p, ip[0], ip[1], ip[2])] : (reflect ? -x0 : 0.0);
+                    xm = (m > lo_i) ? x[ix(h, p, im[0], im[1], im[2])] : (reflect ? -rho0 * x0 : 0.0);
+                    xp = (m < hi_i) ? x[ix(h, p, ip[0], ip[1], ip[2])] : (reflect ? -rho1 * x0 : 0.0);
                     y[ix(h, p, i, j, k)] = c.lo * xm + c.di * x0 + c.up * xp;
                 }
     return 0;

@@ -50,6 +50,10 @@ int yyo_set_mode(yyo *h, int mode);
  * fill so that each patch's boundary carries no net mass flux (Algorithm
  * step 4, optional in the paper); 0 (default): off */
 int yyo_set_mass_fix(yyo *h, int on);
+/* Robin condition a T + b dT/dn = g on a wall (0: R1, 1: R2; n the outward
+ * normal), a, b >= 0, a + b > 0; g = the wall data of T or the constant
+ * wall temperature.  Default (1, 0): Dirichlet. */
+int yyo_set_t_bc(yyo *h, int wall, double a, double b);
 int64_t yyo_field_count(const yyo *h, int field, int layout);
 int yyo_set_field(yyo *h, int field, int level, int layout, const double *src);
 int yyo_get_field(const yyo *h, int field, int level, int layout, double *dst);

@@ -34,6 +34,7 @@ def lib():
         L.yyo_set_params.argtypes = [vp, d, d, d, d, d, d]
         L.yyo_set_mode.argtypes = [vp, i]
         L.yyo_set_mass_fix.argtypes = [vp, i]
+        L.yyo_set_t_bc.argtypes = [vp, i, d, d]
         L.yyo_field_count.restype = ctypes.c_int64
         L.yyo_field_count.argtypes = [vp, i, i]
         L.yyo_set_field.argtypes = [vp, i, i, i, dp]
@@ -144,6 +145,11 @@ class Shell:
         a = _f64(a)
         assert a.shape == self.mac_shape(field)
         lib().yyo_set_forcing(self.h, field, _ptr(a))
+
+    def set_t_bc(self, wall, a, b):
+        """Robin condition a T + b dT/dn = g on a wall (0: R1, 1: R2)"""
+        if lib().yyo_set_t_bc(self.h, wall, a, b) != 0:
+            raise RuntimeError("set_t_bc failed")
 
     def set_mass_fix(self, on):
         if lib().yyo_set_mass_fix(self.h, 1 if on else 0) != 0:

@@ -271,6 +271,83 @@ def _discrete_conductive(g, t_in, t_out):
     return prof
 
 
+def _robin_conductive(g, bc):
+    """T(r) with D_rr T = 0 on the centres and the Robin walls
+    a T + b dT/dn = g (T_wall the mean of the cell pair across the wall,
+    dT/dn their outward difference over dr), dense solve."""
+    rf = g.r1 + np.arange(g.nr + 1) * g.dr
+    n = g.nr
+    A = np.zeros((n, n))
+    rhs = np.zeros(n)
+    for i in range(n):
+        a_m, a_p = rf[i] ** 2, rf[i + 1] ** 2
+        A[i, i] = -(a_m + a_p)
+        if i > 0:
+            A[i, i - 1] = a_m
+        if i < n - 1:
+            A[i, i + 1] = a_p
+    for wall, (row, area) in enumerate(((0, rf[0] ** 2), (n - 1, rf[n] ** 2))):
+        a, b, gv = bc[wall]
+        # a (Tg + Tin)/2 + b (Tg - Tin)/dr = gv  =>  Tg = (gv - Tin (a/2 - b/dr)) / (a/2 + b/dr)
+        den = 0.5 * a + b / g.dr
+        A[row, row] += area * (-(0.5 * a - b / g.dr) / den)
+        rhs[row] -= area * gv / den
+    return np.linalg.solve(A, rhs)
+
+
+def test_t_robin_walls(oracle_lib):
+    """Robin walls for T (a T + b dT/dn = g, the wall conditions the paper
+    calls applicable): (1) the discrete conductive profile of these walls,
+    from a dense solve of the definition, with its hydrostatic pressure is
+    a steady state of the full scheme; (2) the r-sweep of T with the Robin
+    end rows inverts I - tau/2 L_r applied with the Robin ghost rule;
+    (3) the same for a prescribed heat flux (a = 0) on one wall."""
+    y = oracle_lib
+    g = I.Grid(6, 12, 36)
+    pr, ra = 1.0, 1e3
+    bc = [(1.0, 0.3, 1.2), (0.5, 0.2, 0.1)]
+    prof = _robin_conductive(g, bc)
+    T = np.broadcast_to(prof[None, :, None, None], g.mac_shape(I.T)).copy()
+    p = np.zeros_like(T)
+    for i in range(1, g.nr):
+        p[:, i] = p[:, i - 1] + g.dr * pr * ra * 0.5 * (T[:, i - 1] + T[:, i])
+    sh = y.Shell(6, 12, 36)
+    sh.set_params(pr=pr, ra=ra, tau=1e-2, t_inner=bc[0][2], t_outer=bc[1][2])
+    sh.set_t_bc(0, bc[0][0], bc[0][1])
+    sh.set_t_bc(1, bc[1][0], bc[1][1])
+    st = {f: np.zeros(g.mac_shape(f)) for f in range(9)}
+    st[I.T], st[I.P1], st[I.P2] = T, p, p
+    for f in range(9):
+        sh.set_field(f, y.LEV_N, st[f])
+        sh.set_field(f, y.LEV_NM1, st[f])
+    for _ in range(3):
+        sh.step(2)
+    assert np.max(np.abs(sh.get_field(I.T) - T)) < 1e-12
+    assert np.max(np.abs(sh.get_field(I.U2R))) < 1e-11
+    # (2) sweep end rows against the ghost rule of the operator
+    rng = np.random.default_rng(31)
+    x = rng.uniform(-1, 1, sh.padded_shape())
+    yv = sh.sweep(I.T, 0, x)
+    back = yv - 0.5 * 1e-2 * sh.apply_op(I.T, y.OP_LR, yv)
+    m = np.zeros(sh.padded_shape(), bool)
+    m[:, 1:-1, 1:-1, 1:-1] = True
+    assert np.max(np.abs(back[m] - x[m])) < 1e-12
+    # (3) a pure Neumann wall (prescribed heat flux) with a Dirichlet one
+    bc = [(0.0, 1.0, -0.7), (1.0, 0.0, 0.2)]
+    prof = _robin_conductive(g, bc)
+    T = np.broadcast_to(prof[None, :, None, None], g.mac_shape(I.T)).copy()
+    sh = y.Shell(6, 12, 36)
+    sh.set_params(pr=pr, ra=0.0, tau=1e-2, t_inner=bc[0][2], t_outer=bc[1][2])
+    sh.set_t_bc(0, 0.0, 1.0)
+    for lev in (y.LEV_N, y.LEV_NM1):
+        sh.set_field(I.T, lev, T)
+    for _ in range(3):
+        sh.step(2)
+    assert np.max(np.abs(sh.get_field(I.T) - T)) < 1e-12
+    # the flux condition holds on the profile: (T0 - T_ghost)/dr ... = -g at R1
+    assert abs((prof[1] - prof[0]) / g.dr) > 0.1
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_conductive_state_is_steady(oracle_lib, mode):
     y = oracle_lib
