@@ -153,6 +153,18 @@ int yy_set_wall(yy_shell *s, int32_t field, int32_t level, int32_t wall, const d
  * (default) turns it off.  Errors: YY_ERR_ARG. */
 int yy_set_mass_fix(yy_shell *s, int32_t on);
 
+/* Wall condition of T on one wall (0: r = R1, 1: r = R2): the Robin form
+ * a T + b dT/dn = g (n the outward normal; a, b >= 0, a + b > 0), which
+ * the paper states its method can take in place of Dirichlet data
+ * (Sec. 1).  g is the wall data of T (yy_set_wall) or else the constant
+ * wall temperature of yy_params.  Discretised on the cell pair across the
+ * wall (T_wall their mean, dT/dn their outward difference over dr): the
+ * ghost is (g - T_in (a/2 - b/dr)) / (a/2 + b/dr), and the r-line
+ * corrections of T take c_ghost = -(a/2 - b/dr)/(a/2 + b/dr) c_in.
+ * Default (1, 0): Dirichlet.  The velocity walls stay Dirichlet.
+ * Errors: YY_ERR_ARG. */
+int yy_set_t_bc(yy_shell *s, int32_t wall, double a, double b);
+
 /* Advance one time step n -> n+1 with n_schwarz Schwarz iterations
  * (Sec. 4 Algorithm with the splitting-error reduction eq. er): per
  * iteration, refresh every field's ghosts from the other patch, solve T,

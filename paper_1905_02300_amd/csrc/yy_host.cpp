@@ -327,6 +327,7 @@ template <typename R> void bind_geo(Geo<R> &g, const R *base, const Dims &d, con
     g.r1 = (R)F.r1;
     const double th1 = M_PI / 4.0 - F.delta;
     g.cphat = (R)(1.0 / (F.r1 * F.r1 * std::sin(th1) * std::sin(th1) * F.dph * F.dph));
+    g.rho_t[0] = g.rho_t[1] = R(1);   // Dirichlet until yy_set_t_bc
 }
 
 // parameter-dependent tables: Pr * (u_r radial) + (1/(2 chi)) * D11 per
@@ -408,6 +409,10 @@ struct yy_shell {
     double *wall[4][3][2];
     bool wall_on[4][3][2] = {};
     bool wall_fresh[4][2] = {};
+    // T's wall conditions a T + b dT/dn = g, (a, b) per wall, and the
+    // derived ghost coefficients
+    double t_ab[2][2] = {{1.0, 0.0}, {1.0, 0.0}};
+    TRobin tb = {{2.0, 2.0}, {1.0, 1.0}};
     // Algorithm step 4 on every velocity fill
     bool mass_fix = false;
     double mf_S = 0.0;           // sum of the squared boundary flux weights
@@ -501,7 +506,7 @@ template <typename R> void do_fill(yy_shell *s, int lev, int pmask, hipStream_t 
 {
     Timed tm(s, PC_FILL, st);
     Ops<R>::fill(s->L.d, state_of<R>(s), lev, s->fcc, (int)s->L.ncc, s->fvt, (int)s->L.nvt, s->fvp,
-                 (int)s->L.nvp, s->prm.t_inner, s->prm.t_outer, walls_of(s, lev), pmask, st);
+                 (int)s->L.nvp, s->prm.t_inner, s->prm.t_outer, s->tb, walls_of(s, lev), pmask, st);
     if (s->mass_fix) Ops<R>::mass_fix(s->L.d, s->gd, state_of<R>(s), lev, s->mf_S, s->mfp, pmask, st);
 }
 
@@ -847,6 +852,24 @@ int yy_set_forcing(yy_shell *s, int32_t field, const double *src, hipStream_t st
         if (src) Ops<float>::io(s->L.d, (float *)s->force_ptr[c], src, nullptr, loc, YY_MAC, st);
     }
     return hip_status(hipGetLastError());
+}
+
+int yy_set_t_bc(yy_shell *s, int32_t wall, double a, double b)
+{
+    if (!s || wall < 0 || wall > 1 || !(a >= 0.0) || !(b >= 0.0) || !(a + b > 0.0) || !std::isfinite(a) ||
+        !std::isfinite(b))
+        return YY_ERR_ARG;
+    const double dr = s->F.dr;
+    s->t_ab[wall][0] = a;
+    s->t_ab[wall][1] = b;
+    s->tb.cg[wall] = 1.0 / (0.5 * a + b / dr);
+    s->tb.rho[wall] = (0.5 * a - b / dr) / (0.5 * a + b / dr);
+    s->gd.rho_t[wall] = s->tb.rho[wall];
+    s->g64.rho_t[wall] = s->tb.rho[wall];
+    s->g32.rho_t[wall] = (float)s->tb.rho[wall];
+    s->need_fill = true;
+    s->version++;
+    return YY_OK;
 }
 
 int yy_set_mass_fix(yy_shell *s, int32_t on)

@@ -71,6 +71,14 @@ template <typename R> struct Geo {
     // parameter-dependent combinations (rebuilt when Pr or chi change):
     // Pr * rf_* + ic * gf_* (u_r radial operator) and Pr * ef_* + ic * gt_*
     CPtr<R> fr_lo, fr_up, fr_di, ft_lo, ft_up, ft_di;
+    // T's wall rule of the correction, c_ghost = -rho_t c_in (1: Dirichlet)
+    R rho_t[2];
+};
+
+// T's Robin walls a T + b dT/dn = g: ghost = cg g - rho T_in (Dirichlet:
+// cg = 2, rho = 1)
+struct TRobin {
+    double cg[2], rho[2];
 };
 constexpr int NTAB_R = 14;   // per-r coefficient tables (length nr+3)
 constexpr int NTAB_T = 20;   // per-theta coefficient tables (length nt+3)
@@ -133,7 +141,8 @@ template <typename R> struct Ops {
     static void copy_levels(const Dims &d, const State<R> &s, int from, int to, hipStream_t st);
     static void fill(const Dims &d, const State<R> &s, int level, const FillScalar *cc, int ncc,
                      const FillVector *vt, int nvt, const FillVector *vp, int nvp,
-                     double t_in, double t_out, const WallLev &walls, int patch_mask, hipStream_t st);
+                     double t_in, double t_out, const TRobin &tb, const WallLev &walls, int patch_mask,
+                     hipStream_t st);
     static void residual(const Dims &d, const Geo<R> &g, const State<R> &s, int field, R *out,
                          hipStream_t st);
     // one sweep; mode 0: y = solve(x); mode 1: psi_k += solve(x) and norm

@@ -332,7 +332,7 @@ __global__ void k_fill_vector(Dims d, const FillVector *__restrict__ tab, int nt
 // its wall faces.  Both velocity systems take the same data.  Thread =
 // padded (j, k) point of patch blockIdx.y.
 template <typename R>
-__global__ void k_walls(Dims d, State<R> s, int lev, R t_in, R t_out, WallLev w, int pmask)
+__global__ void k_walls(Dims d, State<R> s, int lev, R t_in, R t_out, TRobin tb, WallLev w, int pmask)
 {
     const int p = blockIdx.y;
     if (!((pmask >> p) & 1)) return;
@@ -345,8 +345,8 @@ __global__ void k_walls(Dims d, State<R> s, int lev, R t_in, R t_out, WallLev w,
     const int64_t wq = ((int64_t)p * nj + (j + 1)) * nk + (k + 1);
     auto wv = [&](int c, int side, R dflt) { return w.v[c][side] ? (R)w.v[c][side][wq] : dflt; };
     R *T = s.T[lev];
-    T[qm] = R(2) * wv(0, 0, t_in) - T[q0];
-    T[qp] = R(2) * wv(0, 1, t_out) - T[q1];
+    T[qm] = (R)tb.cg[0] * wv(0, 0, t_in) - (R)tb.rho[0] * T[q0];
+    T[qp] = (R)tb.cg[1] * wv(0, 1, t_out) - (R)tb.rho[1] * T[q1];
     const R a0 = wv(2, 0, R(0)), a1 = wv(2, 1, R(0)), b0 = wv(3, 0, R(0)), b1 = wv(3, 1, R(0));
     const R c0 = wv(1, 0, R(0)), c1 = wv(1, 1, R(0));
     for (int y = 0; y < 2; y++) {
@@ -363,7 +363,7 @@ __global__ void k_walls(Dims d, State<R> s, int lev, R t_in, R t_out, WallLev w,
 template <typename R>
 void Ops<R>::fill(const Dims &d, const State<R> &s, int lev, const FillScalar *cc, int ncc,
                   const FillVector *vt, int nvt, const FillVector *vp, int nvp, double t_in,
-                  double t_out, const WallLev &walls, int pmask, hipStream_t st)
+                  double t_out, const TRobin &tb, const WallLev &walls, int pmask, hipStream_t st)
 {
     const int pl = lev == 0 ? 0 : 1;     // pressure keeps levels n and k
     // centre-type scalars: T, p1, p2 (radial 0..nr-1); u_r (faces 1..nr-1)
@@ -388,7 +388,7 @@ void Ops<R>::fill(const Dims &d, const State<R> &s, int lev, const FillScalar *c
     }
     n = (d.np + 2) * (d.nt + 2);
     hipLaunchKernelGGL(k_walls<R>, dim3((n + 255) / 256, 2), dim3(256), 0, st, d, s, lev, (R)t_in,
-                       (R)t_out, walls, pmask);
+                       (R)t_out, tb, walls, pmask);
 }
 
 // ---------------------------------------------------------------------------
@@ -628,8 +628,9 @@ __global__ void __launch_bounds__(256) k_sweep(Dims d, Geo<R> g, Geo<double> gd,
             const Tri<R> c = coef<L, D>(g, ii, jj, ar, at, ap, nu);
             const R lo = -ht * c.lo, up = -ht * c.up;
             R di = R(1) - ht * c.di;
-            if (reflect && m == 0) di = R(1) - ht * (c.di - c.lo);
-            if (reflect && m == n - 1) di = R(1) - ht * (c.di - c.up);
+            const bool tr = L == CC && !DIFF;
+            if (reflect && m == 0) di = R(1) - ht * (c.di - (tr ? g.rho_t[0] : R(1)) * c.lo);
+            if (reflect && m == n - 1) di = R(1) - ht * (c.di - (tr ? g.rho_t[1] : R(1)) * c.up);
             const R den = di - lo * cprev;
             const R cp = (m < n - 1) ? up / den : R(0);
             const R dp = (x[q] - lo * dprev) / den;
@@ -793,8 +794,11 @@ __device__ __forceinline__ void line_row(const Dims &d, const Geo<R> &g, const S
     up = gr < n - 1 ? -g.ht * c.up : R(0);
     di = R(1) - g.ht * c.di;
     if (D == 0 && L != FR) {
-        if (gr == 0) di = R(1) - g.ht * (c.di - c.lo);
-        if (gr == n - 1) di = R(1) - g.ht * (c.di - c.up);
+        // wall rule of the correction c_ghost = -rho c_in: rho = 1 for
+        // Dirichlet walls, T's Robin rule otherwise
+        const bool t = L == CC && !DIFF;
+        if (gr == 0) di = R(1) - g.ht * (c.di - (t ? g.rho_t[0] : R(1)) * c.lo);
+        if (gr == n - 1) di = R(1) - g.ht * (c.di - (t ? g.rho_t[1] : R(1)) * c.up);
     }
 }
 

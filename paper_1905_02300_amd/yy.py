@@ -26,7 +26,7 @@ EXPORTS = ["yy_workspace_bytes", "yy_create", "yy_set_params", "yy_set_field", "
            "yy_residual", "yy_profile", "yy_profile_read", "yy_profile_name",
            "yy_ensemble_workspace_bytes", "yy_ensemble_create", "yy_ensemble_shell",
            "yy_ensemble_step", "yy_ensemble_destroy", "yy_autotune", "yy_set_tuning", "yy_step_tol",
-           "yy_set_wall", "yy_set_mass_fix"]
+           "yy_set_wall", "yy_set_mass_fix", "yy_set_t_bc"]
 NPROF = 17
 
 
@@ -68,6 +68,7 @@ def load():
     L.yy_set_forcing.argtypes = [vp, i32, vp, vp]
     L.yy_set_wall.argtypes = [vp, i32, i32, i32, vp, vp]
     L.yy_set_mass_fix.argtypes = [vp, i32]
+    L.yy_set_t_bc.argtypes = [vp, i32, ctypes.c_double, ctypes.c_double]
     L.yy_step.argtypes = [vp, i32, vp]
     L.yy_step_tol.argtypes = [vp, i32, ctypes.c_double, P(i32), vp]
     L.yy_get_norms.argtypes = [vp, P(ctypes.c_double), i32, vp]
@@ -216,6 +217,10 @@ class Shell:
         _check(load().yy_set_forcing(self.h, field, ctypes.c_void_p(t.data_ptr()),
                                      _stream_ptr(stream)), "yy_set_forcing")
         self._keep_f = t
+
+    def set_t_bc(self, wall, a, b):
+        """Robin wall condition a T + b dT/dn = g of T (wall 0: R1, 1: R2)"""
+        _check(load().yy_set_t_bc(self.h, wall, ctypes.c_double(a), ctypes.c_double(b)), "yy_set_t_bc")
 
     def set_mass_fix(self, on):
         """Algorithm step 4 (boundary mass-flux correction) on every velocity fill"""

@@ -76,6 +76,36 @@ def test_fill_parity(oracle_lib, yy):
         assert _rel(a, b) <= 1e-14, I.FIELD_NAMES[f]
 
 
+def test_t_robin_parity(oracle_lib, yy):
+    """Robin (a T + b dT/dn = g) and prescribed-flux walls for T: the r-sweep
+    of T alone, then 3 manufactured steps (K=2)."""
+    print("case: T robin walls 5x13x40 and 12x24x72", flush=True)
+    o, g = _pair(oracle_lib, yy, 5, 13, 40, pr=1.1, dt=1e-3, t_inner=0.4, t_outer=-0.2)
+    for w, (a, b) in enumerate(((1.0, 0.3), (0.0, 1.0))):
+        o.set_t_bc(w, a, b)
+        g.set_t_bc(w, a, b)
+    rng = np.random.default_rng(61)
+    _set_random(o, g, rng, [0, 1], scale=0.5)
+    o.extrapolate()
+    g.extrapolate()
+    m = _unknown_mask(o.padded_shape(), I.T)
+    x = rng.uniform(-1, 1, o.padded_shape())
+    ref = o.sweep(I.T, 0, x)
+    yt = g.internal_tensor()
+    g.sweep(I.T, 0, g.to_internal(x), yt)
+    got = g.from_internal(yt).cpu().numpy()
+    assert _rel(got[m], ref[m]) <= TOL, _rel(got[m], ref[m])
+    o, g, grid = _mms_pair(oracle_lib, yy, 12, 24, 72, 1e-3)
+    for w, (a, b) in enumerate(((1.0, 0.3), (0.0, 1.0))):
+        o.set_t_bc(w, a, b)
+        g.set_t_bc(w, a, b)
+    _mms_steps(o, g, grid, 1e-3, 3, 2)
+    for f in range(9):
+        a = g.get_field(f).cpu().numpy()
+        b = o.get_field(f)
+        assert _rel(a, b) <= TOL, (I.FIELD_NAMES[f], _rel(a, b))
+
+
 def test_mass_fix_parity(oracle_lib, yy):
     """Algorithm step 4 (boundary mass-flux correction after each velocity
     fill): one fill of random data, then 3 manufactured steps (K=2), with
