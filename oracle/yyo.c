@@ -984,6 +984,53 @@ int yyo_sweep(yyo *h, int field, int dir, const double *x, double *y)
     return 0;
 }
 
+/* (I - tau/2 Pr D) y = x along the direction of a plain metric operator D
+ * (D_rr, D_thth, Dhat_thth, D_phph, Dhat_phph) for the centre unknowns,
+ * every line of both patches; zero at theta/phi ghosts, reflection
+ * (c_{-1} = -c_0) at the walls. */
+int yyo_sweep_op(yyo *h, int op, const double *x, double *y)
+{
+    if (!h || !x || !y || op < YYO_OP_DRR || op > YYO_OP_DPP_HAT) return -1;
+    const int d = op == YYO_OP_DRR ? 0 : (op == YYO_OP_DTT || op == YYO_OP_DTT_HAT) ? 1 : 2;
+    const int d1 = d == 0 ? 1 : 0, d2 = d == 2 ? 1 : 2;
+    const int n = ncell(h, d);
+    const double ht = 0.5 * h->tau;
+    memset(y, 0, sizeof(double) * 2 * h->npatch);
+    for (int p = 0; p < 2; p++) {
+#pragma omp parallel for collapse(2) schedule(static)
+        for (int a = 0; a < ncell(h, d1); a++)
+            for (int b = 0; b < ncell(h, d2); b++) {
+                double lo[2048], di[2048], up[2048], rhs[2048], sol[2048];
+                for (int m = 0; m < n; m++) {
+                    int idx[3];
+                    idx[d] = m; idx[d1] = a; idx[d2] = b;
+                    const double r = rc(h, idx[0]), th = tc(h, idx[1]);
+                    tri c;
+                    switch (op) {
+                    case YYO_OP_DRR: c = op_drr(h, CC, idx[0]); break;
+                    case YYO_OP_DTT: c = op_dtt(h, CC, idx[1], r); break;
+                    case YYO_OP_DTT_HAT: c = op_dtt(h, CC, idx[1], h->r1); break;
+                    case YYO_OP_DPP: c = op_dpp(h, r, th); break;
+                    default: c = op_dpp_hat(h); break;
+                    }
+                    lo[m] = -ht * h->pr * c.lo;
+                    di[m] = 1.0 - ht * h->pr * c.di;
+                    up[m] = -ht * h->pr * c.up;
+                    if (d == 0 && m == 0) di[m] = 1.0 - ht * h->pr * (c.di - c.lo);
+                    if (d == 0 && m == n - 1) di[m] = 1.0 - ht * h->pr * (c.di - c.up);
+                    rhs[m] = x[ix(h, p, idx[0], idx[1], idx[2])];
+                }
+                yyo_thomas(n, lo, di, up, rhs, sol);
+                for (int m = 0; m < n; m++) {
+                    int idx[3];
+                    idx[d] = m; idx[d1] = a; idx[d2] = b;
+                    y[ix(h, p, idx[0], idx[1], idx[2])] = sol[m];
+                }
+            }
+    }
+    return 0;
+}
+
 /* explicit operator at the unknowns with homogeneous neighbours outside
  * the unknown set (the operator whose inverse factor a sweep applies) */
 int yyo_apply_op(yyo *h, int field, int op, const double *x, double *y)

@@ -87,6 +87,12 @@ int yyo_fill(yyo *h, int level);
 int yyo_sweep(yyo *h, int field, int dir, const double *x, double *y);
 /* apply an explicit operator at the field's unknowns (padded in/out) */
 int yyo_apply_op(yyo *h, int field, int op, const double *x, double *y);
+/* (I - tau/2 Pr D) y = x along the direction of D = D_rr, D_thth,
+ * Dhat_thth, D_phph or Dhat_phph (op YYO_OP_DRR..YYO_OP_DPP_HAT) for the
+ * centre unknowns (padded layout); zero at theta/phi ghosts, reflection at
+ * the walls.  The line-solve workload with the paper's split operators
+ * (hat) or the true metric. */
+int yyo_sweep_op(yyo *h, int op, const double *x, double *y);
 /* the residual R^k of a field (padded out, zero off the unknowns) for the
  * current working iterate; s = velocity system (1 or 2) */
 int yyo_residual(yyo *h, int field, double *out);

@@ -47,6 +47,7 @@ def lib():
         L.yyo_fill.argtypes = [vp, i]
         L.yyo_sweep.argtypes = [vp, i, i, dp, dp]
         L.yyo_apply_op.argtypes = [vp, i, i, dp, dp]
+        L.yyo_sweep_op.argtypes = [vp, i, dp, dp]
         L.yyo_residual.argtypes = [vp, i, dp]
         L.yyo_extrapolate.argtypes = [vp]
         L.yyo_thomas.argtypes = [i, dp, dp, dp, dp, dp]
@@ -195,6 +196,14 @@ class Shell:
         y = np.zeros(self.padded_shape())
         if lib().yyo_sweep(self.h, field, d, _ptr(x), _ptr(y)) != 0:
             raise ValueError("bad sweep")
+        return y
+
+    def sweep_op(self, op, x):
+        """(I - tau/2 Pr D_op) y = x along D_op's direction (centre unknowns)"""
+        x = _f64(x)
+        y = np.zeros(self.padded_shape())
+        if lib().yyo_sweep_op(self.h, op, _ptr(x), _ptr(y)) != 0:
+            raise ValueError("bad sweep_op")
         return y
 
     def apply_op(self, field, op, x):

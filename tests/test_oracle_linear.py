@@ -162,3 +162,28 @@ def test_hat_operators_over_stabilise(oracle_lib):
         assert ip(y.OP_DTT_HAT) >= ip(y.OP_DTT) * (1 - 1e-13) >= 0
         assert ip(y.OP_DPP_HAT) >= ip(y.OP_DPP) * (1 - 1e-13) >= 0
         assert ip(y.OP_DRR) >= 0
+
+
+def test_sweep_op_line_solves(oracle_lib):
+    """The line-solve workload's solves (I - tau/2 Pr D) y = x: with the
+    paper's split operators (Drr, Dhat_thth, Dhat_phph) they are the sweeps
+    of T at rest (Pr = 1); with the true metric (D_thth, D_phph) they
+    invert I - tau/2 Pr D for the operator applied with homogeneous
+    neighbours (zero at theta/phi ghosts, reflection at the walls)."""
+    y = oracle_lib
+    sh = y.Shell(6, 14, 40, 0.5, 1.0)
+    tau, pr = 3e-3, 1.3
+    sh.set_params(pr=1.0, tau=tau)
+    sh.extrapolate()
+    rng = np.random.default_rng(8)
+    x = rng.uniform(-1, 1, sh.padded_shape())
+    m = _unknown_mask(sh, I.T)
+    for d, op in enumerate((y.OP_DRR, y.OP_DTT_HAT, y.OP_DPP_HAT)):
+        a = sh.sweep_op(op, x)
+        b = sh.sweep(I.T, d, x)
+        assert np.max(np.abs(a[m] - b[m])) <= 1e-14 * np.max(np.abs(b[m]))
+    sh.set_params(pr=pr, tau=tau)
+    for op in (y.OP_DRR, y.OP_DTT, y.OP_DPP, y.OP_DTT_HAT, y.OP_DPP_HAT):
+        v = sh.sweep_op(op, x)
+        back = v - 0.5 * tau * pr * sh.apply_op(I.T, op, v)
+        assert np.max(np.abs(back[m] - x[m])) < 1e-12, op
