@@ -222,10 +222,12 @@ int yy_extrapolate(yy_shell *s, hipStream_t stream);
 int yy_sweep(yy_shell *s, int32_t field, int32_t dir, const void *dev_x, void *dev_y,
              hipStream_t stream);
 
-/* The same line solve with constant-in-line coefficients from the metric
- * tables only (no advection): the factors (I - tau/2 Pr D) with D = D_rr,
- * Dhat_thth, Dhat_phph of a cell-centred scalar (Sec. 3.2). */
-int yy_sweep_diffusion(yy_shell *s, int32_t dir, const void *dev_x, void *dev_y,
+/* The same line solve with coefficients from the metric tables only (no
+ * advection) for a cell-centred scalar: the factors (I - tau/2 Pr D) with
+ * D = D_rr, and for metric = 0 the paper's split operators Dhat_thth,
+ * Dhat_phph (Sec. 3.2), for metric = 1 the true D_thth, D_phph.
+ * Errors: YY_ERR_ARG, YY_ERR_STATE (params not set). */
+int yy_sweep_diffusion(yy_shell *s, int32_t dir, int32_t metric, const void *dev_x, void *dev_y,
                        hipStream_t stream);
 
 /* tau * R^k of a field for the current working iterate (internal layout,

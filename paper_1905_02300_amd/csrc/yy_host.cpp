@@ -1033,16 +1033,16 @@ int yy_sweep(yy_shell *s, int32_t field, int32_t dir, const void *x, void *y, hi
     return hip_status(hipGetLastError());
 }
 
-int yy_sweep_diffusion(yy_shell *s, int32_t dir, const void *x, void *y, hipStream_t st)
+int yy_sweep_diffusion(yy_shell *s, int32_t dir, int32_t metric, const void *x, void *y, hipStream_t st)
 {
-    if (!s || !x || !y || dir < 0 || dir > 2) return YY_ERR_ARG;
+    if (!s || !x || !y || dir < 0 || dir > 2 || (metric != 0 && metric != 1)) return YY_ERR_ARG;
     if (!s->have_params) return YY_ERR_STATE;
     if (s->L.prec == YY_FP64)
         Ops<double>::sweep(s->L.d, s->g64, s->gd, s->s64, YY_T, dir, (const double *)x, (double *)y, 0,
-                           nullptr, nullptr, 1, st);
+                           nullptr, nullptr, 1 + metric, st);
     else
         Ops<float>::sweep(s->L.d, s->g32, s->gd, s->s32, YY_T, dir, (const float *)x, (float *)y, 0,
-                          nullptr, nullptr, 1, st);
+                          nullptr, nullptr, 1 + metric, st);
     return hip_status(hipGetLastError());
 }
 

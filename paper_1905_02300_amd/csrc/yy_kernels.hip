@@ -131,6 +131,27 @@ __device__ __forceinline__ Tri<R> coef(const Geo<R> &g, int i, int j, R ar, R at
     return c;
 }
 
+// Coefficients of the diffusion-only line solves (DIFF = 1: the paper's
+// split operators Dhat_thth, Dhat_phph; DIFF = 2: the true D_thth =
+// (R1/r)^2 Dhat_thth and D_phph = 1/(r^2 sin^2(theta) dphi^2)) for the
+// centre unknowns; D_rr is common.
+template <int D, int DIFF, typename R>
+__device__ __forceinline__ Tri<R> true_metric(const Geo<R> &g, int i, int j, Tri<R> c, R nu)
+{
+    if (DIFF == 2 && D == 1) {
+        const R f = g.r12 * g.ir2_c[i + 1];
+        c.lo *= f;
+        c.up *= f;
+        c.di *= f;
+    } else if (DIFF == 2 && D == 2) {
+        const R q = nu * g.ir2_c[i + 1] * g.is2_c[j + 1] * g.idph2;
+        c.lo = q;
+        c.up = q;
+        c.di = R(-2) * q;
+    }
+    return c;
+}
+
 template <int L, typename R>
 __device__ __forceinline__ void adv(const State<R> &s, const Dims &d, int64_t q, R &ar, R &at, R &ap)
 {
@@ -595,7 +616,7 @@ __global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R>
 // l2 norm of the increment into per-block partial sums.
 // Thread = line; lines along r and theta are coalesced over k.
 // ---------------------------------------------------------------------------
-template <typename R, int L, int D, int MODE, bool DIFF>
+template <typename R, int L, int D, int MODE, int DIFF>
 __global__ void __launch_bounds__(256) k_sweep(Dims d, Geo<R> g, Geo<double> gd, State<R> s,
                                                const R *x, R *y, R *cb, R *psi, double *partial)
 {
@@ -625,7 +646,7 @@ __global__ void __launch_bounds__(256) k_sweep(Dims d, Geo<R> g, Geo<double> gd,
             const int ii = D == 0 ? m0 + m : i, jj = D == 1 ? m0 + m : j;
             R ar = R(0), at = R(0), ap = R(0);
             if (!DIFF) adv<L>(s, d, q, ar, at, ap);
-            const Tri<R> c = coef<L, D>(g, ii, jj, ar, at, ap, nu);
+            const Tri<R> c = true_metric<D, DIFF>(g, ii, jj, coef<L, D>(g, ii, jj, ar, at, ap, nu), nu);
             const R lo = -ht * c.lo, up = -ht * c.up;
             R di = R(1) - ht * c.di;
             const bool tr = L == CC && !DIFF;
@@ -783,13 +804,13 @@ __device__ __forceinline__ void reduced_solve(R *lo, R *up, R *rhs, int nrow, in
 }
 
 // one row of the line system (I - tau/2 L) at global row g of n
-template <typename R, int L, int D, bool DIFF>
+template <typename R, int L, int D, int DIFF>
 __device__ __forceinline__ void line_row(const Dims &d, const Geo<R> &g, const State<R> &s, int64_t q,
                                          int ii, int jj, int gr, int n, R nu, R &lo, R &di, R &up)
 {
     R ar = R(0), at = R(0), ap = R(0);
     if (!DIFF) adv<L>(s, d, q, ar, at, ap);
-    const Tri<R> c = coef<L, D>(g, ii, jj, ar, at, ap, nu);
+    const Tri<R> c = true_metric<D, DIFF>(g, ii, jj, coef<L, D>(g, ii, jj, ar, at, ap, nu), nu);
     lo = gr > 0 ? -g.ht * c.lo : R(0);
     up = gr < n - 1 ? -g.ht * c.up : R(0);
     di = R(1) - g.ht * c.di;
@@ -811,7 +832,7 @@ template <int L, int D> __device__ __forceinline__ double vol_at(const Geo<doubl
 
 // Strided lines (D = 0: r, D = 1: theta).  Block (W, P): lane x <-> k (W
 // consecutive k, coalesced), y <-> chunk.  A task = (k-tile, other index).
-template <typename R, int L, int D, int MODE, bool DIFF, int M>
+template <typename R, int L, int D, int MODE, int DIFF, int M>
 __global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<double> gd, State<R> s,
                                                         const R *x, R *y, R *psi, double *partial)
 {
@@ -943,7 +964,7 @@ __global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<dou
 // in registers, the reduced system is solved by PCR over wave shuffles, and
 // the chunk's solution goes back to LDS.  Phase C, coalesced: write y (or
 // psi += y and the increment norm).
-template <typename R, int L, int MODE, bool DIFF, int M>
+template <typename R, int L, int MODE, int DIFF, int M>
 __global__ void __launch_bounds__(256) k_sweep_contig(Dims d, Geo<R> g, Geo<double> gd, State<R> s,
                                                       const R *x, R *y, R *psi, double *partial,
                                                       int P, int mc)
@@ -1047,7 +1068,7 @@ __global__ void __launch_bounds__(256) k_sweep_contig(Dims d, Geo<R> g, Geo<doub
 // (fewer registers, more waves per SIMD).  Phases as in k_sweep_contig; the
 // reduced system spans the waves, so its PCR goes through LDS, reusing the
 // staging arrays of the coefficients once the chunks have consumed them.
-template <typename R, int L, int MODE, bool DIFF, int M>
+template <typename R, int L, int MODE, int DIFF, int M>
 __global__ void __launch_bounds__(512) k_sweep_contig_mw(Dims d, Geo<R> g, Geo<double> gd, State<R> s,
                                                          const R *x, R *y, R *psi, double *partial,
                                                          int P, int mc)
@@ -1175,7 +1196,7 @@ bool strided_tile(int n, int M, int wmax, int &W, int &P)
 
 // Launch the partitioned solver when the line fits the register chunks,
 // else the per-line Thomas kernel.  Returns false if it fell back.
-template <typename R, int L, int D, int MODE, bool DIFF>
+template <typename R, int L, int D, int MODE, int DIFF>
 static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double> &gd,
                                const State<R> &s, const R *x, R *y, R *psi, double *partial,
                                int *nblocks, hipStream_t st)
@@ -1278,7 +1299,7 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
 static bool use_partitioned = true;
 void set_partitioned(bool on) { use_partitioned = on; }
 
-template <typename R, int L, int D, int MODE, bool DIFF>
+template <typename R, int L, int D, int MODE, int DIFF>
 static void launch_sweep(const Dims &d, const Geo<R> &g, const Geo<double> &gd, const State<R> &s,
                          const R *x, R *y, R *psi, double *partial, int *nblocks, hipStream_t st)
 {
@@ -1299,9 +1320,9 @@ static void sweep_dir(int dir, const Dims &d, const Geo<R> &g, const Geo<double>
                       const State<R> &s, const R *x, R *y, R *psi, double *partial, int *nb,
                       hipStream_t st)
 {
-    if (dir == 0) launch_sweep<R, L, 0, MODE, false>(d, g, gd, s, x, y, psi, partial, nb, st);
-    else if (dir == 1) launch_sweep<R, L, 1, MODE, false>(d, g, gd, s, x, y, psi, partial, nb, st);
-    else launch_sweep<R, L, 2, MODE, false>(d, g, gd, s, x, y, psi, partial, nb, st);
+    if (dir == 0) launch_sweep<R, L, 0, MODE, 0>(d, g, gd, s, x, y, psi, partial, nb, st);
+    else if (dir == 1) launch_sweep<R, L, 1, MODE, 0>(d, g, gd, s, x, y, psi, partial, nb, st);
+    else launch_sweep<R, L, 2, MODE, 0>(d, g, gd, s, x, y, psi, partial, nb, st);
 }
 
 static int loc_of_field(int f)
@@ -1326,10 +1347,17 @@ void Ops<R>::sweep(const Dims &d, const Geo<R> &g, const Geo<double> &gd, const 
                    int field, int dir, const R *x, R *y, int mode, double *partial, int *nb,
                    int diffusion_only, hipStream_t st)
 {
-    if (diffusion_only) {
-        if (dir == 0) launch_sweep<R, CC, 0, 0, true>(d, g, gd, s, x, y, nullptr, nullptr, nullptr, st);
-        else if (dir == 1) launch_sweep<R, CC, 1, 0, true>(d, g, gd, s, x, y, nullptr, nullptr, nullptr, st);
-        else launch_sweep<R, CC, 2, 0, true>(d, g, gd, s, x, y, nullptr, nullptr, nullptr, st);
+    if (diffusion_only == 1) {
+        if (dir == 0) launch_sweep<R, CC, 0, 0, 1>(d, g, gd, s, x, y, nullptr, nullptr, nullptr, st);
+        else if (dir == 1) launch_sweep<R, CC, 1, 0, 1>(d, g, gd, s, x, y, nullptr, nullptr, nullptr, st);
+        else launch_sweep<R, CC, 2, 0, 1>(d, g, gd, s, x, y, nullptr, nullptr, nullptr, st);
+        return;
+    }
+    if (diffusion_only == 2) {
+        // D_rr is the same in both metrics
+        if (dir == 0) launch_sweep<R, CC, 0, 0, 1>(d, g, gd, s, x, y, nullptr, nullptr, nullptr, st);
+        else if (dir == 1) launch_sweep<R, CC, 1, 0, 2>(d, g, gd, s, x, y, nullptr, nullptr, nullptr, st);
+        else launch_sweep<R, CC, 2, 0, 2>(d, g, gd, s, x, y, nullptr, nullptr, nullptr, st);
         return;
     }
     const int L = loc_of_field(field);

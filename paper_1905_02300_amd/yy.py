@@ -79,7 +79,7 @@ def load():
     L.yy_fill.argtypes = [vp, i32, vp]
     L.yy_extrapolate.argtypes = [vp, vp]
     L.yy_sweep.argtypes = [vp, i32, i32, vp, vp, vp]
-    L.yy_sweep_diffusion.argtypes = [vp, i32, vp, vp, vp]
+    L.yy_sweep_diffusion.argtypes = [vp, i32, i32, vp, vp, vp]
     L.yy_residual.argtypes = [vp, i32, vp, vp]
     L.yy_profile.argtypes = [vp, i32]
     L.yy_profile_read.argtypes = [vp, P(ctypes.c_double), P(i64), vp]
@@ -270,8 +270,10 @@ class Shell:
         _check(load().yy_sweep(self.h, field, d, ctypes.c_void_p(x.data_ptr()),
                                ctypes.c_void_p(y.data_ptr()), _stream_ptr(stream)), "yy_sweep")
 
-    def sweep_diffusion(self, d, x, y, stream=None):
-        _check(load().yy_sweep_diffusion(self.h, d, ctypes.c_void_p(x.data_ptr()),
+    def sweep_diffusion(self, d, x, y, stream=None, metric=0):
+        """(I - tau/2 Pr D) y = x along d; metric 0: D_rr, Dhat_thth,
+        Dhat_phph (the split operators), 1: the true D_thth, D_phph"""
+        _check(load().yy_sweep_diffusion(self.h, d, metric, ctypes.c_void_p(x.data_ptr()),
                                          ctypes.c_void_p(y.data_ptr()), _stream_ptr(stream)),
                "yy_sweep_diffusion")
 

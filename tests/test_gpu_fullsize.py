@@ -28,8 +28,8 @@ def yy():
 @pytest.mark.parametrize("prec", [0, 1])
 def test_line_solve_64x192x576(oracle_lib, yy, prec):
     """(I - tau/2 Pr D) y = x along r, theta, phi on both patches, RHS
-    uniform[-1,1] (seed 2), tau = 1e-3, Pr = 1 (FP64 at 1e-12; FP32 at the
-    rounding of its inputs, 1e-5)."""
+    uniform[-1,1] (seed 2), tau = 1e-3, Pr = 1, with the split (hat) and the
+    true metric (FP64 at 1e-12; FP32 at the rounding of its inputs, 1e-5)."""
     print(f"case: line solve 64x192x576 prec {prec}", flush=True)
     g = I.Grid(64, 192, 576)
     o = oracle_lib.Shell(64, 192, 576)
@@ -42,14 +42,19 @@ def test_line_solve_64x192x576(oracle_lib, yy, prec):
     m = np.zeros(x.shape, bool)
     m[:, 1:-1, 1:-1, 1:-1] = True
     tol = 1e-12 if prec == 0 else 1e-5
-    for d in range(3):
-        ref = o.sweep(I.T, d, x)
-        yt = s.internal_tensor()
-        s.sweep_diffusion(d, s.to_internal(x), yt)
-        got = s.from_internal(yt).double().cpu().numpy()
-        err = np.max(np.abs(got[m] - ref[m])) / np.max(np.abs(ref[m]))
-        print(f"  dir {d}: relative error {err:.2e}", flush=True)
-        assert err <= tol
+    ops = [[oracle_lib.OP_DRR, oracle_lib.OP_DTT_HAT, oracle_lib.OP_DPP_HAT],
+           [oracle_lib.OP_DRR, oracle_lib.OP_DTT, oracle_lib.OP_DPP]]
+    for metric in (0, 1):
+        for d in range(3):
+            if metric == 1 and d == 0:
+                continue                 # D_rr is the same in both metrics
+            ref = o.sweep_op(ops[metric][d], x)
+            yt = s.internal_tensor()
+            s.sweep_diffusion(d, s.to_internal(x), yt, metric=metric)
+            got = s.from_internal(yt).double().cpu().numpy()
+            err = np.max(np.abs(got[m] - ref[m])) / np.max(np.abs(ref[m]))
+            print(f"  metric {metric} dir {d}: relative error {err:.2e}", flush=True)
+            assert err <= tol
 
 
 def _discrete_conductive(g):

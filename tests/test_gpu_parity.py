@@ -173,15 +173,18 @@ def test_sweep_parity_line_lengths(oracle_lib, yy, shape, field):
         assert _rel(got[m], ref[m]) <= TOL, (d, _rel(got[m], ref[m]))
 
 
+@pytest.mark.parametrize("metric", [0, 1])
 @pytest.mark.parametrize("d", [0, 1, 2])
-def test_sweep_diffusion_parity(oracle_lib, yy, d):
-    print(f"case: sweep_diffusion dir {d}", flush=True)
-    o, g = _pair(oracle_lib, yy, 6, 14, 42, pr=1.0, dt=1e-2)
-    o.extrapolate()                      # zero velocity: T's factors are pure diffusion
+def test_sweep_diffusion_parity(oracle_lib, yy, d, metric):
+    """The line-solve kernel with the split (hat) or the true metric."""
+    print(f"case: sweep_diffusion dir {d} metric {metric}", flush=True)
+    o, g = _pair(oracle_lib, yy, 6, 14, 42, pr=1.3, dt=1e-2)
+    op = [[oracle_lib.OP_DRR, oracle_lib.OP_DTT_HAT, oracle_lib.OP_DPP_HAT],
+          [oracle_lib.OP_DRR, oracle_lib.OP_DTT, oracle_lib.OP_DPP]][metric][d]
     x = np.random.default_rng(7 + d).uniform(-1, 1, o.padded_shape())
-    ref = o.sweep(I.T, d, x)
+    ref = o.sweep_op(op, x)
     yt = g.internal_tensor()
-    g.sweep_diffusion(d, g.to_internal(x), yt)
+    g.sweep_diffusion(d, g.to_internal(x), yt, metric=metric)
     got = g.from_internal(yt).cpu().numpy()
     m = _unknown_mask(o.padded_shape(), I.T)
     assert _rel(got[m], ref[m]) <= TOL
