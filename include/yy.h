@@ -243,7 +243,9 @@ int yy_residual(yy_shell *s, int32_t field, void *dev_out, hipStream_t stream);
  * block, "l<lines>", or 2/4/8 waves per line, "v<waves>"), each on the
  * shell's own scratch buffer with its current advecting velocity and in
  * the form the step launches it (the last factor of an unknown fused with
- * its update and norm), keep the fastest per (unknown, direction), and
+ * its update and norm), and those of the diffusion-only line solves
+ * (yy_sweep_diffusion, keys "D.r", "D.t", "D.p"), keep the fastest per
+ * (unknown or "D", direction), and
  * write the choices as a JSON object (a NUL-terminated string of at most
  * cap bytes) to json_out if not NULL.
  * Synchronises the stream.  Needs params.  Errors: YY_ERR_ARG,

@@ -1058,8 +1058,10 @@ int yy_residual(yy_shell *s, int32_t field, void *out, hipStream_t st)
 // ---------------------------------------------------------------------------
 // autotuning of the line-solver tiles
 // ---------------------------------------------------------------------------
-static const char *tune_field_name[4] = {"T", "u_r", "u_t", "u_p"};
-static const int tune_field_id[4] = {YY_T, YY_U2R, YY_U2T, YY_U2P};
+// tile slots: the four unknowns' sweeps and ("D") the diffusion-only line
+// solves of the line-solve workload
+static const char *tune_field_name[5] = {"T", "u_r", "u_t", "u_p", "D"};
+static const int tune_field_id[5] = {YY_T, YY_U2R, YY_U2T, YY_U2P, -1};
 static const char dir_name[3] = {'r', 't', 'p'};
 
 static Tune &tune_of(yy_shell *s) { return s->L.prec == YY_FP64 ? s->s64.tune : s->s32.tune; }
@@ -1073,6 +1075,10 @@ static const int last_dir[4] = {2, 0, 1, 2};   // T: r,t,p; u_r: t,p,r; u_t: p,r
 extern "C++" template <typename R> static int sweep_in_step(yy_shell *s, int field, int dir, hipStream_t st)
 {
     State<R> S = state_of<R>(s);
+    if (field < 0) {   // the diffusion-only solve (split operators)
+        Ops<R>::sweep(s->L.d, geo_of<R>(s), s->gd, S, YY_T, dir, S.res, S.res, 0, nullptr, nullptr, 1, st);
+        return hip_status(hipGetLastError());
+    }
     const int loc = loc_of(field);
     if (dir != last_dir[loc]) {
         Ops<R>::sweep(s->L.d, geo_of<R>(s), s->gd, S, field, dir, S.res, S.res, 0, nullptr, nullptr, 0, st);
@@ -1116,7 +1122,7 @@ extern "C" int yy_autotune(yy_shell *s, char *json_out, int32_t cap, hipStream_t
     s->prof = false;
     Tune &T = tune_of(s);
     std::string js = "{";
-    for (int L = 0; L < 4; L++) {
+    for (int L = 0; L < 5; L++) {
         for (int dir = 0; dir < 3; dir++) {
             char key[16];
             std::snprintf(key, sizeof key, "%s.%c", tune_field_name[L], dir_name[dir]);
@@ -1185,7 +1191,7 @@ extern "C" int yy_set_tuning(yy_shell *s, const char *json)
     if (!s || !json) return YY_ERR_ARG;
     Tune &T = tune_of(s);
     const std::string js(json);
-    for (int L = 0; L < 4; L++)
+    for (int L = 0; L < 5; L++)
         for (int dir = 0; dir < 3; dir++) {
             char key[24];
             std::snprintf(key, sizeof key, "\"%s.%c\":\"", tune_field_name[L], dir_name[dir]);

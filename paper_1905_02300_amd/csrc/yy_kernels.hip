@@ -1205,12 +1205,13 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
     if (D < 2) {
         // rows per chunk: tuned (1 = per-line Thomas), else 12 for the
         // u_theta polar sweep (the most per-row data) and 16 otherwise
-        int M = s.tune.m[L][D];
+        const int TL = DIFF ? 4 : L;   // tile slot
+        int M = s.tune.m[TL][D];
         if (M == 1) return false;
         if (M != 4 && M != 6 && M != 8 && M != 12 && M != 16) M = (L == FT && D == 1) ? 12 : 16;
         const int n = ncell(d, D) - (D == 0 ? i0 : j0);
         int W = 0, P = 0;
-        if (!strided_tile(n, M, s.tune.w[L][D], W, P)) return false;
+        if (!strided_tile(n, M, s.tune.w[TL][D], W, P)) return false;
         const int nk = d.np - k0;
         const int nother = D == 0 ? d.nt - j0 : d.nr - i0;
         int64_t tasks = (int64_t)((nk + W - 1) / W) * nother;
@@ -1246,7 +1247,7 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
         }
         if (mc > 32 || P > 64) return false;
         const int64_t nlines = (int64_t)(d.nr - i0) * (d.nt - j0);
-        const int V = s.tune.wpl[L];
+        const int V = s.tune.wpl[DIFF ? 4 : L];
         if ((V == 2 || V == 4 || V == 8) && n >= 64 * V) {
             // V waves per line: uniform chunks of mcv rows (last >= 2)
             int mcv = (n + 64 * V - 1) / (64 * V);
@@ -1277,7 +1278,7 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
         int lpb = (int)(65536 / per_line);
         if (lpb > 4) lpb = 4;
         if (lpb < 1) return false;
-        const int want = s.tune.lpb[L];
+        const int want = s.tune.lpb[DIFF ? 4 : L];
         if ((want == 1 || want == 2 || want == 4) && want < lpb) lpb = want;
         int64_t b = (nlines + lpb - 1) / lpb;
         if (b > SWEEP_BLOCKS) b = SWEEP_BLOCKS;
