@@ -59,7 +59,8 @@ Layout make_layout(const yy_grid *g, int prec)
     L.d.nr = g->nr;
     L.d.nt = g->nt;
     L.d.np = g->np;
-    L.d.sJ = align_up(g->np + 2, 16);
+    // rows start on 128-byte boundaries in both precisions (one L2 line)
+    L.d.sJ = align_up(g->np + 2, prec == YY_FP64 ? 16 : 32);
     L.d.sI = (int64_t)(g->nt + 2) * L.d.sJ;
     L.d.sP = (int64_t)(g->nr + 2) * L.d.sI;
     L.d.p0 = 0;

@@ -2,8 +2,9 @@
 // kernels of libyy.so (not part of the public ABI).
 //
 // Device layout of every field: [patch][i][j][k] with one ghost layer,
-// logical index -1..N per direction, k (phi) fastest, row pitch padded to a
-// multiple of 16 elements; face f of a face-located field at logical f.
+// logical index -1..N per direction, k (phi) fastest, row pitch padded to
+// 128 bytes (16 FP64 or 32 FP32 elements), so every row starts on an L2
+// line; face f of a face-located field at logical f.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

@@ -830,6 +830,10 @@ template <int L, int D> __device__ __forceinline__ double vol_at(const Geo<doubl
     return r0 * r0 * s0 * gd.dr * gd.dth * gd.dph;
 }
 
+// number of W-wide k-tiles aligned to the row storage that cover the
+// unknowns k < np (row element k + 1)
+__host__ __device__ inline int sweep_ktiles(int np, int W) { return np / W + 1; }
+
 // Strided lines (D = 0: r, D = 1: theta).  Block (W, P): lane x <-> k (W
 // consecutive k, coalesced), y <-> chunk.  A task = (k-tile, other index).
 template <typename R, int L, int D, int MODE, int DIFF, int M>
@@ -840,13 +844,16 @@ __global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<dou
     R *sm = reinterpret_cast<R *>(smem_raw);
     const int W = blockDim.x, P = blockDim.y;
     const int lane = threadIdx.x, t = threadIdx.y;
-    const int p = d.p0 + blockIdx.y;
+    unsigned bx, by;
+    xcd_block(bx, by);
+    const int p = d.p0 + (int)by;
     const int i0 = ulo<L>(0), j0 = ulo<L>(1), k0 = ulo<L>(2);
     const int m0 = D == 0 ? i0 : j0;
     const int n = ncell(d, D) - m0;
-    const int nk = d.np - k0;
     const int nother = D == 0 ? d.nt - j0 : d.nr - i0;
-    const int ntile = (nk + W - 1) / W;
+    // k-tiles aligned to the row storage: tile q covers the row elements
+    // [q W, q W + W), i.e. k = q W - 1 + lane (rows start 128-byte aligned)
+    const int ntile = sweep_ktiles(d.np, W);
     const int64_t stride = D == 0 ? d.sI : d.sJ;
     const R nu = (L == CC && !DIFF) ? R(1) : g.pr;
     // chunk rows [r0, r1)
@@ -855,10 +862,10 @@ __global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<dou
     // reduced-system exchange in LDS: four [P][W] arrays
     R *sA = sm, *sB = sm + P * W, *sC = sm + 2 * P * W, *sD = sm + 3 * P * W;
     double acc = 0.0;
-    for (int task = blockIdx.x; task < ntile * nother; task += gridDim.x) {
+    for (int task = (int)bx; task < ntile * nother; task += gridDim.x) {
         const int tile = task % ntile, oth = task / ntile;
-        const int k = k0 + tile * W + lane;
-        const bool live = (k - k0) < nk;
+        const int k = tile * W + lane - 1;
+        const bool live = k >= k0 && k < d.np;
         int i = 0, j = 0;
         if (D == 0) j = j0 + oth; else i = i0 + oth;
         R a[M], c[M], dd[M];
@@ -951,7 +958,7 @@ __global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<dou
             double tot = 0.0;
             const int nw = (W * P) >> 6;
             for (int w = 0; w < nw; w++) tot += red[w];
-            partial[p * NBMAX + blockIdx.x] = tot;
+            partial[p * NBMAX + bx] = tot;
         }
     }
 }
@@ -1212,9 +1219,8 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
         const int n = ncell(d, D) - (D == 0 ? i0 : j0);
         int W = 0, P = 0;
         if (!strided_tile(n, M, s.tune.w[TL][D], W, P)) return false;
-        const int nk = d.np - k0;
         const int nother = D == 0 ? d.nt - j0 : d.nr - i0;
-        int64_t tasks = (int64_t)((nk + W - 1) / W) * nother;
+        int64_t tasks = (int64_t)sweep_ktiles(d.np, W) * nother;
         int64_t b = tasks;
         if (b > SWEEP_BLOCKS) b = SWEEP_BLOCKS;
         if (nblocks) *nblocks = (int)b;
