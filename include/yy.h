@@ -203,8 +203,11 @@ const char *yy_strerror(int status);
 /* ---- pieces of the step, for kernel-level tests and benchmarks ---- */
 
 /* Internal padded layout of compute-precision arrays: dims = {2, nr+2,
- * nt+2, pitch}, pitch >= np+2 (elements).  elem_bytes = 8 or 4. */
-int yy_internal_dims(const yy_shell *s, int64_t dims[4], int32_t *elem_bytes);
+ * nt+2, pitch} (elements); within each row of `pitch` elements the points
+ * k = -1 .. np occupy elements k_first .. k_first+np+1 (k = 0 lands on a
+ * 128-byte boundary; the other elements are padding).  elem_bytes = 8 or
+ * 4.  elem_bytes and k_first may be NULL. */
+int yy_internal_dims(const yy_shell *s, int64_t dims[4], int32_t *elem_bytes, int32_t *k_first);
 
 /* Refresh ghosts and boundary faces of every field at `level` from the
  * other patch, then apply the wall rules. */

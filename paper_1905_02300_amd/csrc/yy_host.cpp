@@ -40,15 +40,17 @@ int64_t ntab_t(const Dims &d) { return 2 * (d.nt + 2) + 2 * (d.nt + 3) + (int64_
 // forcing (4), residual, Thomas scratch
 constexpr int N_R_ARRAYS = 4 + 18 + 6 + 4 + 2;
 
-bool valid_grid(const yy_grid *g)
+bool valid_grid(const yy_grid *g, int prec)
 {
     if (!(g && g->nr >= 2 && g->nt >= 6 && g->np >= 6 && g->nr <= 4096 && g->nt <= 4096 &&
           g->np <= 8192 && g->r1 > 0.0 && g->r2 > g->r1 && std::isfinite(g->r1) &&
           std::isfinite(g->r2)))
         return false;
-    // kernels address a field by a 32-bit byte offset: one FP64 field (both
-    // patches, ghosts and row padding) must stay below 4 GiB
-    const int64_t field = 2 * (int64_t)(g->nr + 2) * (g->nt + 2) * align_up(g->np + 2, 16) * 8;
+    // kernels address a field by a 32-bit byte offset: one FP64 array (both
+    // patches, ghosts and row padding; the pressures are FP64 in both
+    // precisions) must stay below 4 GiB
+    const int64_t field =
+        2 * (int64_t)(g->nr + 2) * (g->nt + 2) * row_pitch(g->np, prec == YY_FP64 ? 8 : 4) * 8;
     return field < ((int64_t)1 << 32);
 }
 
@@ -59,8 +61,8 @@ Layout make_layout(const yy_grid *g, int prec)
     L.d.nr = g->nr;
     L.d.nt = g->nt;
     L.d.np = g->np;
-    // rows start on 128-byte boundaries in both precisions (one L2 line)
-    L.d.sJ = align_up(g->np + 2, prec == YY_FP64 ? 16 : 32);
+    L.d.ko = row_origin(prec == YY_FP64 ? 8 : 4);
+    L.d.sJ = row_pitch(g->np, prec == YY_FP64 ? 8 : 4);
     L.d.sI = (int64_t)(g->nt + 2) * L.d.sJ;
     L.d.sP = (int64_t)(g->nr + 2) * L.d.sI;
     L.d.p0 = 0;
@@ -680,7 +682,7 @@ const char *yy_strerror(int st)
 
 int yy_workspace_bytes(const yy_grid *g, int32_t prec, uint64_t *bytes)
 {
-    if (!valid_grid(g) || !bytes || (prec != YY_FP64 && prec != YY_FP32_MIXED)) return YY_ERR_ARG;
+    if (!valid_grid(g, prec) || !bytes || (prec != YY_FP64 && prec != YY_FP32_MIXED)) return YY_ERR_ARG;
     *bytes = (uint64_t)make_layout(g, prec).total;
     return YY_OK;
 }
@@ -689,7 +691,7 @@ int yy_create(const yy_grid *g, int32_t prec, void *dev_ws, uint64_t ws_bytes, y
 {
     if (!out) return YY_ERR_ARG;
     *out = nullptr;
-    if (!valid_grid(g) || !dev_ws || (prec != YY_FP64 && prec != YY_FP32_MIXED)) return YY_ERR_ARG;
+    if (!valid_grid(g, prec) || !dev_ws || (prec != YY_FP64 && prec != YY_FP32_MIXED)) return YY_ERR_ARG;
     Layout L = make_layout(g, prec);
     if ((uintptr_t)dev_ws % ALIGN) return YY_ERR_WORKSPACE;
     if (ws_bytes < (uint64_t)L.total) return YY_ERR_WORKSPACE;
@@ -993,7 +995,7 @@ const char *yy_profile_name(int32_t c)
     return (c >= 0 && c < YY_NPROF) ? prof_names[c] : nullptr;
 }
 
-int yy_internal_dims(const yy_shell *s, int64_t dims[4], int32_t *elem_bytes)
+int yy_internal_dims(const yy_shell *s, int64_t dims[4], int32_t *elem_bytes, int32_t *k_first)
 {
     if (!s || !dims) return YY_ERR_ARG;
     dims[0] = 2;
@@ -1001,6 +1003,7 @@ int yy_internal_dims(const yy_shell *s, int64_t dims[4], int32_t *elem_bytes)
     dims[2] = s->L.d.nt + 2;
     dims[3] = s->L.d.sJ;
     if (elem_bytes) *elem_bytes = (int32_t)s->L.elem;
+    if (k_first) *k_first = s->L.d.ko - 1;
     return YY_OK;
 }
 

@@ -2,9 +2,11 @@
 // kernels of libyy.so (not part of the public ABI).
 //
 // Device layout of every field: [patch][i][j][k] with one ghost layer,
-// logical index -1..N per direction, k (phi) fastest, row pitch padded to
-// 128 bytes (16 FP64 or 32 FP32 elements), so every row starts on an L2
-// line; face f of a face-located field at logical f.
+// logical index -1..N per direction, k (phi) fastest; face f of a
+// face-located field at logical f.  Within a row, k = 0 sits at element ko
+// (16 FP64 or 32 FP32 elements: 128 bytes), the ghost k = -1 just before
+// it, and the row pitch is a multiple of 128 bytes, so the unknowns of
+// every row start on an L2 line.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -17,11 +19,21 @@ struct Dims {
     int nr, nt, np;
     int64_t sJ, sI, sP;      // element strides of j, i and patch (k: 1)
     int p0, npatch;          // patches a launch covers: p0 .. p0+npatch-1
+    int ko;                  // element of k = 0 within a row
 };
 
 __host__ __device__ inline int64_t ix(const Dims &d, int p, int i, int j, int k)
 {
-    return (int64_t)p * d.sP + (int64_t)(i + 1) * d.sI + (int64_t)(j + 1) * d.sJ + (k + 1);
+    return (int64_t)p * d.sP + (int64_t)(i + 1) * d.sI + (int64_t)(j + 1) * d.sJ + (k + d.ko);
+}
+
+// element of k = 0 and row pitch of the layout (FP64 or FP32-mixed; the FP64
+// pressures of FP32-mixed share the FP32 indexing)
+__host__ __device__ inline int row_origin(int elem_bytes) { return 128 / elem_bytes; }
+__host__ __device__ inline int64_t row_pitch(int np, int elem_bytes)
+{
+    const int64_t a = 128 / elem_bytes;
+    return (np + 1 + row_origin(elem_bytes) + a - 1) / a * a;
 }
 
 // Pointer to a read-only table.  Device reads go through the constant

@@ -187,19 +187,20 @@ __device__ __forceinline__ void xcd_block(unsigned &bx, unsigned &by)
 // time than it saves, so the waves run free.)
 constexpr int COL_K = 64, COL_J = 4;
 
-// tile of block (bx) over nj x nk columns starting at (j0, k0); false if the
+// tile of block (bx) over the columns j0 <= j < j0 + nj, k0 <= k < np; the
+// k-tiles are aligned to the row storage (k = tk COL_K + x); false if the
 // thread's column is outside
-__device__ __forceinline__ bool col_of(unsigned bx, int nj, int nk, int j0, int k0, int &j, int &k)
+__device__ __forceinline__ bool col_of(unsigned bx, int nj, int np, int j0, int k0, int &j, int &k)
 {
-    const int ntk = (nk + COL_K - 1) / COL_K;
+    const int ntk = (np + COL_K - 1) / COL_K;
     const int tk = (int)(bx % (unsigned)ntk), tj = (int)(bx / (unsigned)ntk);
-    k = k0 + tk * COL_K + (int)threadIdx.x;
+    k = tk * COL_K + (int)threadIdx.x;
     j = j0 + tj * COL_J + (int)threadIdx.y;
-    return (k - k0) < nk && (j - j0) < nj;
+    return k >= k0 && k < np && (j - j0) < nj;
 }
-__host__ __device__ inline int64_t col_blocks(int nj, int nk)
+__host__ __device__ inline int64_t col_blocks(int nj, int np)
 {
-    return (int64_t)((nk + COL_K - 1) / COL_K) * ((nj + COL_J - 1) / COL_J);
+    return (int64_t)((np + COL_K - 1) / COL_K) * ((nj + COL_J - 1) / COL_J);
 }
 
 // ---------------------------------------------------------------------------
@@ -469,9 +470,9 @@ __global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R>
     xcd_block(bx, by);
     const int p = d.p0 + (int)by;
     const int j0 = ulo<L>(1), k0 = ulo<L>(2), i0 = ulo<L>(0);
-    const int nj = d.nt - j0, nk = d.np - k0;
+    const int nj = d.nt - j0;
     int j, k;
-    if (!col_of(bx, nj, nk, j0, k0, j, k)) return;
+    if (!col_of(bx, nj, d.np, j0, k0, j, k)) return;
     // 32-bit element indices (each field is below 4 GiB: checked on the host)
     const uint32_t sI = (uint32_t)d.sI, sJ = (uint32_t)d.sJ;
     const R nu = L == CC ? R(1) : g.pr;
@@ -830,9 +831,9 @@ template <int L, int D> __device__ __forceinline__ double vol_at(const Geo<doubl
     return r0 * r0 * s0 * gd.dr * gd.dth * gd.dph;
 }
 
-// number of W-wide k-tiles aligned to the row storage that cover the
-// unknowns k < np (row element k + 1)
-__host__ __device__ inline int sweep_ktiles(int np, int W) { return np / W + 1; }
+// number of W-wide k-tiles (tile q: k = q W .. q W + W - 1, aligned to the
+// row storage) that cover the unknowns k < np
+__host__ __device__ inline int sweep_ktiles(int np, int W) { return (np + W - 1) / W; }
 
 // Strided lines (D = 0: r, D = 1: theta).  Block (W, P): lane x <-> k (W
 // consecutive k, coalesced), y <-> chunk.  A task = (k-tile, other index).
@@ -851,8 +852,6 @@ __global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<dou
     const int m0 = D == 0 ? i0 : j0;
     const int n = ncell(d, D) - m0;
     const int nother = D == 0 ? d.nt - j0 : d.nr - i0;
-    // k-tiles aligned to the row storage: tile q covers the row elements
-    // [q W, q W + W), i.e. k = q W - 1 + lane (rows start 128-byte aligned)
     const int ntile = sweep_ktiles(d.np, W);
     const int64_t stride = D == 0 ? d.sI : d.sJ;
     const R nu = (L == CC && !DIFF) ? R(1) : g.pr;
@@ -864,7 +863,7 @@ __global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<dou
     double acc = 0.0;
     for (int task = (int)bx; task < ntile * nother; task += gridDim.x) {
         const int tile = task % ntile, oth = task / ntile;
-        const int k = tile * W + lane - 1;
+        const int k = tile * W + lane;
         const bool live = k >= k0 && k < d.np;
         int i = 0, j = 0;
         if (D == 0) j = j0 + oth; else i = i0 + oth;
@@ -1403,7 +1402,7 @@ void Ops<R>::residual(const Dims &d, const Geo<R> &g, const State<R> &s, int fie
     in.p1k = s.p[0][1];
     in.sys = sys;
     const int j0 = L == FT, k0 = L == FP;
-    const dim3 gr((unsigned)col_blocks(d.nt - j0, d.np - k0), d.npatch), bl(COL_K, COL_J);
+    const dim3 gr((unsigned)col_blocks(d.nt - j0, d.np), d.npatch), bl(COL_K, COL_J);
     if (L == CC) hipLaunchKernelGGL((k_residual_col<R, CC>), gr, bl, 0, st, d, g, s, in, out);
     else if (L == FR) hipLaunchKernelGGL((k_residual_col<R, FR>), gr, bl, 0, st, d, g, s, in, out);
     else if (L == FT) hipLaunchKernelGGL((k_residual_col<R, FT>), gr, bl, 0, st, d, g, s, in, out);

@@ -75,7 +75,7 @@ def load():
     L.yy_destroy.argtypes = [vp]
     L.yy_strerror.argtypes = [ctypes.c_int]
     L.yy_strerror.restype = ctypes.c_char_p
-    L.yy_internal_dims.argtypes = [vp, P(i64), P(i32)]
+    L.yy_internal_dims.argtypes = [vp, P(i64), P(i32), P(i32)]
     L.yy_fill.argtypes = [vp, i32, vp]
     L.yy_extrapolate.argtypes = [vp, vp]
     L.yy_sweep.argtypes = [vp, i32, i32, vp, vp, vp]
@@ -149,10 +149,11 @@ class Shell:
             self.ws = _ws
             self.h = ctypes.c_void_p(_handle)
         dims = (ctypes.c_int64 * 4)()
-        eb = ctypes.c_int32()
-        _check(L.yy_internal_dims(self.h, dims, ctypes.byref(eb)), "yy_internal_dims")
+        eb, kf = ctypes.c_int32(), ctypes.c_int32()
+        _check(L.yy_internal_dims(self.h, dims, ctypes.byref(eb), ctypes.byref(kf)), "yy_internal_dims")
         self.internal_dims = tuple(dims)
         self.elem_bytes = eb.value
+        self.k_first = kf.value       # row element of the ghost k = -1
         self.K = 0
 
     def close(self):
@@ -306,11 +307,13 @@ class Shell:
         """(2, nr+2, nt+2, np+2) array -> internal-layout tensor"""
         import torch
         t = self.internal_tensor()
-        t[..., :self.np + 2] = torch.as_tensor(padded, dtype=t.dtype, device=t.device)
+        o = self.k_first
+        t[..., o:o + self.np + 2] = torch.as_tensor(padded, dtype=t.dtype, device=t.device)
         return t
 
     def from_internal(self, t):
-        return t[..., :self.np + 2]
+        o = self.k_first
+        return t[..., o:o + self.np + 2]
 
 
 class Ensemble:

@@ -49,12 +49,13 @@ def test_workspace_bytes_and_argument_errors(lib):
 
 
 def test_field_size_limit(lib):
-    # one FP64 field (2 patches, ghosts, rows padded to 16) must stay below
-    # 4 GiB, since kernels address fields by 32-bit byte offsets
+    # one FP64 field (2 patches, ghosts, k = 0 at row element 16, rows padded
+    # to 16 elements) must stay below 4 GiB, since kernels address fields by
+    # 32-bit byte offsets
     assert yy.workspace_bytes(128, 384, 1152) > 0
-    assert yy.workspace_bytes(254, 766, 1342) > 0        # 2*256*768*1344*8 < 2^32
+    assert yy.workspace_bytes(254, 766, 1342) > 0        # 2*256*768*1360*8 < 2^32
     with pytest.raises(yy.YYError) as e:
-        yy.workspace_bytes(256, 768, 1360)               # 2*258*770*1376*8 > 2^32
+        yy.workspace_bytes(256, 768, 1360)               # 2*258*770*1392*8 > 2^32
     assert e.value.status == yy.YY_ERR_ARG
 
 
