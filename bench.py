@@ -64,8 +64,8 @@ def class_words():
     W["residual_up"] = (0.5 * (12 + 10), 0.5 * (1 + 3))
     W["pressure_1"] = (6.0, 3.0)
     W["pressure_2"] = (6.0, 5.0)
+    W["step_start"] = (28.0, 4.0)                        # 14 read, 14 written; p1, p2 copied
     W["extrap"] = (21.0, 0.0)
-    W["copy"] = (14.0, 4.0)
     return W
 
 

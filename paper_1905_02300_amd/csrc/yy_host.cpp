@@ -371,13 +371,15 @@ template <typename R> void set_coefs(Geo<R> &g, const yy_params &p)
 }  // namespace
 
 enum ProfClass {
-    PC_EXTRAP = 0, PC_COPY, PC_FILL, PC_RES_T, PC_RES_UR, PC_RES_UT, PC_RES_UP,
+    PC_START = 0, PC_EXTRAP, PC_FILL, PC_RES_T, PC_RES_UR, PC_RES_UT, PC_RES_UP,
     PC_SW_R, PC_SW_T, PC_SW_P, PC_SW_R_LAST, PC_SW_T_LAST, PC_SW_P_LAST,
     PC_PRESS1, PC_PRESS2, PC_REDUCE, PC_SW_P_LAST_T
 };
-// sweep_p_last: the last (phi) factor of u_phi; sweep_p_last_T: that of T
+// step_start: extrapolation and working level of a step (extrap: the
+// extrapolation alone, yy_extrapolate); sweep_p_last: the last (phi) factor
+// of u_phi; sweep_p_last_T: that of T
 static const char *prof_names[YY_NPROF] = {
-    "extrap", "copy", "fill", "residual_T", "residual_ur", "residual_ut", "residual_up",
+    "step_start", "extrap", "fill", "residual_T", "residual_ur", "residual_ut", "residual_up",
     "sweep_r", "sweep_t", "sweep_p", "sweep_r_last", "sweep_t_last", "sweep_p_last",
     "pressure_1", "pressure_2", "norm_reduce", "sweep_p_last_T"};
 
@@ -547,12 +549,8 @@ template <typename R> int step_impl(yy_shell *s, int K, double tol, int *k_done,
         s->need_fill = false;
     }
     {
-        Timed tm(s, PC_EXTRAP, st);
-        Ops<R>::extrap(s->L.d, S, st);
-    }
-    {
-        Timed tm(s, PC_COPY, st);
-        Ops<R>::copy_levels(s->L.d, S, 0, 2, st);
+        Timed tm(s, PC_START, st);
+        Ops<R>::extrap_copy(s->L.d, S, st);
     }
     int done = 0;
     for (int k = 0; k < K; k++) {
@@ -1018,8 +1016,11 @@ int yy_fill(yy_shell *s, int32_t level, hipStream_t st)
 int yy_extrapolate(yy_shell *s, hipStream_t st)
 {
     if (!s) return YY_ERR_ARG;
-    if (s->L.prec == YY_FP64) Ops<double>::extrap(s->L.d, s->s64, st);
-    else Ops<float>::extrap(s->L.d, s->s32, st);
+    {
+        Timed tm(s, PC_EXTRAP, st);
+        if (s->L.prec == YY_FP64) Ops<double>::extrap(s->L.d, s->s64, st);
+        else Ops<float>::extrap(s->L.d, s->s32, st);
+    }
     return hip_status(hipGetLastError());
 }
 

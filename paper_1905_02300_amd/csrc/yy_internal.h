@@ -152,7 +152,8 @@ constexpr int NSLOT = 10;        // norm slots
 // ---- launchers (yy_kernels.hip) ----
 template <typename R> struct Ops {
     static void extrap(const Dims &d, const State<R> &s, hipStream_t st);
-    static void copy_levels(const Dims &d, const State<R> &s, int from, int to, hipStream_t st);
+    // extrap, and the working level k = level n (fields and pressures)
+    static void extrap_copy(const Dims &d, const State<R> &s, hipStream_t st);
     static void fill(const Dims &d, const State<R> &s, int level, const FillScalar *cc, int ncc,
                      const FillVector *vt, int nvt, const FillVector *vp, int nvp,
                      double t_in, double t_out, const TRobin &tb, const WallLev &walls, int patch_mask,

@@ -240,15 +240,28 @@ __global__ void k_extrap(Ptr7<R> a, int64_t n)
     }
 }
 
+// start of a step: the extrapolated levels and the working iterate k = n in
+// one pass over level n (T, u1, u2; p1 and p2 copied)
+template <typename R> struct PtrStep {
+    R *s[7], *k[7];
+    const R *n[7], *m[7];
+    const double *p0, *p1;
+    double *p0k, *p1k;
+};
+
 template <typename R>
-__global__ void k_copy(Ptr7<R> a, int nf, const double *p0, double *p0d, const double *p1,
-                       double *p1d, int64_t n)
+__global__ void k_extrap_copy(PtrStep<R> a, int64_t n)
 {
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * blockDim.x) {
-        for (int f = 0; f < nf; f++) a.s[f][q] = a.n[f][q];
-        p0d[q] = p0[q];
-        p1d[q] = p1[q];
+#pragma unroll
+        for (int f = 0; f < 7; f++) {
+            const R v = a.n[f][q];
+            a.s[f][q] = R(1.5) * v - R(0.5) * a.m[f][q];
+            a.k[f][q] = v;
+        }
+        a.p0k[q] = a.p0[q];
+        a.p1k[q] = a.p1[q];
     }
 }
 
@@ -273,22 +286,22 @@ template <typename R> void Ops<R>::extrap(const Dims &d, const State<R> &s, hipS
     hipLaunchKernelGGL(k_extrap<R>, dim3(grid_for(n)), dim3(256), 0, st, a, n);
 }
 
-template <typename R>
-void Ops<R>::copy_levels(const Dims &d, const State<R> &s, int from, int to, hipStream_t st)
+template <typename R> void Ops<R>::extrap_copy(const Dims &d, const State<R> &s, hipStream_t st)
 {
-    Ptr7<R> a;
-    a.s[0] = s.T[to]; a.n[0] = s.T[from];
+    PtrStep<R> a;
+    a.s[0] = s.Ts; a.k[0] = s.T[2]; a.n[0] = s.T[0]; a.m[0] = s.T[1];
     int f = 1;
     for (int y = 0; y < 2; y++)
         for (int c = 0; c < 3; c++, f++) {
-            a.s[f] = s.u[y][c][to];
-            a.n[f] = s.u[y][c][from];
+            a.s[f] = s.us[y][c];
+            a.k[f] = s.u[y][c][2];
+            a.n[f] = s.u[y][c][0];
+            a.m[f] = s.u[y][c][1];
         }
-    const int pf = from == 0 ? 0 : 1, pt = to == 0 ? 0 : 1;
+    a.p0 = s.p[0][0]; a.p0k = s.p[0][1];
+    a.p1 = s.p[1][0]; a.p1k = s.p[1][1];
     const int64_t n = 2 * d.sP;
-    hipLaunchKernelGGL(k_copy<R>, dim3(grid_for(n)), dim3(256), 0, st, a, 7,
-                       (const double *)s.p[0][pf], s.p[0][pt], (const double *)s.p[1][pf],
-                       s.p[1][pt], n);
+    hipLaunchKernelGGL(k_extrap_copy<R>, dim3(grid_for(n)), dim3(256), 0, st, a, n);
 }
 
 
