@@ -369,7 +369,8 @@ def ensemble(args):
                       "shells": [list(s[:3]) + [round(s[3], 1)] for s in shapes]}), flush=True)
 
 
-_LINE_TILES_RT = ["t"] + ["m%dw%d" % (m, w) for m in (4, 6, 8, 12, 16) for w in (16, 32, 64)]
+_LINE_TILES_RT = ["t"] + ["m%dw%d%s" % (m, w, b) for m in (4, 6, 8, 12, 16) for w in (16, 32, 64)
+                          for b in ("", "b")]
 _LINE_TILES_P = ["l1", "l2", "l4", "v2", "v4", "v8"]
 
 

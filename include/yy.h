@@ -242,7 +242,8 @@ int yy_residual(yy_shell *s, int32_t field, void *dev_out, hipStream_t stream);
 /* Time every tile variant of the partitioned line solves of this shell
  * (strided r/theta sweeps: the per-line Thomas kernel, "t", or rows per
  * chunk 4/6/8/12/16 x lane width 64/32/16, "m<rows>w<lanes>", where the
- * lines fit; phi sweeps: one wave per line with 1/2/4 lines per
+ * lines fit, each also with all loads of a chunk issued together,
+ * "m<rows>w<lanes>b"; phi sweeps: one wave per line with 1/2/4 lines per
  * block, "l<lines>", or 2/4/8 waves per line, "v<waves>"), each on the
  * shell's own scratch buffer with its current advecting velocity and in
  * the form the step launches it (the last factor of an unknown fused with

@@ -1138,22 +1138,26 @@ extern "C" int yy_autotune(yy_shell *s, char *json_out, int32_t cap, hipStream_t
                 const int n = (dir == 0 ? s->L.d.nr : s->L.d.nt) - (L == dir + 1 ? 1 : 0);
                 T.m[L][dir] = 1;
                 T.w[L][dir] = 0;
-                int bm = 1, bw = 0;
+                T.bl[L][dir] = 0;
+                int bm = 1, bw = 0, bb = 0;
                 double best = time_sweep(s, tune_field_id[L], dir, st, a, b);
                 const int ms[5] = {4, 6, 8, 12, 16}, ws[3] = {64, 32, 16};
                 for (int im = 0; im < 5; im++)
-                    for (int iw = 0; iw < 3; iw++) {
-                        int W = 0, P = 0;
-                        if (!strided_tile(n, ms[im], ws[iw], W, P)) continue;
-                        T.m[L][dir] = (int8_t)ms[im];
-                        T.w[L][dir] = (int8_t)ws[iw];
-                        const double t = time_sweep(s, tune_field_id[L], dir, st, a, b);
-                        if (t < best) { best = t; bm = ms[im]; bw = ws[iw]; }
-                    }
+                    for (int iw = 0; iw < 3; iw++)
+                        for (int ib = 0; ib < 2; ib++) {
+                            int W = 0, P = 0;
+                            if (!strided_tile(n, ms[im], ws[iw], W, P)) continue;
+                            T.m[L][dir] = (int8_t)ms[im];
+                            T.w[L][dir] = (int8_t)ws[iw];
+                            T.bl[L][dir] = (int8_t)ib;
+                            const double t = time_sweep(s, tune_field_id[L], dir, st, a, b);
+                            if (t < best) { best = t; bm = ms[im]; bw = ws[iw]; bb = ib; }
+                        }
                 T.m[L][dir] = (int8_t)bm;
                 T.w[L][dir] = (int8_t)bw;
+                T.bl[L][dir] = (int8_t)bb;
                 if (bm == 1) std::snprintf(val, sizeof val, "t");
-                else std::snprintf(val, sizeof val, "m%dw%d", bm, bw);
+                else std::snprintf(val, sizeof val, "m%dw%d%s", bm, bw, bb ? "b" : "");
             } else {
                 // one wave per line with 1, 2 or 4 lines per block, or 2, 4 or
                 // 8 waves per line
@@ -1208,13 +1212,18 @@ extern "C" int yy_set_tuning(yy_shell *s, const char *json)
                 if (v[0] == 't' && v[1] == '"') {
                     T.m[L][dir] = 1;
                     T.w[L][dir] = 0;
+                    T.bl[L][dir] = 0;
                     continue;
                 }
-                if (std::sscanf(v, "m%dw%d", &m, &w) != 2) return YY_ERR_ARG;
+                int used = 0;
+                if (std::sscanf(v, "m%dw%d%n", &m, &w, &used) != 2) return YY_ERR_ARG;
                 if ((m != 4 && m != 6 && m != 8 && m != 12 && m != 16) || (w != 16 && w != 32 && w != 64))
                     return YY_ERR_ARG;
+                const bool bl = v[used] == 'b';
+                if (v[used + (bl ? 1 : 0)] != '"') return YY_ERR_ARG;
                 T.m[L][dir] = (int8_t)m;
                 T.w[L][dir] = (int8_t)w;
+                T.bl[L][dir] = (int8_t)bl;
             } else {
                 if (std::sscanf(v, "l%d", &l) == 1 && (l == 1 || l == 2 || l == 4)) {
                     T.lpb[L] = (int8_t)l;

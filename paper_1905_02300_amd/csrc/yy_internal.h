@@ -117,11 +117,11 @@ struct FillVector {
 // line-solver tile choices per location (CC, FR, FT, FP, and 4 for the
 // diffusion-only solves of the line-solve workload); 0 = built-in
 // default.  Strided r/theta sweeps: rows per chunk m (4, 6, 8, 12, 16; 1 =
-// the per-line Thomas kernel) and the
-// largest lane width w (64, 32, 16); phi sweeps: one wave per line and
-// lines per block lpb (1, 2, 4), or wpl (2, 4, 8) waves per line.
+// the per-line Thomas kernel), the largest lane width w (64, 32, 16) and
+// bl (1: all loads of a chunk issued together); phi sweeps: one wave per
+// line and lines per block lpb (1, 2, 4), or wpl (2, 4, 8) waves per line.
 struct Tune {
-    int8_t m[5][2], w[5][2], lpb[5], wpl[5];   // [4]: the diffusion-only line solves
+    int8_t m[5][2], w[5][2], bl[5][2], lpb[5], wpl[5];   // [4]: the diffusion-only line solves
 };
 
 // pointers of one step (compute precision R; pressures double)

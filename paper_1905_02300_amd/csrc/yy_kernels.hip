@@ -654,39 +654,73 @@ __global__ void __launch_bounds__(256) k_sweep(Dims d, Geo<R> g, Geo<double> gd,
         if (D == 0) { j = j0 + a; k = k0 + b; i = m0; }
         else if (D == 1) { i = i0 + a; k = k0 + b; j = m0; }
         else { i = i0 + a; j = j0 + b; k = m0; }
-        int64_t q = ix(d, p, i, j, k);
+        const int64_t q0 = ix(d, p, i, j, k);
+        // rows go in batches of TB: the loads of a batch are unconditional
+        // (rows past the line's end repeat its last row) and in flight
+        // together; the recurrences then run over the batch
+        constexpr int TB = 4;
         R cprev = R(0), dprev = R(0);
-        for (int m = 0; m < n; m++, q += stride) {
-            const int ii = D == 0 ? m0 + m : i, jj = D == 1 ? m0 + m : j;
-            R ar = R(0), at = R(0), ap = R(0);
-            if (!DIFF) adv<L>(s, d, q, ar, at, ap);
-            const Tri<R> c = true_metric<D, DIFF>(g, ii, jj, coef<L, D>(g, ii, jj, ar, at, ap, nu), nu);
-            const R lo = -ht * c.lo, up = -ht * c.up;
-            R di = R(1) - ht * c.di;
-            const bool tr = L == CC && !DIFF;
-            if (reflect && m == 0) di = R(1) - ht * (c.di - (tr ? g.rho_t[0] : R(1)) * c.lo);
-            if (reflect && m == n - 1) di = R(1) - ht * (c.di - (tr ? g.rho_t[1] : R(1)) * c.up);
-            const R den = di - lo * cprev;
-            const R cp = (m < n - 1) ? up / den : R(0);
-            const R dp = (x[q] - lo * dprev) / den;
-            cb[q] = cp;
-            y[q] = dp;
-            cprev = cp;
-            dprev = dp;
-        }
-        q -= stride;
-        R xn = R(0);
-        for (int m = n - 1; m >= 0; m--, q -= stride) {
-            const R xm = y[q] - cb[q] * xn;
-            xn = xm;
-            if (MODE == 0) {
-                y[q] = xm;
-            } else {
-                psi[q] += xm;
+        for (int mb = 0; mb < n; mb += TB) {
+            R lo[TB], di[TB], up[TB], xv[TB];
+#pragma unroll
+            for (int b = 0; b < TB; b++) {
+                const int m = mb + b < n ? mb + b : n - 1;
+                const int64_t q = q0 + (int64_t)m * stride;
                 const int ii = D == 0 ? m0 + m : i, jj = D == 1 ? m0 + m : j;
-                const double r0 = L == FR ? gd.rf[ii + 1] : gd.rc[ii + 1];
-                const double s0 = L == FT ? gd.sf[jj + 1] : gd.sc[jj + 1];
-                acc += r0 * r0 * s0 * gd.dr * gd.dth * gd.dph * (double)xm * (double)xm;
+                R ar = R(0), at = R(0), ap = R(0);
+                if (!DIFF) adv<L>(s, d, q, ar, at, ap);
+                const Tri<R> c = true_metric<D, DIFF>(g, ii, jj, coef<L, D>(g, ii, jj, ar, at, ap, nu), nu);
+                lo[b] = -ht * c.lo;
+                up[b] = -ht * c.up;
+                di[b] = R(1) - ht * c.di;
+                const bool tr = L == CC && !DIFF;
+                if (reflect && m == 0) di[b] = R(1) - ht * (c.di - (tr ? g.rho_t[0] : R(1)) * c.lo);
+                if (reflect && m == n - 1) di[b] = R(1) - ht * (c.di - (tr ? g.rho_t[1] : R(1)) * c.up);
+                xv[b] = x[q];
+            }
+#pragma unroll
+            for (int b = 0; b < TB; b++) {
+                const int m = mb + b;
+                if (m < n) {
+                    const int64_t q = q0 + (int64_t)m * stride;
+                    const R den = di[b] - lo[b] * cprev;
+                    const R cp = (m < n - 1) ? up[b] / den : R(0);
+                    const R dp = (xv[b] - lo[b] * dprev) / den;
+                    cb[q] = cp;
+                    y[q] = dp;
+                    cprev = cp;
+                    dprev = dp;
+                }
+            }
+        }
+        R xn = R(0);
+        for (int mb = n - 1; mb >= 0; mb -= TB) {
+            R yv[TB], cv[TB], pv[TB];
+#pragma unroll
+            for (int b = 0; b < TB; b++) {
+                const int m = mb - b >= 0 ? mb - b : 0;
+                const int64_t q = q0 + (int64_t)m * stride;
+                yv[b] = y[q];
+                cv[b] = cb[q];
+                if (MODE == 1) pv[b] = psi[q];
+            }
+#pragma unroll
+            for (int b = 0; b < TB; b++) {
+                const int m = mb - b;
+                if (m >= 0) {
+                    const int64_t q = q0 + (int64_t)m * stride;
+                    const R xm = yv[b] - cv[b] * xn;
+                    xn = xm;
+                    if (MODE == 0) {
+                        y[q] = xm;
+                    } else {
+                        psi[q] = pv[b] + xm;
+                        const int ii = D == 0 ? m0 + m : i, jj = D == 1 ? m0 + m : j;
+                        const double r0 = L == FR ? gd.rf[ii + 1] : gd.rc[ii + 1];
+                        const double s0 = L == FT ? gd.sf[jj + 1] : gd.sc[jj + 1];
+                        acc += r0 * r0 * s0 * gd.dr * gd.dth * gd.dph * (double)xm * (double)xm;
+                    }
+                }
             }
         }
     }
@@ -850,7 +884,11 @@ __host__ __device__ inline int sweep_ktiles(int np, int W) { return (np + W - 1)
 
 // Strided lines (D = 0: r, D = 1: theta).  Block (W, P): lane x <-> k (W
 // consecutive k, coalesced), y <-> chunk.  A task = (k-tile, other index).
-template <typename R, int L, int D, int MODE, int DIFF, int M>
+// BL: every load of a chunk (and its psi, last factor) is issued before the
+// elimination, rows past the chunk's end repeating its last row, so that
+// they are in flight together (more registers); otherwise each row is
+// loaded as it is eliminated.  The autotuner picks per sweep.
+template <typename R, int L, int D, int MODE, int DIFF, int M, bool BL>
 __global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<double> gd, State<R> s,
                                                         const R *x, R *y, R *psi, double *partial)
 {
@@ -884,18 +922,32 @@ __global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<dou
 #pragma unroll
         for (int m = 0; m < M; m++) { a[m] = R(0); c[m] = R(0); dd[m] = R(0); }
         const int64_t qf = ix(d, p, D == 0 ? m0 + r0 : i, D == 1 ? m0 + r0 : j, k);
+        R pv[M];                           // psi of the chunk (BL, last factor)
         if (live) {
+            if (BL) {
 #pragma unroll
-            for (int m = 0; m < M; m++) {
-                if (m < mt) {
-                    const int gr = r0 + m;
+                for (int m = 0; m < M; m++) {
+                    const int mm = m < mt ? m : mt - 1;
+                    const int gr = r0 + mm;
                     const int ii = D == 0 ? m0 + gr : i, jj = D == 1 ? m0 + gr : j;
-                    const int64_t q = qf + (int64_t)m * stride;
+                    const int64_t q = qf + (int64_t)mm * stride;
                     R lo, di, up;
                     line_row<R, L, D, DIFF>(d, g, s, q, ii, jj, gr, n, nu, lo, di, up);
+                    if (MODE == 1) pv[m] = psi[q];
                     chunk_forward<R, M>(a, c, dd, m, lo, di, up, x[q]);
-                } else {
-                    a[m] = R(0); c[m] = R(0); dd[m] = R(0);
+                    if (m >= mt) { a[m] = R(0); c[m] = R(0); dd[m] = R(0); }
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < M; m++) {
+                    if (m < mt) {
+                        const int gr = r0 + m;
+                        const int ii = D == 0 ? m0 + gr : i, jj = D == 1 ? m0 + gr : j;
+                        const int64_t q = qf + (int64_t)m * stride;
+                        R lo, di, up;
+                        line_row<R, L, D, DIFF>(d, g, s, q, ii, jj, gr, n, nu, lo, di, up);
+                        chunk_forward<R, M>(a, c, dd, m, lo, di, up, x[q]);
+                    }
                 }
             }
             chunk_backward<R, M>(a, c, dd, mt);
@@ -950,7 +1002,7 @@ __global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<dou
                     if (MODE == 0) {
                         y[q] = v;
                     } else {
-                        psi[q] += v;
+                        psi[q] = (BL ? pv[m] : psi[q]) + v;
                         acc += vol_at<L, D>(gd, ii, jj) * (double)v * (double)v;
                     }
                 }
@@ -1008,15 +1060,25 @@ __global__ void __launch_bounds__(256) k_sweep_contig(Dims d, Geo<R> g, Geo<doub
         const int i = i0 + (int)(lv ? line / nj : 0), j = j0 + (int)(lv ? line % nj : 0);
         const int64_t q0 = ix(d, p, i, j, k0);
         if (lv) {
-            for (int e = lane; e < n; e += 64) {
-                R lo, di, up;
-                line_row<R, L, 2, DIFF>(d, g, s, q0 + e, i, j, e, n, nu, lo, di, up);
-                const int cc = e / mc, rr = e - cc * mc;
-                const int o = rr * ld + cc;
-                tlo[o] = lo;
-                tdi[o] = di;
-                tup[o] = up;
-                tx[o] = x[q0 + e];
+            // batches of CB rows per lane, all loads of a batch in flight
+            // together (rows past the end repeat the last one)
+            constexpr int CB = 4;
+            for (int e0 = lane; e0 < n; e0 += 64 * CB) {
+#pragma unroll
+                for (int b = 0; b < CB; b++) {
+                    const int e = e0 + 64 * b, ec = e < n ? e : n - 1;
+                    R lo, di, up;
+                    line_row<R, L, 2, DIFF>(d, g, s, q0 + ec, i, j, ec, n, nu, lo, di, up);
+                    const R xv = x[q0 + ec];
+                    if (e < n) {
+                        const int cc = e / mc, rr = e - cc * mc;
+                        const int o = rr * ld + cc;
+                        tlo[o] = lo;
+                        tdi[o] = di;
+                        tup[o] = up;
+                        tx[o] = xv;
+                    }
+                }
             }
         }
         __syncthreads();
@@ -1063,14 +1125,30 @@ __global__ void __launch_bounds__(256) k_sweep_contig(Dims d, Geo<R> g, Geo<doub
         __syncthreads();
         if (lv) {
             const double vol = MODE == 1 ? vol_at<L, 2>(gd, i, j) : 0.0;
-            for (int e = lane; e < n; e += 64) {
-                const int cc = e / mc, rr = e - cc * mc;
-                const R v = tx[rr * ld + cc];
-                if (MODE == 0) {
-                    y[q0 + e] = v;
-                } else {
-                    psi[q0 + e] += v;
-                    acc += vol * (double)v * (double)v;
+            if (MODE == 0) {
+                for (int e = lane; e < n; e += 64) {
+                    const int cc = e / mc, rr = e - cc * mc;
+                    y[q0 + e] = tx[rr * ld + cc];
+                }
+            } else {
+                constexpr int CB = 4;
+                for (int e0 = lane; e0 < n; e0 += 64 * CB) {
+                    R pv[CB];
+#pragma unroll
+                    for (int b = 0; b < CB; b++) {
+                        const int e = e0 + 64 * b;
+                        pv[b] = psi[q0 + (e < n ? e : n - 1)];
+                    }
+#pragma unroll
+                    for (int b = 0; b < CB; b++) {
+                        const int e = e0 + 64 * b;
+                        if (e < n) {
+                            const int cc = e / mc, rr = e - cc * mc;
+                            const R v = tx[rr * ld + cc];
+                            psi[q0 + e] = pv[b] + v;
+                            acc += vol * (double)v * (double)v;
+                        }
+                    }
                 }
             }
         }
@@ -1237,21 +1315,19 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
         if (b > SWEEP_BLOCKS) b = SWEEP_BLOCKS;
         if (nblocks) *nblocks = (int)b;
         const size_t lds = (size_t)4 * P * W * sizeof(R);
-        if (M == 4)
-            hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, 4>), dim3((unsigned)b, d.npatch), dim3(W, P),
-                               lds, st, d, g, gd, s, x, y, psi, partial);
-        else if (M == 6)
-            hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, 6>), dim3((unsigned)b, d.npatch), dim3(W, P),
-                               lds, st, d, g, gd, s, x, y, psi, partial);
-        else if (M == 8)
-            hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, 8>), dim3((unsigned)b, d.npatch), dim3(W, P),
-                               lds, st, d, g, gd, s, x, y, psi, partial);
-        else if (M == 12)
-            hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, 12>), dim3((unsigned)b, d.npatch), dim3(W, P),
-                               lds, st, d, g, gd, s, x, y, psi, partial);
-        else
-            hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, 16>), dim3((unsigned)b, d.npatch), dim3(W, P),
-                               lds, st, d, g, gd, s, x, y, psi, partial);
+        const bool bl = s.tune.bl[TL][D] != 0;
+#define YY_ST(MM, BB)                                                                                     \
+    hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, MM, BB>), dim3((unsigned)b, d.npatch),      \
+                       dim3(W, P), lds, st, d, g, gd, s, x, y, psi, partial)
+#define YY_STM(MM) \
+    do { if (bl) YY_ST(MM, true); else YY_ST(MM, false); } while (0)
+        if (M == 4) YY_STM(4);
+        else if (M == 6) YY_STM(6);
+        else if (M == 8) YY_STM(8);
+        else if (M == 12) YY_STM(12);
+        else YY_STM(16);
+#undef YY_STM
+#undef YY_ST
         return true;
     } else {
         const int n = d.np - k0;

@@ -447,9 +447,11 @@ def test_ensemble_graph_matches_eager(yy):
         assert np.array_equal(ens[0].shells[q].norms(), ens[1].shells[q].norms())
 
 
-@pytest.mark.parametrize("variant", ["t", "m4w16", "m6w32", "m8w64", "m8w16", "m12w32", "m16w64", "m16w16"])
+@pytest.mark.parametrize("variant", ["t", "m4w16", "m6w32", "m8w64", "m8w16", "m12w32", "m16w64", "m16w16",
+                                     "m4w16b", "m6w32b", "m8w64b", "m12w32b", "m16w16b"])
 def test_sweep_parity_every_tile(oracle_lib, yy, variant):
-    """Every tile choice the autotuner can make gives the oracle's answer."""
+    """Every tile choice the autotuner can make gives the oracle's answer,
+    alone and (with the last factor fused with the update) in whole steps."""
     print(f"case: tile {variant}", flush=True)
     shape = (40, 48, 144)
     o, g = _pair(oracle_lib, yy, *shape, pr=1.1, dt=1e-3, chi=0.9)
@@ -458,7 +460,8 @@ def test_sweep_parity_every_tile(oracle_lib, yy, variant):
     o.extrapolate()
     g.extrapolate()
     phi = {"t": "v4", "m4w16": "v2", "m6w32": "l1", "m8w64": "l1", "m8w16": "l2", "m12w32": "l4", "m16w64": "v2",
-           "m16w16": "v4"}[variant]
+           "m16w16": "v4", "m4w16b": "l2", "m6w32b": "v8", "m8w64b": "l4", "m12w32b": "v2",
+           "m16w16b": "l1"}[variant]
     js = "{" + ",".join(f'"{f}.{d}":"{variant}"' for f in ("T", "u_r", "u_t", "u_p") for d in "rt")
     js += "," + ",".join(f'"{f}.p":"{phi}"' for f in ("T", "u_r", "u_t", "u_p")) + "}"
     g.set_tuning(js)
@@ -471,6 +474,13 @@ def test_sweep_parity_every_tile(oracle_lib, yy, variant):
             g.sweep(field, d, g.to_internal(x), yt)
             got = g.from_internal(yt).cpu().numpy()
             assert _rel(got[m], ref[m]) <= TOL, (field, d, _rel(got[m], ref[m]))
+    o, g, grid = _mms_pair(oracle_lib, yy, 34, 40, 120, 1e-3)
+    g.set_tuning(js)
+    _mms_steps(o, g, grid, 1e-3, 2, 2)
+    for f in range(9):
+        a = g.get_field(f).cpu().numpy()
+        b = o.get_field(f)
+        assert _rel(a, b) <= TOL, (I.FIELD_NAMES[f], _rel(a, b))
 
 
 @pytest.mark.parametrize("variant", ["v2", "v4", "v8"])
@@ -513,3 +523,6 @@ def test_autotune_round_trip(yy):
     g.set_tuning(js)
     with pytest.raises(yy.YYError):
         g.set_tuning('{"T.r":"m7w64"}')
+    g.set_tuning('{"T.r":"m8w32b","u_t.t":"m6w16"}')
+    with pytest.raises(yy.YYError):
+        g.set_tuning('{"T.r":"m8w32x"}')
