@@ -92,6 +92,11 @@ def main():
     ap.add_argument("--mms-delta", type=float, default=0.0,
                     help="overlap of the --paper-mms grids (radians; 0: one cell)")
     ap.add_argument("--mms-tf", type=float, default=1.0, help="final time of the --paper-mms time study")
+    ap.add_argument("--mms-chi", type=float, default=4.0,
+                    help="artificial-compressibility parameter chi of the --paper-mms runs")
+    ap.add_argument("--mms-tol", type=float, default=1e-6,
+                    help="Schwarz stop tolerance of the --paper-mms time study (the paper's 1e-6)")
+    ap.add_argument("--mms-kmax", type=int, default=64, help="Schwarz iteration cap of the --paper-mms runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -194,9 +199,9 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def _paper_run(nr, nt, np_, tau, tf, delta, tol=1e-6, kmax=64):
+def _paper_run(nr, nt, np_, tau, tf, delta, chi, tol=1e-6, kmax=64, keep=False):
     """The manufactured solution of the paper's numerical tests (eq. Exact:
-    R1=1, R2=2, Ra=Pr=1, chi=1, FP64, additive Schwarz) from its exact
+    R1=1, R2=2, Ra=Pr=1, the given chi, FP64, additive Schwarz) from its exact
     levels at t=0 and -tau, with its time-dependent wall data and forcing,
     Schwarz iterations until every increment norm < tol (the paper's stop
     test with its 1e-6); returns the l2 and max errors of u2, p2, T at tf."""
@@ -206,7 +211,7 @@ def _paper_run(nr, nt, np_, tau, tf, delta, tol=1e-6, kmax=64):
     pr, ra, kind = 1.0, 1.0, "paper"
     grid = I.Grid(nr, nt, np_, 1.0, 2.0, delta)
     sh = yy.Shell(nr, nt, np_, 1.0, 2.0, delta)
-    sh.set_params(pr=pr, ra=ra, dt=tau, chi=1.0, t_inner=0.0, t_outer=0.0)
+    sh.set_params(pr=pr, ra=ra, dt=tau, chi=chi, t_inner=0.0, t_outer=0.0)
     dev = sh.ws.device
     wf = (I.T, I.U1R, I.U1T, I.U1P)
     walls = {f: torch.as_tensor(I.wall_parts(grid, f, kind), device=dev) for f in wf}
@@ -246,10 +251,14 @@ def _paper_run(nr, nt, np_, tau, tf, delta, tol=1e-6, kmax=64):
         # midpoint l2 with the cell-centre volume of the nearest cell
         ec = e[:, :grid.nr, :grid.nt, :grid.np]
         err[name] = {"l2": float(np.sqrt(np.sum(vol * ec * ec))), "max": float(np.abs(e).max())}
-    return {"grid": [nr, nt, np_], "overlap": delta, "tau": tau, "steps": nsteps,
-            "iterations": [min(iters), max(iters)],
-            "mean_iterations": float(np.mean(iters)), "seconds": el,
-            "mcell_steps_s": grid.cells * nsteps / el / 1e6, "errors": err}
+    res = {"grid": [nr, nt, np_], "overlap": delta, "chi": chi, "tau": tau, "steps": nsteps,
+           "iterations": [min(iters), max(iters)],
+           "mean_iterations": float(np.mean(iters)), "seconds": el,
+           "mcell_steps_s": grid.cells * nsteps / el / 1e6, "errors": err}
+    if keep:
+        res["_fields"] = {f: sh.get_field(f).cpu().numpy() for f in (I.U2R, I.U2T, I.U2P, I.P2, I.T)}
+        res["_vol"] = vol
+    return res
 
 
 def paper_mms(args):
@@ -257,21 +266,44 @@ def paper_mms(args):
     paper's grid 20x92x192 -- time convergence at Tf = 10 -- and a space
     convergence study (tau = 1e-3, Tf = 0.1) on 10x46x96, 20x92x192,
     40x184x384; prints the errors and the observed orders."""
-    out = {"workload": "paper_mms_eq_exact_R1_1_R2_2", "tol": 1e-6, "overlap": args.mms_delta,
-           "time_tf": args.mms_tf, "time": [], "space": []}
+    out = {"workload": "paper_mms_eq_exact_R1_1_R2_2", "tol": args.mms_tol, "kmax": args.mms_kmax,
+           "overlap": args.mms_delta,
+           "chi": args.mms_chi, "time_tf": args.mms_tf, "time": [], "space": []}
     from paper_1905_02300_amd import yy
 
-    def run(*a):
+    def run(*a, keep=False, tol=1e-6):
         try:
-            res = _paper_run(*a)
+            res = _paper_run(*a, tol=tol, kmax=args.mms_kmax, keep=keep)
         except yy.YYError as e:
             res = {"grid": list(a[:3]), "tau": a[3], "overlap": a[5], "error": str(e)}
-        print(json.dumps(res), file=sys.stderr, flush=True)
+        print(json.dumps({k: v for k, v in res.items() if not k.startswith("_")}), file=sys.stderr, flush=True)
         return res
 
     taus = [float(x) for x in args.mms_taus.split(",")]
-    out["time"] = [run(20, 92, 192, tau, args.mms_tf, args.mms_delta) for tau in taus]
-    out["space"] = [run(10 * m, 46 * m, 96 * m, 1e-3, 0.1, args.mms_delta) for m in (1, 2, 4)]
+    out["time"] = [run(20, 92, 192, tau, args.mms_tf, args.mms_delta, args.mms_chi, keep=True, tol=args.mms_tol)
+                   for tau in taus]
+    # the time error alone: differences of successive runs at the final time
+    # (the spatial error of the common grid cancels), l2 with cell volumes
+    from paper_1905_02300_amd import inputs as I
+    names = {I.U2R: "u_r", I.U2T: "u_theta", I.U2P: "u_phi", I.P2: "p", I.T: "T"}
+    kept = [r for r in out["time"] if "_fields" in r]
+    diffs = []
+    for q in range(len(kept) - 1):
+        a, b, vol = kept[q]["_fields"], kept[q + 1]["_fields"], kept[q]["_vol"]
+        nr, nt, np_ = kept[q]["grid"]
+        dq = {}
+        for f, name in names.items():
+            e = (a[f] - b[f])[:, :nr, :nt, :np_]
+            dq[name] = float(np.sqrt(np.sum(vol * e * e)))
+        diffs.append({"taus": [kept[q]["tau"], kept[q + 1]["tau"]], "l2_difference": dq})
+    out["time_differences"] = diffs
+    if len(diffs) >= 2:
+        out["time_self_orders"] = {name: [math.log2(diffs[q]["l2_difference"][name] / diffs[q + 1]["l2_difference"][name])
+                                          for q in range(len(diffs) - 1)] for name in names.values()}
+    for r in out["time"]:
+        r.pop("_fields", None)
+        r.pop("_vol", None)
+    out["space"] = [run(10 * m, 46 * m, 96 * m, 1e-3, 0.1, args.mms_delta, args.mms_chi) for m in (1, 2, 4)]
     for key in ("time", "space"):
         runs = [r for r in out[key] if "errors" in r]
         if len(runs) < 2:
