@@ -112,13 +112,13 @@ def test_wall_data_residual_consistency(oracle_lib):
         assert bad2[f][1] > 3.0 * bad1[f][1], (I.FIELD_NAMES[f], bad1[f], bad2[f])
 
 
-def _paper_run(y, g, tau, nsteps, tol):
+def _paper_run(y, g, tau, nsteps, tol, chi=1.0):
     """The paper's manufactured solution stepped with its time-dependent
     wall data (level k gets t^{n+1} before each step) and the tolerance
     loop; returns the shell and the iteration counts."""
     pr, ra = 1.0, 1.0
     sh = y.Shell(g.nr, g.nt, g.np, g.r1, g.r2)
-    sh.set_params(pr=pr, ra=ra, tau=tau, chi=1.0)
+    sh.set_params(pr=pr, ra=ra, tau=tau, chi=chi)
     for lev, t in ((y.LEV_N, 0.0), (y.LEV_NM1, -tau)):
         st = I.mms_state(g, t, kind="paper")
         for f in range(9):
@@ -155,6 +155,30 @@ def test_paper_mms_spatial_order(oracle_lib):
         rate = math.log2(err[0][f] / err[1][f])
         lim = 1.6 if f in (I.T, I.U1R, I.U1T, I.U1P) else 1.8
         assert rate > lim, (I.FIELD_NAMES[f], err[0][f], err[1][f])
+
+
+@pytest.mark.slow
+def test_paper_mms_long_run_bounded(oracle_lib):
+    """With chi = 4 the paper's manufactured solution stays bounded over a
+    long run (150 steps of tau = 5e-3 on 6x24x72, past the point where
+    chi = 1 grows without bound): the Schwarz count stays low and the error
+    at the end is no larger than early on (the solution itself decays like
+    cos t).  Sec. 5.1 reports the test to Tf = 10."""
+    y = oracle_lib
+    g = I.Grid(6, 24, 72, 1.0, 2.0)
+    tau = 5e-3
+    sh, ks = _paper_run(y, g, tau, 20, 1e-6, chi=4.0)
+    early = {f: np.max(np.abs(sh.get_field(f) - I.mms_fields(g, 20 * tau, f, kind="paper")))
+             for f in (I.U2R, I.U2T, I.U2P, I.T)}
+    for s in range(20, 150):
+        for f in _WALL_FIELDS:
+            sh.set_forcing(f, I.mms_forcing(g, (s + 0.5) * tau, f, 1.0, 1.0, kind="paper"))
+        _paper_walls(y, sh, g, y.LEV_K, (s + 1) * tau)
+        ks.append(sh.step_tol(30, 1e-6))
+    assert max(ks[20:]) <= 15, ks
+    for f, e0 in early.items():
+        e = np.max(np.abs(sh.get_field(f) - I.mms_fields(g, 150 * tau, f, kind="paper")))
+        assert e < 1.2 * e0, (I.FIELD_NAMES[f], e0, e)
 
 
 def _net_flux(g, ur, ut, up):
