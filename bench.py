@@ -178,6 +178,8 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(args.cpu_grid, pr, ra, dt, K)
+        if line is not None:
+            line["cpu_baseline"] = line_solve_cpu()
 
     out = {
         "metric": METRIC, "value": value, "unit": "Mcell-steps/s", "n_gpus": 1,
@@ -459,6 +461,27 @@ def line_solve_bench(nr=64, nt=192, np_=576, reps=20, nbuf=6):
         del xs, ys, sh
         torch.cuda.empty_cache()
     return out
+
+
+def line_solve_cpu(nr=64, nt=192, np_=576):
+    """The oracle's line solves (per-line Thomas in FP64 on the host cores)
+    on the same 2x64x192x576 workload and right-hand side as the GPU
+    line-solve benchmark: one sweep per direction, same 2-words-per-cell
+    accounting."""
+    from oracle import yyo
+    from paper_1905_02300_amd import inputs as I
+    g = I.Grid(nr, nt, np_)
+    o = yyo.Shell(nr, nt, np_)
+    o.set_params(pr=1.0, tau=1e-3)
+    x = I.line_rhs(g, seed=2)
+    res = {"kind": "oracle", "cores": yyo.omp_threads(), "unit": "GB/s"}
+    for name, op in (("r", yyo.OP_DRR), ("t", yyo.OP_DTT_HAT), ("p", yyo.OP_DPP_HAT)):
+        t0 = time.perf_counter()
+        o.sweep_op(op, x)
+        el = time.perf_counter() - t0
+        res[name] = {"ms": el * 1e3, "gbs": 2 * 8 * g.cells / el / 1e9}
+    o.close()
+    return res
 
 
 def cpu_baseline(grid_s, pr, ra, dt, K):
