@@ -406,6 +406,33 @@ def test_deterministic(oracle_lib, yy):
         assert np.array_equal(a, b)
 
 
+def _mms_steps_from(g, grid, dt, s0, s1, K):
+    for s in range(s0, s1):
+        for f in (I.T, I.U1R, I.U1T, I.U1P):
+            g.set_forcing(f, I.mms_forcing(grid, (s + 0.5) * dt, f, 1.0, 1e3))
+        g.step(K)
+
+
+def test_restart_bitwise(oracle_lib, yy):
+    """10 steps equal 5 steps, a save of levels n and n-1 through the C-ABI,
+    a fresh shell restored from it, and 5 more steps: bitwise."""
+    print("case: restart", flush=True)
+    dt = 1e-3
+    _, a, grid = _mms_pair(oracle_lib, yy, 16, 24, 72, dt)
+    _mms_steps_from(a, grid, dt, 0, 10, 2)
+    _, b, _ = _mms_pair(oracle_lib, yy, 16, 24, 72, dt)
+    _mms_steps_from(b, grid, dt, 0, 5, 2)
+    saved = {(f, lev): b.get_field(f, lev).cpu().numpy() for f in range(9) for lev in (0, 1)
+             if not (lev == 1 and f in (I.P1, I.P2))}
+    del b
+    _, c, _ = _mms_pair(oracle_lib, yy, 16, 24, 72, dt)
+    for (f, lev), v in saved.items():
+        c.set_field(f, lev, v)
+    _mms_steps_from(c, grid, dt, 5, 10, 2)
+    for f in range(9):
+        assert np.array_equal(a.get_field(f).cpu().numpy(), c.get_field(f).cpu().numpy()), I.FIELD_NAMES[f]
+
+
 def test_nonfinite_is_reported(oracle_lib, yy):
     print("case: non-finite", flush=True)
     _, g, grid = _mms_pair(oracle_lib, yy, 8, 12, 36, 1e-3)

@@ -187,3 +187,57 @@ def test_sweep_op_line_solves(oracle_lib):
         v = sh.sweep_op(op, x)
         back = v - 0.5 * tau * pr * sh.apply_op(I.T, op, v)
         assert np.max(np.abs(back[m] - x[m])) < 1e-12, op
+
+
+@pytest.mark.parametrize("tau", [0.05, 1.0, 100.0])
+def test_heat_split_energy_estimate(oracle_lib, tau):
+    """Discrete form of eq. Stability (Sec. 3.2): the split heat scheme
+    [I - tau/2 D_rr][I - tau/2 Dhat_thth][I - tau/2 Dhat_phph] dT^{n+1}/tau
+    = Lap T* - Lap^ dT^n / 2 on each patch with homogeneous Dirichlet data
+    dissipates the energy
+      E^n = (-Lap T^n, T^n)_w / 2 + ((-Lap^ dT^n, dT^n)_w - (-Lap dT^n, dT^n)_w) / 4
+    (the omega_1, omega_2 terms of the estimate are the last bracket):
+    E^{n+1} + tau |dT^{n+1}/tau|_w^2 <= E^n for every tau."""
+    y = oracle_lib
+    g = I.Grid(6, 12, 36)
+    o = y.Shell(g.nr, g.nt, g.np)
+    o.set_params(pr=1.0, tau=tau)
+    rng = np.random.default_rng(9)
+    sh = o.padded_shape()
+    mask = np.zeros(sh, bool)
+    mask[:, 1:-1, 1:-1, 1:-1] = True
+
+    def rnd():
+        a = np.zeros(sh)
+        a[mask] = rng.standard_normal(int(mask.sum()))
+        return a
+
+    r = g.r1 + (np.arange(-1, g.nr + 1) + 0.5) * g.dr
+    th = g.th0 + (np.arange(-1, g.nt + 1) + 0.5) * g.dth
+    w = (r[None, :, None, None] ** 2 * np.sin(th)[None, None, :, None] * g.dr * g.dth * g.dph) * mask
+
+    def ip(a, b):
+        return float(np.sum(w * a * b))
+
+    def lap(x):
+        return sum(o.apply_op(I.T, op, x) for op in (y.OP_DRR, y.OP_DTT, y.OP_DPP))
+
+    def laph(x):
+        return sum(o.apply_op(I.T, op, x) for op in (y.OP_DRR, y.OP_DTT_HAT, y.OP_DPP_HAT))
+
+    def energy(tn, tm):
+        d = tn - tm
+        return 0.5 * ip(-lap(tn), tn) + 0.25 * (ip(-laph(d), d) - ip(-lap(d), d))
+
+    tm = rnd()
+    tn = tm + 0.1 * rnd()
+    e = energy(tn, tm)
+    for _ in range(20):
+        rhs = tau * (lap(1.5 * tn - 0.5 * tm) - 0.5 * laph(tn - tm))
+        d = o.sweep_op(y.OP_DRR, rhs)
+        d = o.sweep_op(y.OP_DTT_HAT, d)
+        d = o.sweep_op(y.OP_DPP_HAT, d)
+        tp = tn + d * mask
+        e1 = energy(tp, tn)
+        assert e1 + tau * ip(d / tau, d / tau) <= e * (1 + 1e-12), (tau, e, e1)
+        e, tm, tn = e1, tn, tp
