@@ -181,6 +181,59 @@ def test_paper_mms_long_run_bounded(oracle_lib):
         assert e < 1.2 * e0, (I.FIELD_NAMES[f], e0, e)
 
 
+def test_radial_reduction_matches_1d_crank_nicolson(oracle_lib):
+    """Radially symmetric T with u = 0, Ra = 0 and Dirichlet walls: the whole
+    scheme (fill, residual, three sweeps, Schwarz iterations) reduces to
+    Crank-Nicolson for r^-2 d/dr(r^2 dT/dr) (Sec. 3.2 with the hat terms
+    vanishing on angle-independent data), here an independent dense 1-D
+    solve with the wall values entering by reflection.  The Schwarz
+    iteration contracts slowly at a one-cell overlap, so 40 iterations per
+    step leave ~1e-8; a Cartesian second difference in place of the
+    spherical one is off by 0.1."""
+    y = oracle_lib
+    g = I.Grid(8, 12, 36)
+    tau, n_steps, tin, tout = 1e-2, 6, 1.0, 0.2
+    o = y.Shell(g.nr, g.nt, g.np)
+    o.set_params(pr=1.0, ra=0.0, tau=tau, t_inner=tin, t_outer=tout)
+    rc = g.r1 + (np.arange(g.nr) + 0.5) * g.dr
+    rf = g.r1 + np.arange(g.nr + 1) * g.dr
+    s = (rc - g.r1) / (g.r2 - g.r1)
+    t0 = tin + (tout - tin) * s + 0.3 * np.sin(np.pi * s)
+    tf = np.broadcast_to(t0[None, :, None, None], g.mac_shape(I.T)).copy()
+    for f in range(9):
+        z = np.zeros(g.mac_shape(f))
+        o.set_field(f, y.LEV_N, tf if f == I.T else z)
+        if f not in (I.P1, I.P2):
+            o.set_field(f, y.LEV_NM1, tf if f == I.T else z)
+    for _ in range(n_steps):
+        o.step(40)
+    n = g.nr
+    A = np.zeros((n, n))
+    b = np.zeros(n)
+    for i in range(n):
+        cl = rf[i] ** 2 / (rc[i] ** 2 * g.dr ** 2)
+        cu = rf[i + 1] ** 2 / (rc[i] ** 2 * g.dr ** 2)
+        A[i, i] -= cl + cu
+        if i > 0:
+            A[i, i - 1] += cl
+        else:                       # ghost = 2 T(R1) - T_0
+            A[i, i] -= cl
+            b[i] += 2.0 * tin * cl
+        if i < n - 1:
+            A[i, i + 1] += cu
+        else:
+            A[i, i] -= cu
+            b[i] += 2.0 * tout * cu
+    t = t0.copy()
+    eye = np.eye(n)
+    for _ in range(n_steps):
+        t = np.linalg.solve(eye - 0.5 * tau * A, (eye + 0.5 * tau * A) @ t + tau * b)
+    got = o.get_field(I.T)
+    change = np.max(np.abs(t - t0))
+    assert change > 0.1
+    assert np.max(np.abs(got - t[None, :, None, None])) < 1e-6 * change
+
+
 def test_restart_bitwise(oracle_lib):
     """10 steps equal 5 steps, a save of levels n and n-1 (every field), a
     fresh shell restored from it, and 5 more steps, bitwise: the two levels
