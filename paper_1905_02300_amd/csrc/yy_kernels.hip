@@ -1188,14 +1188,20 @@ __global__ void __launch_bounds__(512) k_sweep_contig_mw(Dims d, Geo<R> g, Geo<d
     for (int64_t line = blockIdx.x; line < nlines; line += gridDim.x) {
         const int i = i0 + (int)(line / nj), j = j0 + (int)(line % nj);
         const int64_t q0 = ix(d, p, i, j, k0);
+        // the diffusion-only operators have one (lower, diagonal, upper)
+        // per phi line (the ends drop their outer coupling): only x is staged
+        R clo = R(0), cdi = R(0), cup = R(0);
+        if (DIFF) line_row<R, L, 2, DIFF>(d, g, s, q0 + 1, i, j, 1, n, nu, clo, cdi, cup);
         for (int e = tid; e < n; e += nthr) {
-            R lo, di, up;
-            line_row<R, L, 2, DIFF>(d, g, s, q0 + e, i, j, e, n, nu, lo, di, up);
             const int cc = e / mc, rr = e - cc * mc;
             const int o = rr * ld + cc;
-            tlo[o] = lo;
-            tdi[o] = di;
-            tup[o] = up;
+            if (!DIFF) {
+                R lo, di, up;
+                line_row<R, L, 2, DIFF>(d, g, s, q0 + e, i, j, e, n, nu, lo, di, up);
+                tlo[o] = lo;
+                tdi[o] = di;
+                tup[o] = up;
+            }
             tx[o] = x[q0 + e];
         }
         __syncthreads();
@@ -1205,7 +1211,12 @@ __global__ void __launch_bounds__(512) k_sweep_contig_mw(Dims d, Geo<R> g, Geo<d
             a[m] = R(0); c[m] = R(0); dd[m] = R(0);
             if (m < mt) {
                 const int o = m * ld + tid;
-                chunk_forward<R, M>(a, c, dd, m, tlo[o], tdi[o], tup[o], tx[o]);
+                if (DIFF) {
+                    const int gr = tid * mc + m;
+                    chunk_forward<R, M>(a, c, dd, m, gr > 0 ? clo : R(0), cdi, gr < n - 1 ? cup : R(0), tx[o]);
+                } else {
+                    chunk_forward<R, M>(a, c, dd, m, tlo[o], tdi[o], tup[o], tx[o]);
+                }
             }
         }
         if (mt > 0) chunk_backward<R, M>(a, c, dd, mt);
