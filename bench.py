@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--mms-tol", type=float, default=1e-6,
                     help="Schwarz stop tolerance of the --paper-mms time study (the paper's 1e-6)")
     ap.add_argument("--mms-kmax", type=int, default=64, help="Schwarz iteration cap of the --paper-mms runs")
+    ap.add_argument("--mms-mass-fix", action="store_true",
+                    help="apply the mass-flux correction (Algorithm step 4) in the --paper-mms runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -201,7 +203,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def _paper_run(nr, nt, np_, tau, tf, delta, chi, tol=1e-6, kmax=64, keep=False):
+def _paper_run(nr, nt, np_, tau, tf, delta, chi, tol=1e-6, kmax=64, keep=False, mass_fix=False):
     """The manufactured solution of the paper's numerical tests (eq. Exact:
     R1=1, R2=2, Ra=Pr=1, the given chi, FP64, additive Schwarz) from its exact
     levels at t=0 and -tau, with its time-dependent wall data and forcing,
@@ -214,6 +216,7 @@ def _paper_run(nr, nt, np_, tau, tf, delta, chi, tol=1e-6, kmax=64, keep=False):
     grid = I.Grid(nr, nt, np_, 1.0, 2.0, delta)
     sh = yy.Shell(nr, nt, np_, 1.0, 2.0, delta)
     sh.set_params(pr=pr, ra=ra, dt=tau, chi=chi, t_inner=0.0, t_outer=0.0)
+    sh.set_mass_fix(1 if mass_fix else 0)
     dev = sh.ws.device
     wf = (I.T, I.U1R, I.U1T, I.U1P)
     walls = {f: torch.as_tensor(I.wall_parts(grid, f, kind), device=dev) for f in wf}
@@ -269,13 +272,14 @@ def paper_mms(args):
     convergence study (tau = 1e-3, Tf = 0.1) on 10x46x96, 20x92x192,
     40x184x384; prints the errors and the observed orders."""
     out = {"workload": "paper_mms_eq_exact_R1_1_R2_2", "tol": args.mms_tol, "kmax": args.mms_kmax,
+           "mass_fix": bool(args.mms_mass_fix),
            "overlap": args.mms_delta,
            "chi": args.mms_chi, "time_tf": args.mms_tf, "time": [], "space": []}
     from paper_1905_02300_amd import yy
 
     def run(*a, keep=False, tol=1e-6):
         try:
-            res = _paper_run(*a, tol=tol, kmax=args.mms_kmax, keep=keep)
+            res = _paper_run(*a, tol=tol, kmax=args.mms_kmax, keep=keep, mass_fix=args.mms_mass_fix)
         except yy.YYError as e:
             res = {"grid": list(a[:3]), "tau": a[3], "overlap": a[5], "error": str(e)}
         print(json.dumps({k: v for k, v in res.items() if not k.startswith("_")}), file=sys.stderr, flush=True)
