@@ -21,39 +21,45 @@ NORM_NAMES = FIELD_NAMES + ["div_u2"]
 _lib = None
 
 
+def load_library(path):
+    """A configured ctypes handle of an oracle library at `path` (the tests
+    also load deliberately altered builds this way)."""
+    L = ctypes.CDLL(path)
+    vp, d, i, dp = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
+    L.yyo_create.restype = vp
+    L.yyo_create.argtypes = [i, i, i, d, d, d]
+    L.yyo_destroy.argtypes = [vp]
+    L.yyo_set_params.argtypes = [vp, d, d, d, d, d, d]
+    L.yyo_set_mode.argtypes = [vp, i]
+    L.yyo_set_mass_fix.argtypes = [vp, i]
+    L.yyo_set_t_bc.argtypes = [vp, i, d, d]
+    L.yyo_field_count.restype = ctypes.c_int64
+    L.yyo_field_count.argtypes = [vp, i, i]
+    L.yyo_set_field.argtypes = [vp, i, i, i, dp]
+    L.yyo_get_field.argtypes = [vp, i, i, i, dp]
+    L.yyo_set_forcing.argtypes = [vp, i, dp]
+    L.yyo_set_wall.argtypes = [vp, i, i, i, dp]
+    L.yyo_step.argtypes = [vp, i]
+    L.yyo_step_tol.argtypes = [vp, i, d]
+    L.yyo_get_norms.argtypes = [vp, dp, i]
+    L.yyo_fill.argtypes = [vp, i]
+    L.yyo_sweep.argtypes = [vp, i, i, dp, dp]
+    L.yyo_apply_op.argtypes = [vp, i, i, dp, dp]
+    L.yyo_sweep_op.argtypes = [vp, i, dp, dp]
+    L.yyo_residual.argtypes = [vp, i, dp]
+    L.yyo_extrapolate.argtypes = [vp]
+    L.yyo_thomas.argtypes = [i, dp, dp, dp, dp, dp]
+    L.yyo_involution.argtypes = [d, d, dp, dp]
+    L.yyo_rotation.argtypes = [d, d, dp]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_build.LIB):
             _build.build()
-        L = ctypes.CDLL(_build.LIB)
-        vp, d, i, dp = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
-        L.yyo_create.restype = vp
-        L.yyo_create.argtypes = [i, i, i, d, d, d]
-        L.yyo_destroy.argtypes = [vp]
-        L.yyo_set_params.argtypes = [vp, d, d, d, d, d, d]
-        L.yyo_set_mode.argtypes = [vp, i]
-        L.yyo_set_mass_fix.argtypes = [vp, i]
-        L.yyo_set_t_bc.argtypes = [vp, i, d, d]
-        L.yyo_field_count.restype = ctypes.c_int64
-        L.yyo_field_count.argtypes = [vp, i, i]
-        L.yyo_set_field.argtypes = [vp, i, i, i, dp]
-        L.yyo_get_field.argtypes = [vp, i, i, i, dp]
-        L.yyo_set_forcing.argtypes = [vp, i, dp]
-        L.yyo_set_wall.argtypes = [vp, i, i, i, dp]
-        L.yyo_step.argtypes = [vp, i]
-        L.yyo_step_tol.argtypes = [vp, i, d]
-        L.yyo_get_norms.argtypes = [vp, dp, i]
-        L.yyo_fill.argtypes = [vp, i]
-        L.yyo_sweep.argtypes = [vp, i, i, dp, dp]
-        L.yyo_apply_op.argtypes = [vp, i, i, dp, dp]
-        L.yyo_sweep_op.argtypes = [vp, i, dp, dp]
-        L.yyo_residual.argtypes = [vp, i, dp]
-        L.yyo_extrapolate.argtypes = [vp]
-        L.yyo_thomas.argtypes = [i, dp, dp, dp, dp, dp]
-        L.yyo_involution.argtypes = [d, d, dp, dp]
-        L.yyo_rotation.argtypes = [d, d, dp]
-        _lib = L
+        _lib = load_library(_build.LIB)
     return _lib
 
 
@@ -92,15 +98,16 @@ def omp_threads():
 class Shell:
     """One Yin-Yang shell held by the oracle."""
 
-    def __init__(self, nr, nt, np_, r1=0.5, r2=1.0, delta=0.0):
+    def __init__(self, nr, nt, np_, r1=0.5, r2=1.0, delta=0.0, _lib=None):
         self.nr, self.nt, self.np = nr, nt, np_
-        self.h = lib().yyo_create(nr, nt, np_, r1, r2, delta)
+        self._L = _lib if _lib is not None else lib()
+        self.h = self._L.yyo_create(nr, nt, np_, r1, r2, delta)
         if not self.h:
             raise ValueError("oracle rejected the grid (arguments or donor-window fit)")
 
     def close(self):
         if self.h:
-            lib().yyo_destroy(self.h)
+            self._L.yyo_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -110,11 +117,11 @@ class Shell:
             pass
 
     def set_params(self, pr=1.0, ra=0.0, tau=1e-3, chi=1.0, t_inner=0.0, t_outer=0.0):
-        if lib().yyo_set_params(self.h, pr, ra, tau, chi, t_inner, t_outer) != 0:
+        if self._L.yyo_set_params(self.h, pr, ra, tau, chi, t_inner, t_outer) != 0:
             raise ValueError("bad parameters")
 
     def set_mode(self, mode):
-        if lib().yyo_set_mode(self.h, mode) != 0:
+        if self._L.yyo_set_mode(self.h, mode) != 0:
             raise ValueError("bad mode")
 
     def padded_shape(self):
@@ -129,72 +136,72 @@ class Shell:
 
     def set_field(self, field, level, a, layout=MAC):
         a = _f64(a)
-        if a.size != lib().yyo_field_count(self.h, field, layout):
+        if a.size != self._L.yyo_field_count(self.h, field, layout):
             raise ValueError("size mismatch")
-        lib().yyo_set_field(self.h, field, level, layout, _ptr(a))
+        self._L.yyo_set_field(self.h, field, level, layout, _ptr(a))
 
     def get_field(self, field, level=LEV_N, layout=MAC):
         shape = self.padded_shape() if layout == PADDED else self.mac_shape(field)
         a = np.zeros(shape)
-        lib().yyo_get_field(self.h, field, level, layout, _ptr(a))
+        self._L.yyo_get_field(self.h, field, level, layout, _ptr(a))
         return a
 
     def set_forcing(self, field, a):
         if a is None:
-            lib().yyo_set_forcing(self.h, field, None)
+            self._L.yyo_set_forcing(self.h, field, None)
             return
         a = _f64(a)
         assert a.shape == self.mac_shape(field)
-        lib().yyo_set_forcing(self.h, field, _ptr(a))
+        self._L.yyo_set_forcing(self.h, field, _ptr(a))
 
     def set_t_bc(self, wall, a, b):
         """Robin condition a T + b dT/dn = g on a wall (0: R1, 1: R2)"""
-        if lib().yyo_set_t_bc(self.h, wall, a, b) != 0:
+        if self._L.yyo_set_t_bc(self.h, wall, a, b) != 0:
             raise RuntimeError("set_t_bc failed")
 
     def set_mass_fix(self, on):
-        if lib().yyo_set_mass_fix(self.h, 1 if on else 0) != 0:
+        if self._L.yyo_set_mass_fix(self.h, 1 if on else 0) != 0:
             raise RuntimeError("set_mass_fix failed")
 
     def set_wall(self, field, level, wall, a):
         """Dirichlet wall data (2, nt+2, np+2) of T, u_r, u_theta or u_phi
         for a level and a wall (0: R1, 1: R2); None clears"""
         if a is None:
-            if lib().yyo_set_wall(self.h, field, level, wall, None) != 0:
+            if self._L.yyo_set_wall(self.h, field, level, wall, None) != 0:
                 raise RuntimeError("set_wall failed")
             return
         a = _f64(a)
         assert a.shape == (2, self.nt + 2, self.np + 2)
-        if lib().yyo_set_wall(self.h, field, level, wall, _ptr(a)) != 0:
+        if self._L.yyo_set_wall(self.h, field, level, wall, _ptr(a)) != 0:
             raise RuntimeError("set_wall failed")
 
     def step(self, K):
-        if lib().yyo_step(self.h, K) != 0:
+        if self._L.yyo_step(self.h, K) != 0:
             raise RuntimeError("step failed")
 
     def step_tol(self, kmax, tol):
         """one step, Schwarz iterations until every increment norm < tol
         (at most kmax); returns the iteration count"""
-        k = lib().yyo_step_tol(self.h, kmax, tol)
+        k = self._L.yyo_step_tol(self.h, kmax, tol)
         if k < 1:
             raise RuntimeError("step_tol failed")
         return k
 
     def norms(self, K):
         out = np.zeros(K * 2 * 10)
-        lib().yyo_get_norms(self.h, _ptr(out), out.size)
+        self._L.yyo_get_norms(self.h, _ptr(out), out.size)
         return out.reshape(K, 2, 10)
 
     def fill(self, level):
-        lib().yyo_fill(self.h, level)
+        self._L.yyo_fill(self.h, level)
 
     def extrapolate(self):
-        lib().yyo_extrapolate(self.h)
+        self._L.yyo_extrapolate(self.h)
 
     def sweep(self, field, d, x):
         x = _f64(x)
         y = np.zeros(self.padded_shape())
-        if lib().yyo_sweep(self.h, field, d, _ptr(x), _ptr(y)) != 0:
+        if self._L.yyo_sweep(self.h, field, d, _ptr(x), _ptr(y)) != 0:
             raise ValueError("bad sweep")
         return y
 
@@ -202,17 +209,17 @@ class Shell:
         """(I - tau/2 Pr D_op) y = x along D_op's direction (centre unknowns)"""
         x = _f64(x)
         y = np.zeros(self.padded_shape())
-        if lib().yyo_sweep_op(self.h, op, _ptr(x), _ptr(y)) != 0:
+        if self._L.yyo_sweep_op(self.h, op, _ptr(x), _ptr(y)) != 0:
             raise ValueError("bad sweep_op")
         return y
 
     def apply_op(self, field, op, x):
         x = _f64(x)
         y = np.zeros(self.padded_shape())
-        lib().yyo_apply_op(self.h, field, op, _ptr(x), _ptr(y))
+        self._L.yyo_apply_op(self.h, field, op, _ptr(x), _ptr(y))
         return y
 
     def residual(self, field):
         y = np.zeros(self.padded_shape())
-        lib().yyo_residual(self.h, field, _ptr(y))
+        self._L.yyo_residual(self.h, field, _ptr(y))
         return y
