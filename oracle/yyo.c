@@ -45,6 +45,9 @@ struct yyo {
     double pr, ra, tau, chi, t_in, t_out;
     int mode;
     int mass_fix;                /* Algorithm step 4 on every velocity fill */
+    int nring;                   /* Algorithm step 7: rings of pressure cells taken
+                                    from the other patch (0: off) */
+    double *ptmp;                /* gathered ring pressures (both patches) */
     double t_bc[2][2];           /* T walls: a T + b dT/dn = g, (a, b) per wall */
     int64_t npatch;              /* doubles per patch array */
     double *lev[YYO_NF][NLEV];   /* levels n, n-1, working iterate k */
@@ -285,7 +288,7 @@ void yyo_destroy(yyo *h)
     for (int c = 0; c < 4; c++) free(h->force[c]);
     for (int c = 0; c < 4; c++)
         for (int l = 0; l < NLEV; l++) { free(h->wall[c][l][0]); free(h->wall[c][l][1]); }
-    free(h->res); free(h->wa); free(h->wb);
+    free(h->res); free(h->wa); free(h->wb); free(h->ptmp);
     free(h);
 }
 
@@ -334,6 +337,39 @@ int yyo_set_mass_fix(yyo *h, int on)
     h->mass_fix = on;
     h->filled = 0;
     return 0;
+}
+
+/* Algorithm step 7 (Sec. 4): after each pressure update the pressure of
+ * the outermost nring cells of a patch (cells with j < nring,
+ * j >= nt - nring, k < nring or k >= np - nring, every radial index) is
+ * interpolated from the other patch instead of being updated by the AC
+ * equation.  Reading: in this MAC layout no momentum stencil reads a
+ * pressure ghost, so the exchanged values that reach the pressure gradient
+ * of eqs. r_comp - phi_comp are those of the patch's own outermost cells;
+ * those cells then act as boundary data of the pressure (they leave the AC
+ * update and its increment norm, like ghosts).  Every ring cell must lie
+ * inside the other patch's centre span.  0 turns the exchange off. */
+int yyo_set_pressure_exchange(yyo *h, int nring)
+{
+    if (!h || nring < 0 || 2 * nring >= h->nt || 2 * nring >= h->np) return -1;
+    for (int j = 0; j < h->nt; j++)
+        for (int k = 0; k < h->np; k++) {
+            int ring = j < nring || j >= h->nt - nring || k < nring || k >= h->np - nring;
+            if (ring && !target_ok(h, CC, tc(h, j), pc(h, k))) return -1;
+        }
+    if (nring > 0 && !h->ptmp) {
+        h->ptmp = (double *)calloc(2 * (size_t)h->npatch, sizeof(double));
+        if (!h->ptmp) return -1;
+    }
+    h->nring = nring;
+    return 0;
+}
+
+/* is centre (j, k) one of the exchanged pressure cells? */
+static int in_ring(const yyo *h, int j, int k)
+{
+    int n = h->nring;
+    return n > 0 && (j < n || j >= h->nt - n || k < n || k >= h->np - n);
 }
 
 int64_t yyo_field_count(const yyo *h, int field, int layout)
@@ -1151,12 +1187,14 @@ static void pressure(yyo *h, int s, int p0, int p1, int kk)
             for (int j = 0; j < h->nt; j++)
                 for (int k = 0; k < h->np; k++) {
                     int64_t q = ix(h, p, i, j, k);
-                    double nv = pn[q] - div_avg(h, un, uk, p, i, j, k) / h->chi;
-                    if (s == 2) nv += p1k[q] - p1n[q];
-                    double inc = nv - pk[q];
-                    pk[q] = nv;
                     double w = vol(h, CC, i, j);
-                    sinc += w * inc * inc;
+                    if (!in_ring(h, j, k)) {
+                        double nv = pn[q] - div_avg(h, un, uk, p, i, j, k) / h->chi;
+                        if (s == 2) nv += p1k[q] - p1n[q];
+                        double inc = nv - pk[q];
+                        pk[q] = nv;
+                        sinc += w * inc * inc;
+                    }
                     if (s == 2) {
                         double dv = div_rr(h, uk[0], p, i, j, k) + div_th(h, uk[1], p, i, j, k) +
                                     div_ph(h, uk[2], p, i, j, k);
@@ -1168,6 +1206,31 @@ static void pressure(yyo *h, int s, int p0, int p1, int kk)
             if (s == 2) h->norms[kk][p][9] = sqrt(sdiv);
         }
     }
+}
+
+/* Algorithm step 7: the ring cells of pressure `field` on patches
+ * [p0,p1) take the other patch's pressure, interpolated like every other
+ * boundary value (cubic Lagrange at the same radial index).  All targets
+ * are gathered before any is replaced, so in the additive mode each patch
+ * reads the other's values as its pressure update left them. */
+static void exchange_pressure(yyo *h, int field, int p0, int p1)
+{
+    double *a = h->lev[field][YYO_LEV_K];
+    for (int pass = 0; pass < 2; pass++)
+        for (int p = p0; p < p1; p++)
+            for (int i = 0; i < h->nr; i++)
+                for (int j = 0; j < h->nt; j++)
+                    for (int k = 0; k < h->np; k++) {
+                        if (!in_ring(h, j, k)) continue;
+                        int64_t q = ix(h, p, i, j, k);
+                        if (pass == 0) {
+                            double th2, ph2;
+                            yyo_involution(tc(h, j), pc(h, k), &th2, &ph2);
+                            h->ptmp[q] = interp(h, a, CC, 1 - p, i, th2, ph2);
+                        } else {
+                            a[q] = h->ptmp[q];
+                        }
+                    }
 }
 
 int yyo_extrapolate(yyo *h)
@@ -1196,7 +1259,8 @@ int yyo_residual(yyo *h, int field, double *out)
 }
 
 /* Solve every quantity on patches [p0,p1) in the order of the Algorithm
- * of Sec. 4: T, then u1 (r, theta, phi; Gauss-Seidel), p1, then u2, p2. */
+ * of Sec. 4: T, then u1 (r, theta, phi; Gauss-Seidel), p1 (and its
+ * exchange, step 7, when on), then u2, p2. */
 static void solve_all(yyo *h, int p0, int p1, int kk)
 {
     solve_field(h, YYO_T, p0, p1, kk);
@@ -1204,10 +1268,12 @@ static void solve_all(yyo *h, int p0, int p1, int kk)
     solve_field(h, YYO_U1T, p0, p1, kk);
     solve_field(h, YYO_U1P, p0, p1, kk);
     pressure(h, 1, p0, p1, kk);
+    if (h->nring > 0) exchange_pressure(h, YYO_P1, p0, p1);
     solve_field(h, YYO_U2R, p0, p1, kk);
     solve_field(h, YYO_U2T, p0, p1, kk);
     solve_field(h, YYO_U2P, p0, p1, kk);
     pressure(h, 2, p0, p1, kk);
+    if (h->nring > 0) exchange_pressure(h, YYO_P2, p0, p1);
 }
 
 /* One time step n -> n+1 with K Schwarz iterations. */

@@ -50,6 +50,14 @@ int yyo_set_mode(yyo *h, int mode);
  * fill so that each patch's boundary carries no net mass flux (Algorithm
  * step 4, optional in the paper); 0 (default): off */
 int yyo_set_mass_fix(yyo *h, int on);
+/* Algorithm step 7 (pressure exchange): nring > 0 makes the outermost
+ * nring cells of each patch (in theta and phi, every radial index) take,
+ * after every pressure update of p1 and p2, the other patch's pressure
+ * interpolated at their centres, in place of the AC update (they leave
+ * the pressure increment norms).  0 (default) turns it off.  Returns -1
+ * if nring < 0, 2 nring >= nt or np, or a ring cell lies outside the
+ * other patch's centre span. */
+int yyo_set_pressure_exchange(yyo *h, int nring);
 /* Robin condition a T + b dT/dn = g on a wall (0: R1, 1: R2; n the outward
  * normal), a, b >= 0, a + b > 0; g = the wall data of T or the constant
  * wall temperature.  Default (1, 0): Dirichlet. */

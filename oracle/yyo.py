@@ -32,6 +32,7 @@ def load_library(path):
     L.yyo_set_params.argtypes = [vp, d, d, d, d, d, d]
     L.yyo_set_mode.argtypes = [vp, i]
     L.yyo_set_mass_fix.argtypes = [vp, i]
+    L.yyo_set_pressure_exchange.argtypes = [vp, i]
     L.yyo_set_t_bc.argtypes = [vp, i, d, d]
     L.yyo_field_count.restype = ctypes.c_int64
     L.yyo_field_count.argtypes = [vp, i, i]
@@ -162,6 +163,12 @@ class Shell:
     def set_mass_fix(self, on):
         if self._L.yyo_set_mass_fix(self.h, 1 if on else 0) != 0:
             raise RuntimeError("set_mass_fix failed")
+
+    def set_pressure_exchange(self, nring):
+        """Algorithm step 7: the outermost nring cells take the other
+        patch's pressure (0: off)"""
+        if self._L.yyo_set_pressure_exchange(self.h, int(nring)) != 0:
+            raise ValueError("set_pressure_exchange failed")
 
     def set_wall(self, field, level, wall, a):
         """Dirichlet wall data (2, nt+2, np+2) of T, u_r, u_theta or u_phi
