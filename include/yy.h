@@ -153,6 +153,27 @@ int yy_set_wall(yy_shell *s, int32_t field, int32_t level, int32_t wall, const d
  * (default) turns it off.  Errors: YY_ERR_ARG. */
 int yy_set_mass_fix(yy_shell *s, int32_t on);
 
+/* Algorithm step 7 (Sec. 4: after the pressure update of a patch,
+ * interpolate the pressure near its boundary from the other patch; the
+ * remark after the Algorithm states that the exchanged pressure enters the
+ * pressure gradient of eqs. r_comp - phi_comp and that skipping it slows
+ * the Schwarz iteration).  nring > 0: after every update of p1 and of p2
+ * (both systems), the outermost nring cells of each patch in theta and phi
+ * (cells with j < nring, j >= nt - nring, k < nring or k >= np - nring, at
+ * every radial index) take the other patch's pressure, interpolated at
+ * their centres by the cubic Lagrange rule of the ghost fill, instead of
+ * the AC update; they leave the pressure increment norms (the divergence
+ * norm still covers them).  In the additive mode every target of both
+ * patches is gathered before any is written.  (In this MAC layout no
+ * momentum stencil reads a pressure ghost, so the exchange acts through
+ * the patch's own outermost cells.)  nring = 0 (default) turns it off.
+ * Uploads a table synchronously (null stream).
+ * Errors: YY_ERR_ARG (nring < 0 or > 8, 2 nring >= nt or np),
+ * YY_ERR_GEOMETRY (a ring centre outside the other patch's span of
+ * centres: the one-cell overlap leaves room for one ring, two on coarse
+ * grids), YY_ERR_HIP. */
+int yy_set_pressure_exchange(yy_shell *s, int32_t nring);
+
 /* Wall condition of T on one wall (0: r = R1, 1: r = R2): the Robin form
  * a T + b dT/dn = g (n the outward normal; a, b >= 0, a + b > 0), which
  * the paper states its method can take in place of Dirichlet data

@@ -1,6 +1,7 @@
 // yy_host.cpp -- host side of libyy.so: C-ABI entry points (include/yy.h),
 // metric and overlap-interpolation tables, workspace layout, and the
 // schedule of one time step (Sec. 4 Algorithm, additive Schwarz).
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -27,7 +28,8 @@ struct Layout {
     int64_t ncc, nvt, nvp;   // interpolation targets per class
     // byte offsets
     int64_t off_fields, off_p, off_tab_r, off_tab_d, off_ptab_r, off_ptab_d, off_fill, off_partial,
-        off_norms, off_wall, off_mf, total;
+        off_norms, off_wall, off_mf, off_ring, total;
+    int64_t nring_max;       // ring targets of the pressure exchange at NRING_MAX rings
     int64_t wall_elems;      // doubles of one wall-data slot: 2 (nt+2)(np+2)
     int64_t elem;            // bytes per compute element
     int nR;                  // compute-precision arrays
@@ -97,6 +99,13 @@ Layout make_layout(const yy_grid *g, int prec)
     o += 24 * align_up(L.wall_elems * 8, ALIGN);
     L.off_mf = o;
     o += align_up((int64_t)4 * MF_BLOCKS * 8, ALIGN);
+    // targets of the pressure exchange (Algorithm step 7), up to NRING_MAX rings
+    {
+        const int64_t it = std::max<int64_t>(0, g->nt - 2 * NRING_MAX), ip = std::max<int64_t>(0, g->np - 2 * NRING_MAX);
+        L.nring_max = (int64_t)g->nt * g->np - it * ip;
+    }
+    L.off_ring = o;
+    o += align_up(L.nring_max * (int64_t)sizeof(FillScalar), ALIGN);
     L.total = o;
     return L;
 }
@@ -217,6 +226,27 @@ bool build_fill(const Frame &F, const Dims &d, std::vector<FillScalar> &cc,
         add_vector(vp, thc(d.nt), phf(k), d.nt, k, 1);
     }
     return ok;
+}
+
+// Targets of the pressure exchange (Algorithm step 7): the centres of the
+// outermost nring cells in theta and phi, each interpolated from the other
+// patch's centres.  false if one lies outside the donor span.
+bool build_ring(const Frame &F, const Dims &d, int nring, std::vector<FillScalar> &ring)
+{
+    const Axis tc = centres(F.th0, F.dth, d.nt), pc = centres(F.ph0, F.dph, d.np);
+    ring.clear();
+    for (int j = 0; j < d.nt; j++)
+        for (int k = 0; k < d.np; k++) {
+            if (!(j < nring || j >= d.nt - nring || k < nring || k >= d.np - nring)) continue;
+            double a, b;
+            other_coords(F.th0 + (j + 0.5) * F.dth, F.ph0 + (k + 0.5) * F.dph, a, b);
+            FillScalar e{};
+            int mt = 0, mp = 0;
+            if (!window(a, tc.x0, tc.h, tc.n, mt, e.wt) || !window(b, pc.x0, pc.h, pc.n, mp, e.wp)) return false;
+            e.tj = j; e.tk = k; e.dj = mt + tc.off; e.dk = mp + pc.off;
+            ring.push_back(e);
+        }
+    return true;
 }
 
 double safe_inv(double x) { return x != 0.0 ? 1.0 / x : 0.0; }
@@ -418,6 +448,10 @@ struct yy_shell {
     // derived ghost coefficients
     double t_ab[2][2] = {{1.0, 0.0}, {1.0, 0.0}};
     TRobin tb = {{2.0, 2.0}, {1.0, 1.0}};
+    // Algorithm step 7: rings of pressure cells taken from the other patch
+    int nring = 0;
+    int nptab = 0;
+    FillScalar *ptab = nullptr;
     // Algorithm step 4 on every velocity fill
     bool mass_fix = false;
     double mf_S = 0.0;           // sum of the squared boundary flux weights
@@ -573,7 +607,8 @@ template <typename R> int step_impl(yy_shell *s, int K, double tol, int *k_done,
             {
                 Timed tm(s, PC_PRESS1, st);
                 Ops<R>::pressure(d, geo_of<R>(s), s->gd, S, 1, s->partial + (int64_t)YY_P1 * 2 * NBMAX,
-                                 nullptr, &s->nblocks[YY_P1], st);
+                                 nullptr, &s->nblocks[YY_P1], s->nring, st);
+                if (s->nring > 0) pressure_exchange(d, S.p[0][1], s->ptab, s->nptab, (double *)S.cb, st);
             }
             solve_field<R>(s, d, YY_U2R, st);
             solve_field<R>(s, d, YY_U2T, st);
@@ -581,7 +616,8 @@ template <typename R> int step_impl(yy_shell *s, int K, double tol, int *k_done,
             {
                 Timed tm(s, PC_PRESS2, st);
                 Ops<R>::pressure(d, geo_of<R>(s), s->gd, S, 2, s->partial + (int64_t)YY_P2 * 2 * NBMAX,
-                                 s->partial + (int64_t)9 * 2 * NBMAX, &s->nblocks[YY_P2], st);
+                                 s->partial + (int64_t)9 * 2 * NBMAX, &s->nblocks[YY_P2], s->nring, st);
+                if (s->nring > 0) pressure_exchange(d, S.p[1][1], s->ptab, s->nptab, (double *)S.cb, st);
             }
         }
         s->nblocks[9] = s->nblocks[YY_P2];
@@ -747,6 +783,7 @@ int yy_create(const yy_grid *g, int32_t prec, void *dev_ws, uint64_t ws_bytes, y
             for (int w = 0; w < 2; w++)
                 s->wall[c][l][w] = (double *)(s->ws + L.off_wall + ((c * 3 + l) * 2 + w) * align_up(L.wall_elems * 8, ALIGN));
     s->mfp = (double *)(s->ws + L.off_mf);
+    s->ptab = (FillScalar *)(s->ws + L.off_ring);
     {
         // squared flux weights of the interpolated boundary faces (theta- and
         // phi-boundary), the same for both patches
@@ -879,6 +916,28 @@ int yy_set_mass_fix(yy_shell *s, int32_t on)
     if ((on != 0) != s->mass_fix) s->version++;
     s->mass_fix = on != 0;
     s->need_fill = true;
+    return YY_OK;
+}
+
+int yy_set_pressure_exchange(yy_shell *s, int32_t nring)
+{
+    if (!s || nring < 0 || nring > NRING_MAX || 2 * nring >= s->L.d.nt || 2 * nring >= s->L.d.np)
+        return YY_ERR_ARG;
+    std::vector<FillScalar> ring;
+    if (nring > 0) {
+        if (!build_ring(s->F, s->L.d, nring, ring)) return YY_ERR_GEOMETRY;
+        // gathered values (2 patches x nr x targets doubles) go to the Thomas
+        // scratch array, which no kernel uses between the pressure update and
+        // the next sweep
+        if ((int64_t)ring.size() > s->L.nring_max ||
+            2 * (int64_t)ring.size() * s->L.d.nr * 8 > s->L.field_elems * s->L.elem)
+            return YY_ERR_ARG;
+        if (hipMemcpy(s->ptab, ring.data(), ring.size() * sizeof(FillScalar), hipMemcpyHostToDevice) != hipSuccess)
+            return YY_ERR_HIP;
+    }
+    if (nring != s->nring) s->version++;
+    s->nring = nring;
+    s->nptab = (int)ring.size();
     return YY_OK;
 }
 

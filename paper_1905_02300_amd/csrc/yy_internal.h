@@ -148,6 +148,7 @@ constexpr int MF_BLOCKS = 128;       // partial sums per (system, patch) of the 
 constexpr int NBMAX = 16384;     // partial-sum slots per patch (grid limit of norm launches)
 constexpr int SWEEP_BLOCKS = 1024;   // blocks per patch of a sweep (each loops over its tasks)
 constexpr int NSLOT = 10;        // norm slots
+constexpr int NRING_MAX = 8;     // rings of the pressure exchange
 
 // ---- launchers (yy_kernels.hip) ----
 template <typename R> struct Ops {
@@ -164,8 +165,9 @@ template <typename R> struct Ops {
     static void sweep(const Dims &d, const Geo<R> &g, const Geo<double> &gd, const State<R> &s,
                       int field, int dir, const R *x, R *y, int mode, double *partial,
                       int *nblocks, int diffusion_only, hipStream_t st);
+    // nring > 0: the outermost nring cells are left to the pressure exchange
     static void pressure(const Dims &d, const Geo<R> &g, const Geo<double> &gd, const State<R> &s,
-                         int sys, double *partial_inc, double *partial_div, int *nblocks,
+                         int sys, double *partial_inc, double *partial_div, int *nblocks, int nring,
                          hipStream_t st);
     static void io(const Dims &d, R *internal, const double *ext, double *ext_out, int field_loc,
                    int layout, hipStream_t st);
@@ -178,6 +180,11 @@ template <typename R> struct Ops {
 void io_double(const Dims &d, double *internal, const double *ext, double *ext_out, int field_loc,
                int layout, hipStream_t st);
 void reduce_norms(const double *partial, const int *nblocks_dev, double *out, hipStream_t st);
+// Algorithm step 7: the ring targets tab[0..ntab) of the launched patches
+// (d.p0, d.npatch) take the other patch's interpolated pressure p; tmp
+// holds 2 * ntab * nr doubles
+void pressure_exchange(const Dims &d, double *p, const FillScalar *tab, int ntab, double *tmp,
+                       hipStream_t st);
 void zero_doubles(double *p, int64_t n, hipStream_t st);
 // choose the register-resident partitioned line solver (default) or the
 // per-line Thomas kernel

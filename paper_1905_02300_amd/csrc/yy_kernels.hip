@@ -1517,9 +1517,13 @@ void Ops<R>::residual(const Dims &d, const Geo<R> &g, const State<R> &s, int fie
 // ---------------------------------------------------------------------------
 // Column-marching form: a thread owns one (patch, j, k) column and walks i
 // upwards; the radial face value at i+1 is reused at the next i.
+// With the pressure exchange on (nring > 0), the outermost nring cells in
+// theta and phi take the other patch's pressure instead (Algorithm step 7):
+// they are not updated and leave the increment norm; the divergence norm
+// still covers every cell.
 template <typename R>
 __global__ void __launch_bounds__(256) k_pressure(Dims d, Geo<double> gd, State<R> s, int sys,
-                                                  double *pinc, double *pdiv)
+                                                  double *pinc, double *pdiv, int nring)
 {
     unsigned bx, by;
     xcd_block(bx, by);
@@ -1536,6 +1540,7 @@ __global__ void __launch_bounds__(256) k_pressure(Dims d, Geo<double> gd, State<
         const FV<double> pyn(s.p[y][0]), pyk(s.p[y][1]), p1n(s.p[0][0]), p1k(s.p[0][1]);
         const double dtp = gd.dt_p[j + 1], dtm = gd.dt_m[j + 1], dpc = gd.dp_c[j + 1];
         const double wj = gd.sc[j + 1] * gd.dr * gd.dth * gd.dph;
+        const bool upd = !(j < nring || j >= d.nt - nring || k < nring || k >= d.np - nring);
         uint32_t q = (uint32_t)ix(d, p, 0, j, k);
         double rn0 = (double)rn[q], rk0 = (double)rk[q];
         for (int i = 0; i < d.nr; i++, q += sI) {
@@ -1550,13 +1555,15 @@ __global__ void __launch_bounds__(256) k_pressure(Dims d, Geo<double> gd, State<
                                     dpc * ((double)pk[q + 1] - (double)pk[q]));
             rn0 = rn1;
             rk0 = rk1;
-            double nv = pyn[q] - 0.5 * (dn + dk) * gd.inv_chi;
-            if (sys == 2) nv += p1k[q] - p1n[q];
-            const double inc = nv - pyk[q];
-            st(s.p[y][1], q, nv);
             const double rc = gd.rc[i + 1];
             const double w = rc * rc * wj;
-            ai += w * inc * inc;
+            if (upd) {
+                double nv = pyn[q] - 0.5 * (dn + dk) * gd.inv_chi;
+                if (sys == 2) nv += p1k[q] - p1n[q];
+                const double inc = nv - pyk[q];
+                st(s.p[y][1], q, nv);
+                ai += w * inc * inc;
+            }
             if (sys == 2) ad += w * dk * dk;
         }
     }
@@ -1570,14 +1577,54 @@ __global__ void __launch_bounds__(256) k_pressure(Dims d, Geo<double> gd, State<
 
 template <typename R>
 void Ops<R>::pressure(const Dims &d, const Geo<R> &g, const Geo<double> &gd, const State<R> &s,
-                      int sys, double *pinc, double *pdiv, int *nb, hipStream_t st)
+                      int sys, double *pinc, double *pdiv, int *nb, int nring, hipStream_t st)
 {
     (void)g;
     int64_t b = col_blocks(d.nt, d.np);        // one thread per (j, k) column
     if (b > NBMAX) b = NBMAX;                   // then blocks loop over tiles
     *nb = (int)b;
     hipLaunchKernelGGL(k_pressure<R>, dim3((unsigned)b, d.npatch), dim3(COL_K, COL_J), 0, st, d, gd, s, sys,
-                       pinc, pdiv);
+                       pinc, pdiv, nring);
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm step 7 (Sec. 4): the pressure of a patch's outermost cells is
+// interpolated from the other patch (cubic Lagrange at the same radial
+// index, as every boundary value).  Every target of the launched patches
+// is gathered into tmp first ([patch][i][target]) and written afterwards,
+// so in the additive mode each patch reads the other's values as its
+// pressure update left them (ring cells are donors of the other patch's
+// ring).  Thread = (target, radial index).
+// ---------------------------------------------------------------------------
+__global__ void k_pring_gather(Dims d, const FillScalar *__restrict__ tab, int ntab, const double *a,
+                               double *tmp)
+{
+    const int p = d.p0 + (int)blockIdx.y;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntab * d.nr) return;
+    const int e = t % ntab, i = t / ntab;
+    const FillScalar &f = tab[e];
+    tmp[(int64_t)p * ntab * d.nr + t] = gather16(a, ix(d, 1 - p, i, f.dj, f.dk), d.sJ, f.wt, f.wp);
+}
+
+__global__ void k_pring_scatter(Dims d, const FillScalar *__restrict__ tab, int ntab, double *a,
+                                const double *tmp)
+{
+    const int p = d.p0 + (int)blockIdx.y;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntab * d.nr) return;
+    const int e = t % ntab, i = t / ntab;
+    const FillScalar &f = tab[e];
+    a[ix(d, p, i, f.tj, f.tk)] = tmp[(int64_t)p * ntab * d.nr + t];
+}
+
+void pressure_exchange(const Dims &d, double *p, const FillScalar *tab, int ntab, double *tmp,
+                       hipStream_t st)
+{
+    const int n = ntab * d.nr;
+    const dim3 g((unsigned)((n + 255) / 256), (unsigned)d.npatch);
+    hipLaunchKernelGGL(k_pring_gather, g, dim3(256), 0, st, d, tab, ntab, (const double *)p, tmp);
+    hipLaunchKernelGGL(k_pring_scatter, g, dim3(256), 0, st, d, tab, ntab, p, (const double *)tmp);
 }
 
 // ---------------------------------------------------------------------------

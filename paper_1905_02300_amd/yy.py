@@ -26,7 +26,8 @@ EXPORTS = ["yy_workspace_bytes", "yy_create", "yy_set_params", "yy_set_field", "
            "yy_residual", "yy_profile", "yy_profile_read", "yy_profile_name",
            "yy_ensemble_workspace_bytes", "yy_ensemble_create", "yy_ensemble_shell",
            "yy_ensemble_step", "yy_ensemble_destroy", "yy_autotune", "yy_set_tuning", "yy_step_tol",
-           "yy_set_wall", "yy_set_mass_fix", "yy_set_t_bc"]
+           "yy_set_wall", "yy_set_mass_fix", "yy_set_t_bc",
+           "yy_set_pressure_exchange"]
 NPROF = 17
 
 
@@ -68,6 +69,7 @@ def load():
     L.yy_set_forcing.argtypes = [vp, i32, vp, vp]
     L.yy_set_wall.argtypes = [vp, i32, i32, i32, vp, vp]
     L.yy_set_mass_fix.argtypes = [vp, i32]
+    L.yy_set_pressure_exchange.argtypes = [vp, i32]
     L.yy_set_t_bc.argtypes = [vp, i32, ctypes.c_double, ctypes.c_double]
     L.yy_step.argtypes = [vp, i32, vp]
     L.yy_step_tol.argtypes = [vp, i32, ctypes.c_double, P(i32), vp]
@@ -226,6 +228,11 @@ class Shell:
     def set_mass_fix(self, on):
         """Algorithm step 4 (boundary mass-flux correction) on every velocity fill"""
         _check(load().yy_set_mass_fix(self.h, 1 if on else 0), "yy_set_mass_fix")
+
+    def set_pressure_exchange(self, nring):
+        """Algorithm step 7: the outermost nring cells take the other
+        patch's pressure after every pressure update (0: off)"""
+        _check(load().yy_set_pressure_exchange(self.h, int(nring)), "yy_set_pressure_exchange")
 
     def set_wall(self, field, level, wall, a, stream=None):
         """Dirichlet wall data (2, nt+2, np+2) of T, u_r, u_theta or u_phi

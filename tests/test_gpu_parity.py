@@ -347,6 +347,59 @@ def test_step_parity_paper_mms_walls(oracle_lib, yy, mode, tol):
     assert e.value.status == yy.YY_ERR_STATE
 
 
+@pytest.mark.parametrize("mode,nring,delta,tol", [(0, 1, 0.0, None), (1, 1, 0.0, None), (0, 2, 0.12, None),
+                                                   (1, 3, 0.12, None), (0, 1, 0.0, 2.6e-7)])
+def test_pressure_exchange_parity(oracle_lib, yy, mode, nring, delta, tol):
+    """Algorithm step 7 (the outermost nring cells take the other patch's
+    pressure after every pressure update) on the paper's manufactured
+    solution with its wall data: 12x24x72, tau = 2e-3, 4 steps, fixed K = 3
+    in both Schwarz modes, a wider overlap with more rings, and the
+    tolerance loop (same iteration counts)."""
+    print(f"case: pressure exchange mode {mode} nring {nring} delta {delta} tol {tol}", flush=True)
+    nr, nt, np_, dt, pr, ra = 12, 24, 72, 2e-3, 1.0, 1.0
+    o = oracle_lib.Shell(nr, nt, np_, 1.0, 2.0, delta)
+    g = yy.Shell(nr, nt, np_, 1.0, 2.0, delta)
+    o.set_params(pr=pr, ra=ra, tau=dt, chi=1.0, t_inner=0.0, t_outer=0.0)
+    o.set_mode(mode)
+    g.set_params(pr=pr, ra=ra, dt=dt, chi=1.0, t_inner=0.0, t_outer=0.0, mode=mode)
+    o.set_pressure_exchange(nring)
+    g.set_pressure_exchange(nring)
+    grid = I.Grid(nr, nt, np_, 1.0, 2.0, delta)
+    for lev, t in ((0, 0.0), (1, -dt)):
+        st = I.mms_state(grid, t, kind="paper")
+        for f in range(9):
+            if lev == 1 and f in (I.P1, I.P2):
+                continue
+            o.set_field(f, lev, st[f])
+            g.set_field(f, lev, st[f])
+        _set_paper_walls(o, g, grid, lev, t)
+    for s in range(4):
+        for f in _WALLF:
+            a = I.mms_forcing(grid, (s + 0.5) * dt, f, pr, ra, kind="paper")
+            o.set_forcing(f, a)
+            g.set_forcing(f, a)
+        _set_paper_walls(o, g, grid, 2, (s + 1) * dt)
+        if tol is None:
+            o.step(3)
+            g.step(3)
+        else:
+            ko = o.step_tol(20, tol)
+            kg = g.step_tol(20, tol)
+            mx = o.norms(ko)[:, :, :9].max(axis=(1, 2))
+            assert mx[-1] < 0.9 * tol and (ko == 1 or mx[-2] > 1.1 * tol), mx
+            assert kg == ko, (s, kg, ko)
+    for f in range(9):
+        a = g.get_field(f).cpu().numpy()
+        b = o.get_field(f)
+        assert _rel(a, b) <= TOL, (I.FIELD_NAMES[f], _rel(a, b))
+    kk = 3 if tol is None else ko
+    assert np.allclose(g.norms()[:kk], o.norms(kk), rtol=1e-7, atol=1e-300)
+    # three rings reach past the other patch's centres at the one-cell overlap
+    with pytest.raises(yy.YYError) as e:
+        yy.Shell(nr, nt, np_, 1.0, 2.0).set_pressure_exchange(3)
+    assert e.value.status == yy.YY_ERR_GEOMETRY
+
+
 def test_paper_mms_long_run_parity(oracle_lib, yy):
     """The paper's manufactured solution with chi = 4 over 100 steps of
     tau = 5e-3 (6x24x72, fixed K = 10; the chi = 4 oracle pin shows this run
