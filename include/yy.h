@@ -196,6 +196,23 @@ int yy_set_t_bc(yy_shell *s, int32_t wall, double a, double b);
  * values), YY_ERR_HIP. */
 int yy_step(yy_shell *s, int32_t n_schwarz, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * step of yy_step (same arguments, same result bit for bit), with its
+ * scratch arrays -- the residual/correction buffer, the Thomas scratch
+ * (each at most 32 MiB: 2 (nr+2)(nt+2) x padded row of compute-precision
+ * elements, e.g. grids up to about 2x32x96x288 in FP64), the norm partial
+ * sums and the mass-flux partials -- in one static device array of the
+ * library (about 67 MiB, one copy per GPU the library runs on, held until
+ * the process ends; its address is looked up once per device) instead of
+ * the workspace.  It calls no allocating routine.  The array is shared by
+ * every call on that GPU and cleared at the start of each call (by a
+ * kernel on `stream`): calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller.
+ * Errors: as yy_step; YY_ERR_WORKSPACE if the grid's scratch does not fit
+ * the static array; YY_ERR_HIP if its address cannot be obtained. */
+int yy_step_static(yy_shell *s, int32_t n_schwarz, hipStream_t stream);
+
 /* One time step with the paper's tolerance-driven Schwarz loop (Sec. 5.1:
  * iterate until the l2 norm of the difference of two successive iterates
  * of every computed quantity is below a tolerance).  After each iteration

@@ -15,7 +15,7 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
-SOURCES = ["yy_kernels.hip", "yy_host.cpp"]
+SOURCES = ["yy_kernels.hip", "yy_host.cpp", "yy_static.hip"]
 
 
 def build(verbose=False):

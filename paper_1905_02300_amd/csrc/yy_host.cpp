@@ -972,6 +972,47 @@ int yy_step(yy_shell *s, int32_t K, hipStream_t st)
                                 : step_impl<float>(s, K, -1.0, nullptr, st);
 }
 
+}  // extern "C"
+
+namespace yy {
+// yy_step whose scratch arrays (residual/correction buffer, Thomas scratch,
+// norm partial sums, mass-flux partials) live at `scratch`.  The region in
+// use is cleared first (a kernel, so a captured graph replays it), so each
+// call starts from the same zeroed scratch as a fresh workspace.
+template <typename R> int step_scratch_impl(yy_shell *s, int K, char *scratch, hipStream_t st)
+{
+    State<R> &S = state_of<R>(s);
+    const int64_t fb = align_up(s->L.field_elems * s->L.elem, ALIGN);
+    R *res = S.res, *cb = S.cb;
+    double *partial = s->partial, *mfp = s->mfp;
+    S.res = (R *)scratch;
+    S.cb = (R *)(scratch + fb);
+    s->partial = (double *)(scratch + 2 * fb);
+    s->mfp = (double *)(scratch + 2 * fb + STATIC_PARTIAL_BYTES);
+    zero_doubles((double *)scratch, (2 * fb + STATIC_PARTIAL_BYTES + STATIC_MF_BYTES) / 8, st);
+    const int rc = step_impl<R>(s, K, -1.0, nullptr, st);
+    S.res = res;
+    S.cb = cb;
+    s->partial = partial;
+    s->mfp = mfp;
+    return rc;
+}
+
+int step_with_scratch(yy_shell *s, int K, char *scratch, int64_t cap, hipStream_t st)
+{
+    if (!s || !scratch || K < 1 || K > MAXK) return YY_ERR_ARG;
+    const int64_t fb = align_up(s->L.field_elems * s->L.elem, ALIGN);
+    if (fb > STATIC_FIELD_BYTES || 2 * fb + STATIC_PARTIAL_BYTES + STATIC_MF_BYTES > cap)
+        return YY_ERR_WORKSPACE;
+    if (!s->have_params || walls_stale(s)) return YY_ERR_STATE;
+    if (s->sticky != YY_OK) return s->sticky;
+    return s->L.prec == YY_FP64 ? step_scratch_impl<double>(s, K, scratch, st)
+                                : step_scratch_impl<float>(s, K, scratch, st);
+}
+}  // namespace yy
+
+extern "C" {
+
 int yy_step_tol(yy_shell *s, int32_t kmax, double tol, int32_t *k_done, hipStream_t st)
 {
     if (!s || !k_done || kmax < 1 || kmax > MAXK || !(tol >= 0.0) || !std::isfinite(tol)) return YY_ERR_ARG;

@@ -150,6 +150,14 @@ constexpr int SWEEP_BLOCKS = 1024;   // blocks per patch of a sweep (each loops 
 constexpr int NSLOT = 10;        // norm slots
 constexpr int NRING_MAX = 8;     // rings of the pressure exchange
 
+// Step scratch held in a static device array (yy_step_static): the
+// residual/correction buffer and the Thomas scratch (each at most
+// STATIC_FIELD_BYTES), the norm partial sums and the mass-flux partials.
+constexpr int64_t STATIC_FIELD_BYTES = (int64_t)32 << 20;
+constexpr int64_t STATIC_PARTIAL_BYTES = (int64_t)NSLOT * 2 * NBMAX * 8;
+constexpr int64_t STATIC_MF_BYTES = (int64_t)4 * MF_BLOCKS * 8;
+constexpr int64_t STATIC_SCRATCH_BYTES = 2 * STATIC_FIELD_BYTES + STATIC_PARTIAL_BYTES + STATIC_MF_BYTES;
+
 // ---- launchers (yy_kernels.hip) ----
 template <typename R> struct Ops {
     static void extrap(const Dims &d, const State<R> &s, hipStream_t st);
@@ -193,4 +201,12 @@ void set_partitioned(bool on);
 // at most wmax lanes); false if it does not fit
 bool strided_tile(int n, int M, int wmax, int &W, int &P);
 
+}  // namespace yy
+
+struct yy_shell;
+namespace yy {
+// yy_step with the step's scratch arrays taken from `scratch` (device
+// memory of `cap` bytes, 256-byte aligned) instead of the workspace
+// (yy_host.cpp)
+int step_with_scratch(yy_shell *s, int K, char *scratch, int64_t cap, hipStream_t st);
 }  // namespace yy

@@ -27,7 +27,7 @@ EXPORTS = ["yy_workspace_bytes", "yy_create", "yy_set_params", "yy_set_field", "
            "yy_ensemble_workspace_bytes", "yy_ensemble_create", "yy_ensemble_shell",
            "yy_ensemble_step", "yy_ensemble_destroy", "yy_autotune", "yy_set_tuning", "yy_step_tol",
            "yy_set_wall", "yy_set_mass_fix", "yy_set_t_bc",
-           "yy_set_pressure_exchange"]
+           "yy_set_pressure_exchange", "yy_step_static"]
 NPROF = 17
 
 
@@ -72,6 +72,7 @@ def load():
     L.yy_set_pressure_exchange.argtypes = [vp, i32]
     L.yy_set_t_bc.argtypes = [vp, i32, ctypes.c_double, ctypes.c_double]
     L.yy_step.argtypes = [vp, i32, vp]
+    L.yy_step_static.argtypes = [vp, i32, vp]
     L.yy_step_tol.argtypes = [vp, i32, ctypes.c_double, P(i32), vp]
     L.yy_get_norms.argtypes = [vp, P(ctypes.c_double), i32, vp]
     L.yy_destroy.argtypes = [vp]
@@ -251,6 +252,11 @@ class Shell:
 
     def step(self, K, stream=None):
         _check(load().yy_step(self.h, K, _stream_ptr(stream)), "yy_step")
+        self.K = K
+
+    def step_static(self, K, stream=None):
+        """yy_step with its scratch in the library's static device array"""
+        _check(load().yy_step_static(self.h, K, _stream_ptr(stream)), "yy_step_static")
         self.K = K
 
     def step_tol(self, kmax, tol, stream=None):
