@@ -99,6 +99,10 @@ def main():
     ap.add_argument("--mms-kmax", type=int, default=64, help="Schwarz iteration cap of the --paper-mms runs")
     ap.add_argument("--mms-mass-fix", action="store_true",
                     help="apply the mass-flux correction (Algorithm step 4) in the --paper-mms runs")
+    ap.add_argument("--mms-ring", type=int, default=0,
+                    help="rings of pressure cells exchanged between the patches (Algorithm step 7) "
+                         "in the --paper-mms runs; 0: off")
+    ap.add_argument("--mms-no-space", action="store_true", help="skip the --paper-mms space study")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -203,7 +207,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def _paper_run(nr, nt, np_, tau, tf, delta, chi, tol=1e-6, kmax=64, keep=False, mass_fix=False):
+def _paper_run(nr, nt, np_, tau, tf, delta, chi, tol=1e-6, kmax=64, keep=False, mass_fix=False, nring=0):
     """The manufactured solution of the paper's numerical tests (eq. Exact:
     R1=1, R2=2, Ra=Pr=1, the given chi, FP64, additive Schwarz) from its exact
     levels at t=0 and -tau, with its time-dependent wall data and forcing,
@@ -217,6 +221,7 @@ def _paper_run(nr, nt, np_, tau, tf, delta, chi, tol=1e-6, kmax=64, keep=False, 
     sh = yy.Shell(nr, nt, np_, 1.0, 2.0, delta)
     sh.set_params(pr=pr, ra=ra, dt=tau, chi=chi, t_inner=0.0, t_outer=0.0)
     sh.set_mass_fix(1 if mass_fix else 0)
+    sh.set_pressure_exchange(nring)
     dev = sh.ws.device
     wf = (I.T, I.U1R, I.U1T, I.U1P)
     walls = {f: torch.as_tensor(I.wall_parts(grid, f, kind), device=dev) for f in wf}
@@ -256,7 +261,7 @@ def _paper_run(nr, nt, np_, tau, tf, delta, chi, tol=1e-6, kmax=64, keep=False, 
         # midpoint l2 with the cell-centre volume of the nearest cell
         ec = e[:, :grid.nr, :grid.nt, :grid.np]
         err[name] = {"l2": float(np.sqrt(np.sum(vol * ec * ec))), "max": float(np.abs(e).max())}
-    res = {"grid": [nr, nt, np_], "overlap": delta, "chi": chi, "tau": tau, "steps": nsteps,
+    res = {"grid": [nr, nt, np_], "overlap": delta, "chi": chi, "tau": tau, "steps": nsteps, "rings": nring,
            "iterations": [min(iters), max(iters)],
            "mean_iterations": float(np.mean(iters)), "seconds": el,
            "mcell_steps_s": grid.cells * nsteps / el / 1e6, "errors": err}
@@ -272,14 +277,15 @@ def paper_mms(args):
     convergence study (tau = 1e-3, Tf = 0.1) on 10x46x96, 20x92x192,
     40x184x384; prints the errors and the observed orders."""
     out = {"workload": "paper_mms_eq_exact_R1_1_R2_2", "tol": args.mms_tol, "kmax": args.mms_kmax,
-           "mass_fix": bool(args.mms_mass_fix),
+           "mass_fix": bool(args.mms_mass_fix), "rings": args.mms_ring,
            "overlap": args.mms_delta,
            "chi": args.mms_chi, "time_tf": args.mms_tf, "time": [], "space": []}
     from paper_1905_02300_amd import yy
 
     def run(*a, keep=False, tol=1e-6):
         try:
-            res = _paper_run(*a, tol=tol, kmax=args.mms_kmax, keep=keep, mass_fix=args.mms_mass_fix)
+            res = _paper_run(*a, tol=tol, kmax=args.mms_kmax, keep=keep, mass_fix=args.mms_mass_fix,
+                             nring=args.mms_ring)
         except yy.YYError as e:
             res = {"grid": list(a[:3]), "tau": a[3], "overlap": a[5], "error": str(e)}
         print(json.dumps({k: v for k, v in res.items() if not k.startswith("_")}), file=sys.stderr, flush=True)
@@ -309,7 +315,8 @@ def paper_mms(args):
     for r in out["time"]:
         r.pop("_fields", None)
         r.pop("_vol", None)
-    out["space"] = [run(10 * m, 46 * m, 96 * m, 1e-3, 0.1, args.mms_delta, args.mms_chi) for m in (1, 2, 4)]
+    out["space"] = [] if args.mms_no_space else [run(10 * m, 46 * m, 96 * m, 1e-3, 0.1, args.mms_delta, args.mms_chi)
+                                                 for m in (1, 2, 4)]
     for key in ("time", "space"):
         runs = [r for r in out[key] if "errors" in r]
         if len(runs) < 2:
