@@ -103,6 +103,10 @@ def main():
                     help="rings of pressure cells exchanged between the patches (Algorithm step 7) "
                          "in the --paper-mms runs; 0: off")
     ap.add_argument("--mms-no-space", action="store_true", help="skip the --paper-mms space study")
+    ap.add_argument("--parity-oracle", type=int, default=0,
+                    help="run the first N steps of the workload (--grid, --prec fp64, autotuned tiles) on "
+                         "the GPU and on the oracle and report their difference per field")
+    ap.add_argument("--out", default="", help="also write the --parity-oracle record to this file")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -112,6 +116,9 @@ def main():
         return
     if args.paper_mms:
         paper_mms(args)
+        return
+    if args.parity_oracle:
+        parity_oracle(args)
         return
     if args.ensemble:
         ensemble(args)
@@ -493,6 +500,73 @@ def line_solve_cpu(nr=64, nt=192, np_=576):
         res[name] = {"ms": el * 1e3, "gbs": 2 * 8 * g.cells / el / 1e9}
     o.close()
     return res
+
+
+def parity_oracle(args):
+    """The first N steps of the benchmark's workload on the GPU (FP64, the
+    tiles the autotuner picks, as in the timed run) and on the oracle (all
+    host threads; a progress line per Schwarz iteration), compared field by
+    field: max |gpu - oracle| relative to the oracle's max, and the
+    velocities' rounding floor of the cancelling buoyancy and hydrostatic
+    pressure gradient (16 eps tau Pr Ra max|T| per correction)."""
+    import torch
+    from oracle import yyo
+    from paper_1905_02300_amd import inputs as I
+    from paper_1905_02300_amd import yy
+    nr, nt, np_ = (int(x) for x in args.grid.split(","))
+    pr, ra, dt, K, n = 1.0, 1e5, 2e-4, args.schwarz, args.parity_oracle
+    grid = I.Grid(nr, nt, np_)
+    st = I.convection_state(grid, pr, ra, seed=3)
+    sh = yy.Shell(nr, nt, np_, prec=yy.YY_FP64)
+    sh.set_params(pr=pr, ra=ra, dt=dt, chi=1.0, t_inner=1.0, t_outer=0.0)
+    for f in range(9):
+        sh.set_field(f, 0, st[f])
+        if f not in (I.P1, I.P2):
+            sh.set_field(f, 1, st[f])
+    tiles = sh.autotune()
+    for _ in range(n):
+        sh.step(K)
+    got = {f: sh.get_field(f).cpu().numpy() for f in range(9)}
+    gn = sh.norms()
+    del sh
+    torch.cuda.empty_cache()
+    print(f"gpu: {n} steps done", file=sys.stderr, flush=True)
+    o = yyo.Shell(nr, nt, np_)
+    o.set_verbose(True)
+    o.set_params(pr=pr, ra=ra, tau=dt, chi=1.0, t_inner=1.0, t_outer=0.0)
+    for f in range(9):
+        o.set_field(f, 0, st[f])
+        if f not in (I.P1, I.P2):
+            o.set_field(f, 1, st[f])
+    steps_s = []
+    for s_ in range(n):
+        t0 = time.perf_counter()
+        o.step(K)
+        steps_s.append(time.perf_counter() - t0)
+        print(f"oracle: step {s_ + 1} done in {steps_s[-1]:.1f} s", file=sys.stderr, flush=True)
+    M = pr * ra * float(np.max(np.abs(st[I.T])))
+    floor = 16 * np.finfo(float).eps * dt * M * n * K
+    fields = {}
+    ok = True
+    for f in range(9):
+        b = o.get_field(f)
+        err = float(np.max(np.abs(got[f] - b)))
+        scale = float(np.max(np.abs(b)))
+        lim = 1e-12 * scale + (0.0 if f in (I.T, I.P1, I.P2) else floor)
+        fields[I.FIELD_NAMES[f]] = {"max_abs_diff": err, "max_abs_oracle": scale, "relative": err / scale,
+                                    "bound": lim, "ok": bool(err <= lim)}
+        ok = ok and bool(err <= lim)
+    on = o.norms(K)
+    out = {"workload": f"yinyang_ac_step_2x{nr}x{nt}x{np_}_fp64_K{K}", "steps": n, "Pr": pr, "Ra": ra, "dt": dt,
+           "tiles": tiles, "fields": fields, "velocity_rounding_floor": floor, "all_within_bound": ok,
+           "norms_max_relative_difference": float(np.max(np.abs(gn - on) / np.maximum(np.abs(on), 1e-300))),
+           "oracle_seconds_per_step": steps_s, "oracle_threads": yyo.omp_threads(),
+           "oracle_mcell_steps_s": grid.cells / float(np.mean(steps_s)) / 1e6,
+           "command": "python3 bench.py --parity-oracle %d --grid %s --out %s" % (n, args.grid, args.out)}
+    print(json.dumps(out), flush=True)
+    if args.out:
+        with open(args.out, "w") as fh:
+            json.dump(out, fh, indent=1)
 
 
 def cpu_baseline(grid_s, pr, ra, dt, K):

@@ -26,6 +26,7 @@
  */
 #include "yyo.h"
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -60,6 +61,7 @@ struct yyo {
     double *res, *wa, *wb;
     double norms[MAXK][2][NNORM];
     int nk, filled;
+    int verbose;                 /* progress line per Schwarz iteration */
 };
 
 /* ------------------------------------------------------------------ */
@@ -298,6 +300,14 @@ int yyo_set_params(yyo *h, double pr, double ra, double tau, double chi,
     if (!h || !(tau > 0.0) || !(chi > 0.0) || !(pr > 0.0)) return -1;
     h->pr = pr; h->ra = ra; h->tau = tau; h->chi = chi;
     h->t_in = t_inner; h->t_out = t_outer;
+    return 0;
+}
+
+/* 1: print a line on stderr after every Schwarz iteration (long runs) */
+int yyo_set_verbose(yyo *h, int on)
+{
+    if (!h) return -1;
+    h->verbose = on != 0;
     return 0;
 }
 
@@ -1314,6 +1324,10 @@ static int step_run(yyo *h, int K, double tol)
             }
         }
         done = kk + 1;
+        if (h->verbose) {
+            fprintf(stderr, "oracle: Schwarz iteration %d done\n", kk + 1);
+            fflush(stderr);
+        }
         if (tol >= 0.0 && kk < MAXK && max_increment(h, kk) < tol) break;
     }
     h->nk = done < MAXK ? done : MAXK;

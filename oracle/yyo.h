@@ -44,6 +44,8 @@ void yyo_destroy(yyo *h);
 /* pr, ra, tau (time step), chi (AC parameter), wall temperatures */
 int yyo_set_params(yyo *h, double pr, double ra, double tau, double chi,
                    double t_inner, double t_outer);
+/* 1: print a progress line on stderr after every Schwarz iteration */
+int yyo_set_verbose(yyo *h, int on);
 /* 0 = additive Schwarz (default), 1 = multiplicative (Yin then Yang) */
 int yyo_set_mode(yyo *h, int mode);
 /* 1: correct the interpolated boundary normal velocities of every velocity

@@ -31,6 +31,7 @@ def load_library(path):
     L.yyo_destroy.argtypes = [vp]
     L.yyo_set_params.argtypes = [vp, d, d, d, d, d, d]
     L.yyo_set_mode.argtypes = [vp, i]
+    L.yyo_set_verbose.argtypes = [vp, i]
     L.yyo_set_mass_fix.argtypes = [vp, i]
     L.yyo_set_pressure_exchange.argtypes = [vp, i]
     L.yyo_set_t_bc.argtypes = [vp, i, d, d]
@@ -120,6 +121,9 @@ class Shell:
     def set_params(self, pr=1.0, ra=0.0, tau=1e-3, chi=1.0, t_inner=0.0, t_outer=0.0):
         if self._L.yyo_set_params(self.h, pr, ra, tau, chi, t_inner, t_outer) != 0:
             raise ValueError("bad parameters")
+
+    def set_verbose(self, on):
+        self._L.yyo_set_verbose(self.h, 1 if on else 0)
 
     def set_mode(self, mode):
         if self._L.yyo_set_mode(self.h, mode) != 0:

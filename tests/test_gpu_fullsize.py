@@ -1,9 +1,11 @@
 """GPU checks at the benchmarked sizes, in the launch configuration
 bench.py times (autotuned tiles).
 
-The 64x192x576 line-solve workload is compared element by element with the
-oracle (it finishes in seconds).  At 2x128x384x1152 the oracle cannot run a
-step in test time, so properties that hold at any size are checked: the
+The 64x192x576 line-solve workload and two steps of the benchmark's
+convection workload on 2x64x192x576 (with the benchmark's tile set) are
+compared element by element with the oracle.  At 2x128x384x1152 the oracle
+needs minutes per step (bench.py --parity-oracle covers it), so the tests
+check properties that hold at any size: the
 discrete conductive state is steady, and identical data on the two patches
 stays bitwise identical (the Yin-Yang construction treats both alike).
 """
@@ -55,6 +57,69 @@ def test_line_solve_64x192x576(oracle_lib, yy, prec):
             err = np.max(np.abs(got[m] - ref[m])) / np.max(np.abs(ref[m]))
             print(f"  metric {metric} dir {d}: relative error {err:.2e}", flush=True)
             assert err <= tol
+
+
+# the tiles the autotuner chose for the FP64 step on 2x128x384x1152 in the
+# benchmark's driver run (lane widths shrink to fit where a line is shorter)
+BENCH_TILES = ('{"T.r":"m8w16b","T.t":"m6w32b","T.p":"v4","u_r.r":"m4w32b","u_r.t":"m12w16",'
+               '"u_r.p":"v4","u_t.r":"m8w16b","u_t.t":"t","u_t.p":"v4","u_p.r":"m8w16",'
+               '"u_p.t":"m6w32b","u_p.p":"v4","D.r":"m8w16b","D.t":"m6w16b","D.p":"v4"}')
+
+
+_ORACLE_64 = {}     # the oracle's two steps, shared by both tile sets
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("tiles", ["bench", "auto"])
+def test_convection_steps_64x192x576(oracle_lib, yy, tiles):
+    """The benchmark's workload (convection start: conductive T plus seeded
+    noise, hydrostatic p, Ra = 1e5, tau = 2e-4, K = 3) on 2x64x192x576:
+    two whole steps against the oracle, with the benchmark's tile set and
+    with the tiles the autotuner picks at this size.  Every field within
+    1e-12 relative, the velocities plus the rounding floor of the cancelling
+    buoyancy and hydrostatic pressure gradient (as in the small convection
+    parity case)."""
+    print(f"case: convection 64x192x576 x2 steps, tiles {tiles}", flush=True)
+    nr, nt, np_ = 64, 192, 576
+    pr, ra, dt, K, nsteps = 1.0, 1e5, 2e-4, 3, 2
+    st = I.convection_state(I.Grid(nr, nt, np_), pr, ra, seed=3)
+    g = yy.Shell(nr, nt, np_)
+    g.set_params(pr=pr, ra=ra, dt=dt, chi=1.0, t_inner=1.0, t_outer=0.0)
+    for f in range(9):
+        g.set_field(f, 0, st[f])
+        if f not in (I.P1, I.P2):
+            g.set_field(f, 1, st[f])
+    if tiles == "bench":
+        g.set_tuning(BENCH_TILES)
+    else:
+        g.autotune()
+    for _ in range(nsteps):
+        g.step(K)
+    got = {f: g.get_field(f).cpu().numpy() for f in range(9)}
+    gn = g.norms()
+    del g
+    if "ref" not in _ORACLE_64:
+        o = oracle_lib.Shell(nr, nt, np_)
+        o.set_params(pr=pr, ra=ra, tau=dt, chi=1.0, t_inner=1.0, t_outer=0.0)
+        for f in range(9):
+            o.set_field(f, 0, st[f])
+            if f not in (I.P1, I.P2):
+                o.set_field(f, 1, st[f])
+        for s in range(nsteps):
+            o.step(K)
+            print(f"  oracle step {s + 1} done", flush=True)
+        _ORACLE_64["ref"] = ({f: o.get_field(f) for f in range(9)}, o.norms(K))
+    ref, on = _ORACLE_64["ref"]
+    M = pr * ra * np.max(np.abs(st[I.T]))
+    floor = 16 * np.finfo(float).eps * dt * M * nsteps * K
+    for f in range(9):
+        b = ref[f]
+        err = np.max(np.abs(got[f] - b))
+        scale = np.max(np.abs(b))
+        print(f"  {I.FIELD_NAMES[f]}: max |gpu - oracle| {err:.2e}, relative {err / scale:.2e}", flush=True)
+        lim = 1e-12 * scale + (0.0 if f in (I.T, I.P1, I.P2) else floor)
+        assert err <= lim, (I.FIELD_NAMES[f], err, lim)
+    assert np.allclose(gn, on, rtol=1e-6, atol=0.0)
 
 
 def _discrete_conductive(g):
