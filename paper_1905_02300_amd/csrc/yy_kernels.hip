@@ -76,18 +76,61 @@ template <int L, typename R> __device__ __forceinline__ R c_of(const Geo<R> &g, 
 // grad-div blocks D_cc/(2 chi) in the own direction, advection by the
 // extrapolated u2 (ar, at, ap at the point) with a minus sign.
 // ---------------------------------------------------------------------------
-template <int L, int D, typename R>
-__device__ __forceinline__ Tri<R> coef(const Geo<R> &g, int i, int j, R ar, R at, R ap, R nu)
+// Per-row coefficient tables of L_{L,D} along an r-line (D = 0, index i+1)
+// or a theta-line (D = 1, index j+1), in a fixed order: D = 0: u_r (FR)
+// fr_lo, fr_up, fr_di, else rc_lo, rc_up; D = 1: u_theta (FT) tf_lo, tf_up,
+// ft_lo, ft_up, ft_di, else tc_lo, tc_up.  The strided line solves stage
+// them in LDS (Tab = an LDS row); everyone else reads the tables (GTab).
+template <int L, int D> __host__ __device__ constexpr int ntabs()
+{
+    return D == 0 ? (L == FR ? 3 : 2) : (D == 1 ? (L == FT ? 5 : 2) : 0);
+}
+template <int L, int D, typename R> __device__ __forceinline__ const R *row_table(const Geo<R> &g, int t)
+{
+    if (D == 0) {
+        if (L == FR) return t == 0 ? (const R *)g.fr_lo : (t == 1 ? (const R *)g.fr_up : (const R *)g.fr_di);
+        return t == 0 ? (const R *)g.rc_lo : (const R *)g.rc_up;
+    }
+    if (L == FT)
+        return t == 0 ? (const R *)g.tf_lo : t == 1 ? (const R *)g.tf_up : t == 2 ? (const R *)g.ft_lo
+                                                                          : t == 3 ? (const R *)g.ft_up
+                                                                                   : (const R *)g.ft_di;
+    return t == 0 ? (const R *)g.tc_lo : (const R *)g.tc_up;
+}
+// table t of the row through the Geo tables
+template <int L, int D, typename R> struct GTab {
+    const Geo<R> &g;
+    int idx;
+    __device__ __forceinline__ R operator()(int t) const
+    {
+        if (D == 0) {
+            if (L == FR) return t == 0 ? g.fr_lo[idx] : (t == 1 ? g.fr_up[idx] : g.fr_di[idx]);
+            return t == 0 ? g.rc_lo[idx] : g.rc_up[idx];
+        }
+        if (L == FT)
+            return t == 0 ? g.tf_lo[idx] : t == 1 ? g.tf_up[idx] : t == 2 ? g.ft_lo[idx] : t == 3 ? g.ft_up[idx] : g.ft_di[idx];
+        return t == 0 ? g.tc_lo[idx] : g.tc_up[idx];
+    }
+};
+// table t of the row from LDS (row-major: table t at base[t * ld])
+template <typename R> struct LTab {
+    const R *base;
+    int ld;
+    __device__ __forceinline__ R operator()(int t) const { return base[t * ld]; }
+};
+
+template <int L, int D, typename R, typename TB>
+__device__ __forceinline__ Tri<R> coef_t(const Geo<R> &g, int i, int j, R ar, R at, R ap, R nu, const TB &tb)
 {
     Tri<R> c;
     if (D == 0) {
         if (L == FR) {
             // u_r is always a velocity unknown: nu = Pr, combined on the host
-            c.lo = g.fr_lo[i + 1];
-            c.up = g.fr_up[i + 1];
-            c.di = g.fr_di[i + 1];
+            c.lo = tb(0);
+            c.up = tb(1);
+            c.di = tb(2);
         } else {
-            const R lo = g.rc_lo[i + 1], up = g.rc_up[i + 1];
+            const R lo = tb(0), up = tb(1);
             c.lo = nu * lo;
             c.up = nu * up;
             c.di = -nu * (lo + up);
@@ -98,13 +141,13 @@ __device__ __forceinline__ Tri<R> coef(const Geo<R> &g, int i, int j, R ar, R at
     } else if (D == 1) {
         const R ir = L == FR ? g.ir_f[i + 1] : g.ir_c[i + 1];
         if (L == FT) {
-            const R lo = g.tf_lo[j + 1], up = g.tf_up[j + 1];
+            const R lo = tb(0), up = tb(1);
             const R ir2 = g.ir2_c[i + 1];
-            c.lo = nu * lo + ir2 * g.ft_lo[j + 1];
-            c.up = nu * up + ir2 * g.ft_up[j + 1];
-            c.di = -nu * (lo + up) + ir2 * g.ft_di[j + 1] - ar * ir;
+            c.lo = nu * lo + ir2 * tb(2);
+            c.up = nu * up + ir2 * tb(3);
+            c.di = -nu * (lo + up) + ir2 * tb(4) - ar * ir;
         } else {
-            const R lo = g.tc_lo[j + 1], up = g.tc_up[j + 1];
+            const R lo = tb(0), up = tb(1);
             c.lo = nu * lo;
             c.up = nu * up;
             c.di = -nu * (lo + up);
@@ -129,6 +172,12 @@ __device__ __forceinline__ Tri<R> coef(const Geo<R> &g, int i, int j, R ar, R at
         c.up -= a;
     }
     return c;
+}
+
+template <int L, int D, typename R>
+__device__ __forceinline__ Tri<R> coef(const Geo<R> &g, int i, int j, R ar, R at, R ap, R nu)
+{
+    return coef_t<L, D>(g, i, j, ar, at, ap, nu, GTab<L, D, R>{g, D == 0 ? i + 1 : j + 1});
 }
 
 // Coefficients of the diffusion-only line solves (DIFF = 1: the paper's
@@ -158,6 +207,71 @@ __device__ __forceinline__ void adv(const State<R> &s, const Dims &d, int64_t q,
     ar = vel<0, L>(s.us[1][0], q, d);
     at = vel<1, L>(s.us[1][1], q, d);
     ap = vel<2, L>(s.us[1][2], q, d);
+}
+
+// The same averages split into a fetch of the raw face values and their
+// combination (same operands, same order: bitwise equal to vel<C, L>), so
+// that a line solve can issue the loads of every row of a chunk before any
+// arithmetic waits on them.  nvel: raw values of component C at location L.
+template <int C, int L> __host__ __device__ constexpr int nvel()
+{
+    return (C == 0 && L == FR) || (C == 1 && L == FT) || (C == 2 && L == FP) ? 1 : (L == CC ? 2 : 4);
+}
+template <int C, int L, typename R>
+__device__ __forceinline__ void vel_fetch(const R *__restrict__ a, int64_t q, const Dims &d, R *v)
+{
+    const int64_t sI = d.sI, sJ = d.sJ;
+    constexpr int N = nvel<C, L>();
+    const int64_t sa = C == 0 ? sI : (C == 1 ? sJ : 1);          // the component's own face step
+    // the other step of a 4-point average (face-centred L in another direction)
+    const int64_t sb = L == FR ? sI : (L == FT ? sJ : 1);
+    if (N == 1) {
+        v[0] = a[q];
+    } else if (N == 2) {
+        v[0] = a[q];
+        v[1] = a[q + sa];
+    } else {
+        v[0] = a[q - sb];
+        v[1] = a[q - sb + sa];
+        v[2] = a[q];
+        v[3] = a[q + sa];
+    }
+}
+template <int C, int L, typename R> __device__ __forceinline__ R vel_combine(const R *v)
+{
+    constexpr int N = nvel<C, L>();
+    if (N == 1) return v[0];
+    if (N == 2) return R(0.5) * (v[0] + v[1]);
+    return R(0.25) * ((v[0] + v[1]) + (v[2] + v[3]));
+}
+
+// Advecting-velocity components the split operator L_{L,D} uses: the one
+// along the line, and u_r (u_theta on theta-faces, D = 1; u_phi on
+// phi-faces, D = 2) and u_theta (u_phi, D = 2) for the metric terms.
+template <int L, int D> struct AdvNeed {
+    static constexpr bool r = D == 0 || (D == 1 && L == FT) || (D == 2 && L == FP);
+    static constexpr bool t = D == 1 || (D == 2 && L == FP);
+    static constexpr bool p = D == 2;
+    static constexpr int N = (r ? nvel<0, L>() : 0) + (t ? nvel<1, L>() : 0) + (p ? nvel<2, L>() : 0);
+};
+template <int L, int D, typename R>
+__device__ __forceinline__ void adv_fetch(const State<R> &s, const Dims &d, int64_t q, R *v)
+{
+    using A = AdvNeed<L, D>;
+    int o = 0;
+    if (A::r) { vel_fetch<0, L>(s.us[1][0], q, d, v + o); o += nvel<0, L>(); }
+    if (A::t) { vel_fetch<1, L>(s.us[1][1], q, d, v + o); o += nvel<1, L>(); }
+    if (A::p) { vel_fetch<2, L>(s.us[1][2], q, d, v + o); }
+}
+template <int L, int D, typename R>
+__device__ __forceinline__ void adv_combine(const R *v, R &ar, R &at, R &ap)
+{
+    using A = AdvNeed<L, D>;
+    int o = 0;
+    ar = at = ap = R(0);
+    if (A::r) { ar = vel_combine<0, L>(v + o); o += nvel<0, L>(); }
+    if (A::t) { at = vel_combine<1, L>(v + o); o += nvel<1, L>(); }
+    if (A::p) { ap = vel_combine<2, L>(v + o); }
 }
 
 template <int L> __host__ __device__ constexpr int ulo(int dir) { return L == dir + 1 ? 1 : 0; }
@@ -851,14 +965,13 @@ __device__ __forceinline__ void reduced_solve(R *lo, R *up, R *rhs, int nrow, in
     }
 }
 
-// one row of the line system (I - tau/2 L) at global row g of n
-template <typename R, int L, int D, int DIFF>
-__device__ __forceinline__ void line_row(const Dims &d, const Geo<R> &g, const State<R> &s, int64_t q,
-                                         int ii, int jj, int gr, int n, R nu, R &lo, R &di, R &up)
+// one row of the line system (I - tau/2 L) at global row g of n, from the
+// advecting velocity at the point
+template <typename R, int L, int D, int DIFF, typename TB>
+__device__ __forceinline__ void line_row_t(const Geo<R> &g, int ii, int jj, int gr, int n, R nu, R ar, R at,
+                                           R ap, const TB &tb, R &lo, R &di, R &up)
 {
-    R ar = R(0), at = R(0), ap = R(0);
-    if (!DIFF) adv<L>(s, d, q, ar, at, ap);
-    const Tri<R> c = true_metric<D, DIFF>(g, ii, jj, coef<L, D>(g, ii, jj, ar, at, ap, nu), nu);
+    const Tri<R> c = true_metric<D, DIFF>(g, ii, jj, coef_t<L, D>(g, ii, jj, ar, at, ap, nu, tb), nu);
     lo = gr > 0 ? -g.ht * c.lo : R(0);
     up = gr < n - 1 ? -g.ht * c.up : R(0);
     di = R(1) - g.ht * c.di;
@@ -869,6 +982,16 @@ __device__ __forceinline__ void line_row(const Dims &d, const Geo<R> &g, const S
         if (gr == 0) di = R(1) - g.ht * (c.di - (t ? g.rho_t[0] : R(1)) * c.lo);
         if (gr == n - 1) di = R(1) - g.ht * (c.di - (t ? g.rho_t[1] : R(1)) * c.up);
     }
+}
+
+template <typename R, int L, int D, int DIFF>
+__device__ __forceinline__ void line_row(const Dims &d, const Geo<R> &g, const State<R> &s, int64_t q,
+                                         int ii, int jj, int gr, int n, R nu, R &lo, R &di, R &up)
+{
+    R ar = R(0), at = R(0), ap = R(0);
+    if (!DIFF) adv<L>(s, d, q, ar, at, ap);
+    line_row_t<R, L, D, DIFF>(g, ii, jj, gr, n, nu, ar, at, ap, GTab<L, D, R>{g, D == 0 ? ii + 1 : jj + 1}, lo,
+                              di, up);
 }
 
 template <int L, int D> __device__ __forceinline__ double vol_at(const Geo<double> &gd, int ii, int jj)
@@ -909,8 +1032,16 @@ __global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<dou
     // chunk rows [r0, r1)
     const int r0 = (int)((int64_t)t * n / P), r1 = (int)((int64_t)(t + 1) * n / P);
     const int mt = r1 - r0;
-    // reduced-system exchange in LDS: four [P][W] arrays
+    // reduced-system exchange in LDS: four [P][W] arrays; then the line's
+    // per-row coefficient tables (ntabs x n, row gr at gr), staged once
     R *sA = sm, *sB = sm + P * W, *sC = sm + 2 * P * W, *sD = sm + 3 * P * W;
+    constexpr int NT = ntabs<L, D>();
+    R *stab = sm + 4 * P * W;
+    for (int e = t * W + lane; e < NT * n; e += W * P) {
+        const int tt = e / n, gr = e % n;
+        stab[e] = row_table<L, D>(g, tt)[m0 + gr + 1];
+    }
+    __syncthreads();
     double acc = 0.0;
     for (int task = (int)bx; task < ntile * nother; task += gridDim.x) {
         const int tile = task % ntile, oth = task / ntile;
@@ -925,16 +1056,31 @@ __global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<dou
         R pv[M];                           // psi of the chunk (BL, last factor)
         if (live) {
             if (BL) {
+                // every raw load of the chunk first (right-hand side, psi,
+                // advecting-velocity face values); the empty asm with a
+                // memory clobber keeps the scheduler from sinking any of
+                // them below the arithmetic, so they are in flight together
+                constexpr int NA = DIFF ? 1 : AdvNeed<L, D>::N;
+                R xv[M], av[M][NA];
+#pragma unroll
+                for (int m = 0; m < M; m++) {
+                    const int mm = m < mt ? m : mt - 1;
+                    const int64_t q = qf + (int64_t)mm * stride;
+                    xv[m] = x[q];
+                    if (MODE == 1) pv[m] = psi[q];
+                    if (!DIFF) adv_fetch<L, D>(s, d, q, av[m]);
+                }
+                asm volatile("" ::: "memory");
 #pragma unroll
                 for (int m = 0; m < M; m++) {
                     const int mm = m < mt ? m : mt - 1;
                     const int gr = r0 + mm;
                     const int ii = D == 0 ? m0 + gr : i, jj = D == 1 ? m0 + gr : j;
-                    const int64_t q = qf + (int64_t)mm * stride;
+                    R ar = R(0), at = R(0), ap = R(0);
+                    if (!DIFF) adv_combine<L, D>(av[m], ar, at, ap);
                     R lo, di, up;
-                    line_row<R, L, D, DIFF>(d, g, s, q, ii, jj, gr, n, nu, lo, di, up);
-                    if (MODE == 1) pv[m] = psi[q];
-                    chunk_forward<R, M>(a, c, dd, m, lo, di, up, x[q]);
+                    line_row_t<R, L, D, DIFF>(g, ii, jj, gr, n, nu, ar, at, ap, LTab<R>{stab + gr, n}, lo, di, up);
+                    chunk_forward<R, M>(a, c, dd, m, lo, di, up, xv[m]);
                     if (m >= mt) { a[m] = R(0); c[m] = R(0); dd[m] = R(0); }
                 }
             } else {
@@ -944,8 +1090,11 @@ __global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<dou
                         const int gr = r0 + m;
                         const int ii = D == 0 ? m0 + gr : i, jj = D == 1 ? m0 + gr : j;
                         const int64_t q = qf + (int64_t)m * stride;
+                        R ar = R(0), at = R(0), ap = R(0);
+                        if (!DIFF) adv<L>(s, d, q, ar, at, ap);
                         R lo, di, up;
-                        line_row<R, L, D, DIFF>(d, g, s, q, ii, jj, gr, n, nu, lo, di, up);
+                        line_row_t<R, L, D, DIFF>(g, ii, jj, gr, n, nu, ar, at, ap, LTab<R>{stab + gr, n}, lo, di,
+                                                  up);
                         chunk_forward<R, M>(a, c, dd, m, lo, di, up, x[q]);
                     }
                 }
@@ -1325,7 +1474,7 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
         int64_t b = tasks;
         if (b > SWEEP_BLOCKS) b = SWEEP_BLOCKS;
         if (nblocks) *nblocks = (int)b;
-        const size_t lds = (size_t)4 * P * W * sizeof(R);
+        const size_t lds = ((size_t)4 * P * W + (size_t)ntabs<L, D>() * n) * sizeof(R);
         const bool bl = s.tune.bl[TL][D] != 0;
 #define YY_ST(MM, BB)                                                                                     \
     hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, MM, BB>), dim3((unsigned)b, d.npatch),      \
