@@ -1333,6 +1333,15 @@ __global__ void __launch_bounds__(512) k_sweep_contig_mw(Dims d, Geo<R> g, Geo<d
     R *sA = tlo, *sB = tdi, *sC = tup, *sD = tlo + ld;
     const R nu = (L == CC && !DIFF) ? R(1) : g.pr;
     const int mt = tid < P ? (tid < P - 1 ? mc : n - (P - 1) * mc) : 0;
+    // a thread stages rows tid + r nthr, r < M (n <= P mc <= nthr M).  PRE:
+    // every raw load of the thread's rows is issued first (x, psi of the
+    // last factor, the advecting-velocity face values), in flight together;
+    // the empty asm keeps the scheduler from sinking them into the
+    // arithmetic.  u_phi's own line needs 9 velocity values a row: there
+    // the registers would cost more occupancy than the prefetch gains, and
+    // each row is loaded as it is staged.
+    constexpr bool PRE = DIFF || AdvNeed<L, 2>::N <= 4;
+    constexpr int NA = (PRE && !DIFF) ? AdvNeed<L, 2>::N : 1;
     double acc = 0.0;
     for (int64_t line = blockIdx.x; line < nlines; line += gridDim.x) {
         const int i = i0 + (int)(line / nj), j = j0 + (int)(line % nj);
@@ -1341,17 +1350,45 @@ __global__ void __launch_bounds__(512) k_sweep_contig_mw(Dims d, Geo<R> g, Geo<d
         // per phi line (the ends drop their outer coupling): only x is staged
         R clo = R(0), cdi = R(0), cup = R(0);
         if (DIFF) line_row<R, L, 2, DIFF>(d, g, s, q0 + 1, i, j, 1, n, nu, clo, cdi, cup);
-        for (int e = tid; e < n; e += nthr) {
-            const int cc = e / mc, rr = e - cc * mc;
-            const int o = rr * ld + cc;
-            if (!DIFF) {
+        R pv[M];
+        if (PRE) {
+            R xv[M], av[M][NA];
+#pragma unroll
+            for (int r = 0; r < M; r++) {
+                const int e = tid + r * nthr, ec = e < n ? e : n - 1;
+                xv[r] = x[q0 + ec];
+                if (MODE == 1) pv[r] = psi[q0 + ec];
+                if (!DIFF) adv_fetch<L, 2>(s, d, q0 + ec, av[r]);
+            }
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int r = 0; r < M; r++) {
+                const int e = tid + r * nthr;
+                if (e < n) {
+                    const int cc = e / mc, rr = e - cc * mc;
+                    const int o = rr * ld + cc;
+                    if (!DIFF) {
+                        R ar, at, ap, lo, di, up;
+                        adv_combine<L, 2>(av[r], ar, at, ap);
+                        line_row_t<R, L, 2, DIFF>(g, i, j, e, n, nu, ar, at, ap, GTab<L, 2, R>{g, 0}, lo, di, up);
+                        tlo[o] = lo;
+                        tdi[o] = di;
+                        tup[o] = up;
+                    }
+                    tx[o] = xv[r];
+                }
+            }
+        } else {
+            for (int e = tid; e < n; e += nthr) {
+                const int cc = e / mc, rr = e - cc * mc;
+                const int o = rr * ld + cc;
                 R lo, di, up;
                 line_row<R, L, 2, DIFF>(d, g, s, q0 + e, i, j, e, n, nu, lo, di, up);
                 tlo[o] = lo;
                 tdi[o] = di;
                 tup[o] = up;
+                tx[o] = x[q0 + e];
             }
-            tx[o] = x[q0 + e];
         }
         __syncthreads();
         R a[M], c[M], dd[M];
@@ -1415,14 +1452,18 @@ __global__ void __launch_bounds__(512) k_sweep_contig_mw(Dims d, Geo<R> g, Geo<d
         }
         __syncthreads();
         const double vol = MODE == 1 ? vol_at<L, 2>(gd, i, j) : 0.0;
-        for (int e = tid; e < n; e += nthr) {
-            const int cc = e / mc, rr = e - cc * mc;
-            const R v = tx[rr * ld + cc];
-            if (MODE == 0) {
-                y[q0 + e] = v;
-            } else {
-                psi[q0 + e] += v;
-                acc += vol * (double)v * (double)v;
+#pragma unroll
+        for (int r = 0; r < M; r++) {
+            const int e = tid + r * nthr;
+            if (e < n) {
+                const int cc = e / mc, rr = e - cc * mc;
+                const R v = tx[rr * ld + cc];
+                if (MODE == 0) {
+                    y[q0 + e] = v;
+                } else {
+                    psi[q0 + e] = (PRE ? pv[r] : psi[q0 + e]) + v;
+                    acc += vol * (double)v * (double)v;
+                }
             }
         }
         __syncthreads();
