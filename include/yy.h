@@ -287,7 +287,10 @@ int yy_residual(yy_shell *s, int32_t field, void *dev_out, hipStream_t stream);
  * the form the step launches it (the last factor of an unknown fused with
  * its update and norm), and those of the diffusion-only line solves
  * (yy_sweep_diffusion, keys "D.r", "D.t", "D.p"), keep the fastest per
- * (unknown or "D", direction), and
+ * (unknown or "D", direction); then the column tile of each residual
+ * (keys "res.T", "res.u_r", "res.u_t", "res.u_p": a 256-thread block of
+ * k x j columns, "64x4", "128x2", "256x1", "32x8" or "16x16", taken by
+ * consecutive blocks k-tile first, "k", or j-tile first, "j"), and
  * write the choices as a JSON object (a NUL-terminated string of at most
  * cap bytes) to json_out if not NULL.
  * Synchronises the stream.  Needs params.  Errors: YY_ERR_ARG,

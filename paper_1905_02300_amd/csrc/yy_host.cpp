@@ -1203,6 +1203,25 @@ static int sweep_as_in_step(yy_shell *s, int field, int dir, hipStream_t st)
 }
 
 // time one sweep configuration: mean of 3 runs after one warm-up (ms)
+// mean time of the residual of `field` (into the scratch buffer), as the step launches it
+extern "C++" template <typename R> static double time_residual_t(yy_shell *s, int field, hipStream_t st, hipEvent_t a, hipEvent_t b)
+{
+    State<R> &S = state_of<R>(s);
+    Ops<R>::residual(s->L.d, geo_of<R>(s), S, field, S.res, st);
+    (void)hipEventRecord(a, st);
+    for (int q = 0; q < 3; q++) Ops<R>::residual(s->L.d, geo_of<R>(s), S, field, S.res, st);
+    (void)hipEventRecord(b, st);
+    if (hipEventSynchronize(b) != hipSuccess) return 1e30;
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    return ms / 3.0;
+}
+static double time_residual(yy_shell *s, int field, hipStream_t st, hipEvent_t a, hipEvent_t b)
+{
+    return s->L.prec == YY_FP64 ? time_residual_t<double>(s, field, st, a, b)
+                                : time_residual_t<float>(s, field, st, a, b);
+}
+
 static double time_sweep(yy_shell *s, int field, int dir, hipStream_t st, hipEvent_t a, hipEvent_t b)
 {
     if (sweep_as_in_step(s, field, dir, st) != YY_OK) return 1e30;
@@ -1283,6 +1302,22 @@ extern "C" int yy_autotune(yy_shell *s, char *json_out, int32_t cap, hipStream_t
             js += "\"";
         }
     }
+    // column tiles of the residuals (one per unknown location)
+    for (int L = 0; L < 4; L++) {
+        int best_t = 0;
+        double best = 1e30;
+        for (int t = 0; t < N_RES_TILES; t++) {
+            T.rt[L] = (int8_t)t;
+            const double tm = time_residual(s, tune_field_id[L], st, a, b);
+            if (tm < best) { best = tm; best_t = t; }
+        }
+        T.rt[L] = (int8_t)best_t;
+        js += ",\"res.";
+        js += tune_field_name[L];
+        js += "\":\"";
+        js += RES_TILES[best_t].name;
+        js += "\"";
+    }
     js += "}";
     s->prof = prof;
     (void)hipEventDestroy(a);
@@ -1336,6 +1371,17 @@ extern "C" int yy_set_tuning(yy_shell *s, const char *json)
                 }
             }
         }
+    for (int L = 0; L < 4; L++) {
+        const std::string key = std::string("\"res.") + tune_field_name[L] + "\":\"";
+        const size_t at = js.find(key);
+        if (at == std::string::npos) continue;
+        const std::string v = js.substr(at + key.size(), js.find('"', at + key.size()) - at - key.size());
+        int found = -1;
+        for (int t = 0; t < N_RES_TILES; t++)
+            if (v == RES_TILES[t].name) found = t;
+        if (found < 0) return YY_ERR_ARG;
+        T.rt[L] = (int8_t)found;
+    }
     s->version++;
     return YY_OK;
 }

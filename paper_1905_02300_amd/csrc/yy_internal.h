@@ -122,7 +122,18 @@ struct FillVector {
 // line and lines per block lpb (1, 2, 4), or wpl (2, 4, 8) waves per line.
 struct Tune {
     int8_t m[5][2], w[5][2], bl[5][2], lpb[5], wpl[5];   // [4]: the diffusion-only line solves
+    int8_t rt[4];            // residual column tile per location (index into RES_TILES)
 };
+
+// Column tiles of the residual kernels: (k extent, j extent) of a
+// 256-thread block and the order in which consecutive blocks take tiles
+// (k-tiles fastest, or j-tiles fastest so that blocks sharing theta-halo
+// rows run together).  Index 0 is the default.
+struct ResTile { int ck, cj, jfast; const char *name; };
+constexpr int N_RES_TILES = 8;
+constexpr ResTile RES_TILES[N_RES_TILES] = {
+    {64, 4, 0, "64x4k"}, {64, 4, 1, "64x4j"}, {128, 2, 1, "128x2j"}, {256, 1, 1, "256x1j"},
+    {128, 2, 0, "128x2k"}, {32, 8, 1, "32x8j"}, {32, 8, 0, "32x8k"}, {16, 16, 0, "16x16k"}};
 
 // pointers of one step (compute precision R; pressures double)
 template <typename R> struct State {

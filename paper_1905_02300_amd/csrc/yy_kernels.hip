@@ -317,6 +317,22 @@ __host__ __device__ inline int64_t col_blocks(int nj, int np)
     return (int64_t)((np + COL_K - 1) / COL_K) * ((nj + COL_J - 1) / COL_J);
 }
 
+// the same for a block of (blockDim.x, blockDim.y) columns, tiles taken
+// k-fastest or (jfast) j-fastest by consecutive logical blocks
+__device__ __forceinline__ bool col_of_t(unsigned bx, int nj, int np, int j0, int k0, int jfast, int &j, int &k)
+{
+    const int ck = (int)blockDim.x, cj = (int)blockDim.y;
+    const unsigned ntk = (unsigned)((np + ck - 1) / ck), ntj = (unsigned)((nj + cj - 1) / cj);
+    const int tk = (int)(jfast ? bx / ntj : bx % ntk), tj = (int)(jfast ? bx % ntj : bx / ntk);
+    k = tk * ck + (int)threadIdx.x;
+    j = j0 + tj * cj + (int)threadIdx.y;
+    return k >= k0 && k < np && (j - j0) < nj;
+}
+inline int64_t col_blocks_t(int nj, int np, const ResTile &t)
+{
+    return (int64_t)((np + t.ck - 1) / t.ck) * ((nj + t.cj - 1) / t.cj);
+}
+
 // ---------------------------------------------------------------------------
 // block reduction of a double (blockDim.x * blockDim.y a multiple of 64,
 // <= 1024, blockDim.x a multiple of 64 or blockDim.y == 1); the sum is
@@ -591,7 +607,8 @@ template <typename R> struct Col {
 };
 
 template <typename R, int L>
-__global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R> s, RhsIn<R> in, R *out)
+__global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R> s, RhsIn<R> in, R *out,
+                                                      int jfast)
 {
     unsigned bx, by;
     xcd_block(bx, by);
@@ -599,7 +616,7 @@ __global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R>
     const int j0 = ulo<L>(1), k0 = ulo<L>(2), i0 = ulo<L>(0);
     const int nj = d.nt - j0;
     int j, k;
-    if (!col_of(bx, nj, d.np, j0, k0, j, k)) return;
+    if (!col_of_t(bx, nj, d.np, j0, k0, jfast, j, k)) return;
     // 32-bit element indices (each field is below 4 GiB: checked on the host)
     const uint32_t sI = (uint32_t)d.sI, sJ = (uint32_t)d.sJ;
     const R nu = L == CC ? R(1) : g.pr;
@@ -1692,11 +1709,15 @@ void Ops<R>::residual(const Dims &d, const Geo<R> &g, const State<R> &s, int fie
     in.p1k = s.p[0][1];
     in.sys = sys;
     const int j0 = L == FT, k0 = L == FP;
-    const dim3 gr((unsigned)col_blocks(d.nt - j0, d.np), d.npatch), bl(COL_K, COL_J);
-    if (L == CC) hipLaunchKernelGGL((k_residual_col<R, CC>), gr, bl, 0, st, d, g, s, in, out);
-    else if (L == FR) hipLaunchKernelGGL((k_residual_col<R, FR>), gr, bl, 0, st, d, g, s, in, out);
-    else if (L == FT) hipLaunchKernelGGL((k_residual_col<R, FT>), gr, bl, 0, st, d, g, s, in, out);
-    else hipLaunchKernelGGL((k_residual_col<R, FP>), gr, bl, 0, st, d, g, s, in, out);
+    int ti = s.tune.rt[L];
+    if (ti < 0 || ti >= N_RES_TILES) ti = 0;
+    const ResTile &t = RES_TILES[ti];
+    const dim3 gr((unsigned)col_blocks_t(d.nt - j0, d.np, t), d.npatch), bl(t.ck, t.cj);
+    const int jf = t.jfast;
+    if (L == CC) hipLaunchKernelGGL((k_residual_col<R, CC>), gr, bl, 0, st, d, g, s, in, out, jf);
+    else if (L == FR) hipLaunchKernelGGL((k_residual_col<R, FR>), gr, bl, 0, st, d, g, s, in, out, jf);
+    else if (L == FT) hipLaunchKernelGGL((k_residual_col<R, FT>), gr, bl, 0, st, d, g, s, in, out, jf);
+    else hipLaunchKernelGGL((k_residual_col<R, FP>), gr, bl, 0, st, d, g, s, in, out, jf);
 }
 
 // ---------------------------------------------------------------------------

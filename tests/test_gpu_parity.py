@@ -210,6 +210,31 @@ def test_residual_parity(oracle_lib, yy, field):
     assert _rel(got[m], ref[m]) <= TOL
 
 
+RES_TILES = ["64x4k", "64x4j", "128x2j", "256x1j", "128x2k", "32x8j", "32x8k", "16x16k"]
+
+
+@pytest.mark.parametrize("tile", RES_TILES)
+def test_residual_parity_every_tile(oracle_lib, yy, tile):
+    """Every column tile the autotuner can give the residuals (shape and
+    tile order) computes the oracle's residual, on a grid (7x40x150) that
+    leaves ragged tiles in both k and j."""
+    print(f"case: residual tile {tile}", flush=True)
+    nr, nt, np_ = 7, 40, 150
+    o, g = _pair(oracle_lib, yy, nr, nt, np_, pr=0.8, ra=50.0, dt=0.02, chi=0.9)
+    g.set_tuning('{"res.T":"%s","res.u_r":"%s","res.u_t":"%s","res.u_p":"%s"}' % ((tile,) * 4))
+    rng = np.random.default_rng(300)
+    _set_random(o, g, rng, [0, 1, 2])
+    o.extrapolate()
+    g.extrapolate()
+    for field in (I.T, I.U1R, I.U2T, I.U2P):
+        ref = 0.02 * o.residual(field)
+        out = g.internal_tensor()
+        g.residual(field, out)
+        got = g.from_internal(out).cpu().numpy()
+        m = _unknown_mask(o.padded_shape(), field)
+        assert _rel(got[m], ref[m]) <= TOL, (tile, I.FIELD_NAMES[field])
+
+
 def _mms_pair(oracle_lib, yy, nr, nt, np_, dt, prec=0, pr=1.0, ra=1e3, mode=0):
     o, g = _pair(oracle_lib, yy, nr, nt, np_, prec=prec, pr=pr, ra=ra, dt=dt, mode=mode)
     grid = I.Grid(nr, nt, np_)
