@@ -324,7 +324,14 @@ yy_shell *yy_ensemble_shell(yy_ensemble *e, int32_t s);
  * all shells, each on its own forked stream, into hipGraphs (one per phase
  * of the time-level rotation) and replays them on later calls.
  * graph = 0 enqueues the shells one after another on the stream instead.
- * Errors: YY_ERR_ARG, YY_ERR_STATE (a shell without params), YY_ERR_HIP. */
+ * A single-shell step (yy_step, yy_step_tol, yy_step_static) on a member
+ * between graph steps is allowed: the graphs are captured again.  Shells
+ * with Dirichlet wall data (yy_set_wall) need new values every step, so
+ * graph = 1 refuses them (YY_ERR_STATE, nothing advanced); graph = 0
+ * steps them.  A failed capture leaves every shell's time levels as they
+ * were.
+ * Errors: YY_ERR_ARG, YY_ERR_STATE (a shell without params, or with wall
+ * data under graph = 1), YY_ERR_HIP. */
 int yy_ensemble_step(yy_ensemble *e, int32_t n_schwarz, int32_t graph, hipStream_t stream);
 
 int yy_ensemble_destroy(yy_ensemble *e);

@@ -968,6 +968,8 @@ int yy_step(yy_shell *s, int32_t K, hipStream_t st)
     if (!s || K < 1 || K > MAXK) return YY_ERR_ARG;
     if (!s->have_params || walls_stale(s)) return YY_ERR_STATE;
     if (s->sticky != YY_OK) return s->sticky;
+    // the level pointers rotate here, outside any captured ensemble graph
+    s->version++;
     return s->L.prec == YY_FP64 ? step_impl<double>(s, K, -1.0, nullptr, st)
                                 : step_impl<float>(s, K, -1.0, nullptr, st);
 }
@@ -1006,6 +1008,7 @@ int step_with_scratch(yy_shell *s, int K, char *scratch, int64_t cap, hipStream_
         return YY_ERR_WORKSPACE;
     if (!s->have_params || walls_stale(s)) return YY_ERR_STATE;
     if (s->sticky != YY_OK) return s->sticky;
+    s->version++;
     return s->L.prec == YY_FP64 ? step_scratch_impl<double>(s, K, scratch, st)
                                 : step_scratch_impl<float>(s, K, scratch, st);
 }
@@ -1019,6 +1022,7 @@ int yy_step_tol(yy_shell *s, int32_t kmax, double tol, int32_t *k_done, hipStrea
     *k_done = 0;
     if (!s->have_params || walls_stale(s)) return YY_ERR_STATE;
     if (s->sticky != YY_OK) return s->sticky;
+    s->version++;
     int k = 0;
     const int r = s->L.prec == YY_FP64 ? step_impl<double>(s, kmax, tol, &k, st)
                                        : step_impl<float>(s, kmax, tol, &k, st);
@@ -1430,11 +1434,57 @@ void drop_graphs(yy_ensemble *e)
     e->captured = false;
 }
 
+// host-side time-level state of a shell that a step rotates
+struct LevelState {
+    State<double> s64;
+    State<float> s32;
+    double *wall[4][3][2];
+    bool wall_on[4][3][2];
+    bool wall_fresh[4][2];
+};
+LevelState save_levels(const yy_shell *s)
+{
+    LevelState v;
+    v.s64 = s->s64;
+    v.s32 = s->s32;
+    std::memcpy(v.wall, s->wall, sizeof v.wall);
+    std::memcpy(v.wall_on, s->wall_on, sizeof v.wall_on);
+    std::memcpy(v.wall_fresh, s->wall_fresh, sizeof v.wall_fresh);
+    return v;
+}
+void restore_levels(yy_shell *s, const LevelState &v)
+{
+    s->s64 = v.s64;
+    s->s32 = v.s32;
+    std::memcpy(s->wall, v.wall, sizeof v.wall);
+    std::memcpy(s->wall_on, v.wall_on, sizeof v.wall_on);
+    std::memcpy(s->wall_fresh, v.wall_fresh, sizeof v.wall_fresh);
+}
+
+// does any level of the shell use Dirichlet wall data?  (Wall data must be
+// set for every step, which a replayed graph cannot do.)
+bool uses_walls(const yy_shell *s)
+{
+    for (int c = 0; c < 4; c++)
+        for (int l = 0; l < 3; l++)
+            for (int w = 0; w < 2; w++)
+                if (s->wall_on[c][l][w]) return true;
+    return false;
+}
+
 // capture the six rotation phases of one ensemble step; every shell's
-// kernels go on its own stream, forked from and joined to the capture stream
+// kernels go on its own stream, forked from and joined to the capture
+// stream.  Capturing runs the host side of six steps: the level pointers
+// come back to where they were (the rotation has period 6), and on any
+// failure they are restored from a snapshot, so no shell's levels move
+// without device work.
 int capture(yy_ensemble *e, int K)
 {
     drop_graphs(e);
+    for (yy_shell *s : e->sh)
+        if (uses_walls(s) || walls_stale(s)) return YY_ERR_STATE;
+    std::vector<LevelState> snap;
+    for (yy_shell *s : e->sh) snap.push_back(save_levels(s));
     std::vector<bool> prof(e->sh.size());
     for (size_t q = 0; q < e->sh.size(); q++) {
         prof[q] = e->sh[q]->prof;
@@ -1461,6 +1511,7 @@ int capture(yy_ensemble *e, int K)
         if (h != hipSuccess && st == YY_OK) st = YY_ERR_HIP;
     }
     for (size_t q = 0; q < e->sh.size(); q++) e->sh[q]->prof = prof[q];
+    for (size_t q = 0; q < e->sh.size(); q++) restore_levels(e->sh[q], snap[q]);
     if (st != YY_OK) {
         drop_graphs(e);
         return st;
@@ -1568,6 +1619,9 @@ int yy_ensemble_step(yy_ensemble *e, int32_t K, int32_t graph, hipStream_t strea
         }
         return YY_OK;
     }
+    // wall data must be set before every step, which a replay cannot do
+    for (yy_shell *s : e->sh)
+        if (uses_walls(s)) return YY_ERR_STATE;
     bool stale = !e->captured || e->K != K;
     for (size_t q = 0; q < e->sh.size() && !stale; q++)
         if (e->sh[q]->version != e->versions[q]) stale = true;

@@ -1,0 +1,150 @@
+"""Ensembles of independent shells (uneven sizes and Rayleigh numbers)
+advanced by the captured graphs: each shell against its own oracle shell,
+the FP32-mixed ensemble against graph-free stepping and against FP64,
+single-shell steps interleaved with graph steps, and the refusal of shells
+with wall data."""
+import numpy as np
+import pytest
+
+from paper_1905_02300_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GRIDS = [(6, 12, 36), (10, 20, 60), (8, 16, 48)]
+RAS = [1e3, 1e4, 1e5]
+DT, K = 2e-4, 3
+
+
+@pytest.fixture(scope="module")
+def yy():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1905_02300_amd import yy as mod
+    mod.load()
+    return mod
+
+
+def _states():
+    return [I.convection_state(I.Grid(*g), 1.0, ra, seed=1000 + q) for q, (g, ra) in enumerate(zip(GRIDS, RAS))]
+
+
+def _load_ensemble(yy, prec, states):
+    e = yy.Ensemble(GRIDS, prec=prec)
+    for q, sh in enumerate(e.shells):
+        sh.set_params(pr=1.0, ra=RAS[q], dt=DT, t_inner=1.0)
+        for f in range(9):
+            sh.set_field(f, 0, states[q][f])
+            if f not in (I.P1, I.P2):
+                sh.set_field(f, 1, states[q][f])
+    return e
+
+
+def test_ensemble_graph_matches_oracle(oracle_lib, yy):
+    """Three FP64 shells stepped by graph replay over more than one cycle
+    of the six level-rotation phases (8 steps), each compared with its own
+    oracle shell: 1e-12 relative, the velocities plus the rounding floor of
+    the cancelling buoyancy and hydrostatic pressure gradient."""
+    print("case: FP64 ensemble graph vs oracle", flush=True)
+    states = _states()
+    e = _load_ensemble(yy, yy.YY_FP64, states)
+    nsteps = 8
+    for _ in range(nsteps):
+        e.step(K, graph=True)
+    for q, (g, ra) in enumerate(zip(GRIDS, RAS)):
+        o = oracle_lib.Shell(*g)
+        o.set_params(pr=1.0, ra=ra, tau=DT, chi=1.0, t_inner=1.0, t_outer=0.0)
+        for f in range(9):
+            o.set_field(f, 0, states[q][f])
+            if f not in (I.P1, I.P2):
+                o.set_field(f, 1, states[q][f])
+        for _ in range(nsteps):
+            o.step(K)
+        floor = 16 * np.finfo(float).eps * DT * ra * np.max(np.abs(states[q][I.T])) * nsteps * K
+        for f in range(9):
+            a = e.shells[q].get_field(f).cpu().numpy()
+            b = o.get_field(f)
+            err = np.max(np.abs(a - b))
+            lim = 1e-12 * np.max(np.abs(b)) + (0.0 if f in (I.T, I.P1, I.P2) else floor)
+            assert err <= lim, (q, I.FIELD_NAMES[f], err, lim)
+
+
+def test_ensemble_fp32_graph_autotuned(yy):
+    """FP32-mixed ensemble with each shell's tiles from the autotuner: the
+    graph replay equals graph-free stepping bitwise, and the result stays
+    within the FP32-mixed error of the FP64 ensemble (T and p at 2e-6
+    relative; the velocity, a small response to 1e-3 temperature noise
+    under a 1e5 hydrostatic balance, at 2e-2 relative)."""
+    print("case: FP32 ensemble graph vs eager vs FP64", flush=True)
+    states = _states()
+    ens = [_load_ensemble(yy, yy.YY_FP32_MIXED, states) for _ in range(2)]
+    js = [sh.autotune() for sh in ens[0].shells]
+    for sh, j in zip(ens[1].shells, js):
+        sh.set_tuning(j)
+    ref = _load_ensemble(yy, yy.YY_FP64, states)
+    for _ in range(8):
+        ens[0].step(K, graph=True)
+        ens[1].step(K, graph=False)
+        ref.step(K, graph=True)
+    for q in range(len(GRIDS)):
+        for f in range(9):
+            a = ens[0].shells[q].get_field(f).cpu().numpy()
+            b = ens[1].shells[q].get_field(f).cpu().numpy()
+            assert np.array_equal(a, b), (q, I.FIELD_NAMES[f])
+            c = ref.shells[q].get_field(f).cpu().numpy()
+            rel = np.max(np.abs(a - c)) / np.max(np.abs(c))
+            lim = 2e-6 if f in (I.T, I.P1, I.P2) else 2e-2
+            print(f"  shell {q} {I.FIELD_NAMES[f]}: FP32-mixed vs FP64 {rel:.2e}")
+            assert rel <= lim, (q, I.FIELD_NAMES[f], rel)
+
+
+def test_ensemble_member_steps_between_graph_steps(yy):
+    """A single-shell step on one member between graph steps (the level
+    pointers then rotate outside the captured graphs): the graphs are
+    captured again, and every shell ends bitwise equal to the same sequence
+    stepped without graphs."""
+    print("case: ensemble with interleaved single-shell steps", flush=True)
+    states = _states()
+    a = _load_ensemble(yy, yy.YY_FP64, states)
+    b = _load_ensemble(yy, yy.YY_FP64, states)
+    for n in range(7):
+        a.step(K, graph=True)
+        b.step(K, graph=False)
+        if n in (1, 4):
+            a.shells[1].step(K)
+            b.shells[1].step(K)
+        if n == 2:
+            a.shells[2].step_tol(5, 1e-30)
+            b.shells[2].step_tol(5, 1e-30)
+    for q in range(len(GRIDS)):
+        for f in range(9):
+            x = a.shells[q].get_field(f).cpu().numpy()
+            y = b.shells[q].get_field(f).cpu().numpy()
+            assert np.array_equal(x, y), (q, I.FIELD_NAMES[f])
+
+
+def test_ensemble_graph_refuses_wall_data(yy):
+    """A shell with wall data cannot be replayed (its wall values change
+    every step): the graph step is refused before anything advances, and
+    graph-free stepping still works."""
+    print("case: ensemble refuses wall data under graph", flush=True)
+    states = _states()
+    a = _load_ensemble(yy, yy.YY_FP64, states)
+    b = _load_ensemble(yy, yy.YY_FP64, states)
+    for e in (a, b):
+        g = I.Grid(*GRIDS[0])
+        w = np.zeros((2, g.nt + 2, g.np + 2))
+        for lev in (0, 1, 2):
+            e.shells[0].set_wall(I.T, lev, 0, w + 1.0)
+    with pytest.raises(yy.YYError) as err:
+        a.step(K, graph=True)
+    assert err.value.status == yy.YY_ERR_STATE
+    for e in (a, b):
+        g = I.Grid(*GRIDS[0])
+        e.shells[0].set_wall(I.T, 2, 0, np.ones((2, g.nt + 2, g.np + 2)))
+        e.step(K, graph=False)
+    for q in range(len(GRIDS)):
+        for f in range(9):
+            x = a.shells[q].get_field(f).cpu().numpy()
+            y = b.shells[q].get_field(f).cpu().numpy()
+            assert np.array_equal(x, y), (q, I.FIELD_NAMES[f])
