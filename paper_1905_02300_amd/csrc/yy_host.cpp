@@ -28,7 +28,7 @@ struct Layout {
     int64_t ncc, nvt, nvp;   // interpolation targets per class
     // byte offsets
     int64_t off_fields, off_p, off_tab_r, off_tab_d, off_ptab_r, off_ptab_d, off_fill, off_partial,
-        off_norms, off_wall, off_mf, off_ring, total;
+        off_norms, off_wall, off_mf, off_ring, off_tref, total;
     int64_t nring_max;       // ring targets of the pressure exchange at NRING_MAX rings
     int64_t wall_elems;      // doubles of one wall-data slot: 2 (nt+2)(np+2)
     int64_t elem;            // bytes per compute element
@@ -106,6 +106,10 @@ Layout make_layout(const yy_grid *g, int prec)
     }
     L.off_ring = o;
     o += align_up(L.nring_max * (int64_t)sizeof(FillScalar), ALIGN);
+    // T's reference profile (FP64) and its radial difference (compute
+    // precision), i = -1..nr
+    L.off_tref = o;
+    o += 2 * align_up(((int64_t)g->nr + 2) * 8, ALIGN);
     L.total = o;
     return L;
 }
@@ -447,7 +451,10 @@ struct yy_shell {
     // T's wall conditions a T + b dT/dn = g, (a, b) per wall, and the
     // derived ghost coefficients
     double t_ab[2][2] = {{1.0, 0.0}, {1.0, 0.0}};
-    TRobin tb = {{2.0, 2.0}, {1.0, 1.0}};
+    TRobin tb = {{2.0, 2.0}, {1.0, 1.0}, {0.0, 0.0}};
+    // FP32-mixed: T is stored as T - Tref, Tref the discrete conductive
+    // profile of the wall temperatures (host copy, i = -1..nr)
+    std::vector<double> tref;
     // Algorithm step 7: rings of pressure cells taken from the other patch
     int nring = 0;
     int nptab = 0;
@@ -687,6 +694,63 @@ template <typename R> void rotate_levels(yy_shell *s)
         }
 }
 
+// shift of T's wall ghost under deviation storage (zero in FP64)
+void update_tshift(yy_shell *s)
+{
+    const int nr = s->L.d.nr;
+    const bool dev = s->L.prec == YY_FP32_MIXED;
+    s->tb.shift[0] = dev ? s->tb.rho[0] * s->tref[1] + s->tref[0] : 0.0;
+    s->tb.shift[1] = dev ? s->tb.rho[1] * s->tref[nr] + s->tref[nr + 1] : 0.0;
+}
+
+// FP32-mixed: the discrete conductive profile of the wall temperatures
+// (D_rr Tref = 0 at every centre with the reflection ghosts of Dirichlet
+// walls: the flux r_f^2 dT is the same through every face), uploaded with
+// its centred radial difference; stored T levels are shifted from the old
+// reference to the new one.  Synchronous.
+int set_reference_profile(yy_shell *s, double t_in, double t_out)
+{
+    if (s->L.prec != YY_FP32_MIXED) return YY_OK;
+    const int nr = s->L.d.nr;
+    const double dr = s->F.dr, r1 = s->F.r1;
+    auto rf = [&](int f) { return r1 + f * dr; };
+    double sum = 0.5 / (rf(0) * rf(0)) + 0.5 / (rf(nr) * rf(nr));
+    for (int f = 1; f < nr; f++) sum += 1.0 / (rf(f) * rf(f));
+    const double F = (t_out - t_in) / sum;
+    std::vector<double> t(nr + 2);
+    t[1] = t_in + 0.5 * F / (rf(0) * rf(0));
+    for (int i = 1; i < nr; i++) t[i + 1] = t[i] + F / (rf(i) * rf(i));
+    t[0] = 2.0 * t_in - t[1];
+    t[nr + 1] = 2.0 * t_out - t[nr];
+    std::vector<float> dtf(nr + 2, 0.0f);
+    for (int i = 0; i < nr; i++) dtf[i + 1] = (float)((t[i + 2] - t[i]) / (2.0 * dr));
+    std::vector<double> diff(nr + 2);
+    bool moved = false;
+    for (int i = 0; i < nr + 2; i++) {
+        diff[i] = s->tref[i] - t[i];
+        moved = moved || diff[i] != 0.0;
+    }
+    double *dev_t = (double *)(s->ws + s->L.off_tref);
+    char *dev_d = s->ws + s->L.off_tref + align_up(((int64_t)nr + 2) * 8, ALIGN);
+    hipError_t e = hipSuccess;
+    if (moved) {
+        // shift the stored deviations: T - old = (T - new) + (new - old)
+        e = hipMemcpy(dev_t, diff.data(), diff.size() * 8, hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+            State<float> &S = s->s32;
+            for (int l = 0; l < 3; l++) Ops<float>::add_profile(s->L.d, S.T[l], dev_t, nullptr);
+            Ops<float>::add_profile(s->L.d, S.Ts, dev_t, nullptr);
+            e = hipDeviceSynchronize();
+        }
+    }
+    if (e == hipSuccess) e = hipMemcpy(dev_t, t.data(), t.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dev_d, dtf.data(), dtf.size() * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return YY_ERR_HIP;
+    s->tref = t;
+    update_tshift(s);
+    return YY_OK;
+}
+
 // wall data in use for a field but not set for the step's iterate
 bool walls_stale(const yy_shell *s)
 {
@@ -785,6 +849,14 @@ int yy_create(const yy_grid *g, int32_t prec, void *dev_ws, uint64_t ws_bytes, y
     s->mfp = (double *)(s->ws + L.off_mf);
     s->ptab = (FillScalar *)(s->ws + L.off_ring);
     {
+        const double *tr = (const double *)(s->ws + L.off_tref);
+        char *dt = s->ws + L.off_tref + align_up(((int64_t)L.d.nr + 2) * 8, ALIGN);
+        s->tref.assign(L.d.nr + 2, 0.0);
+        s->gd.tref = tr; s->gd.dtref = (const double *)dt; s->gd.tdev = 0;
+        s->g64.tref = tr; s->g64.dtref = (const double *)dt; s->g64.tdev = 0;
+        s->g32.tref = tr; s->g32.dtref = (const float *)dt; s->g32.tdev = prec == YY_FP32_MIXED ? 1 : 0;
+    }
+    {
         // squared flux weights of the interpolated boundary faces (theta- and
         // phi-boundary), the same for both patches
         double S = 0.0;
@@ -821,6 +893,8 @@ int yy_set_params(yy_shell *s, const yy_params *p)
         st = upload_param_tables<float>(s->g32, s->F, s->L.d, *p, s->ws + s->L.off_ptab_r);
         if (st != YY_OK) return st;
     }
+    st = set_reference_profile(s, p->t_inner, p->t_outer);
+    if (st != YY_OK) return st;
     s->have_params = true;
     s->need_fill = true;   // wall values may have changed
     s->version++;
@@ -841,9 +915,10 @@ int yy_set_field(yy_shell *s, int32_t field, int32_t level, int32_t layout, cons
         double *dst = s->L.prec == YY_FP64 ? s->s64.p[y][level == 0 ? 0 : 1] : s->s32.p[y][level == 0 ? 0 : 1];
         io_double(s->L.d, dst, src, nullptr, loc, layout, st);
     } else if (s->L.prec == YY_FP64) {
-        Ops<double>::io(s->L.d, field_ptr<double>(s, field, level), src, nullptr, loc, layout, st);
+        Ops<double>::io(s->L.d, field_ptr<double>(s, field, level), src, nullptr, loc, layout, nullptr, st);
     } else {
-        Ops<float>::io(s->L.d, field_ptr<float>(s, field, level), src, nullptr, loc, layout, st);
+        Ops<float>::io(s->L.d, field_ptr<float>(s, field, level), src, nullptr, loc, layout,
+                       field == YY_T ? (const double *)s->g32.tref : nullptr, st);
     }
     s->need_fill = true;
     s->version++;
@@ -862,9 +937,10 @@ int yy_get_field(yy_shell *s, int32_t field, int32_t level, int32_t layout, doub
         double *src = s->L.prec == YY_FP64 ? s->s64.p[y][level == 0 ? 0 : 1] : s->s32.p[y][level == 0 ? 0 : 1];
         io_double(s->L.d, src, nullptr, dst, loc, layout, st);
     } else if (s->L.prec == YY_FP64) {
-        Ops<double>::io(s->L.d, field_ptr<double>(s, field, level), nullptr, dst, loc, layout, st);
+        Ops<double>::io(s->L.d, field_ptr<double>(s, field, level), nullptr, dst, loc, layout, nullptr, st);
     } else {
-        Ops<float>::io(s->L.d, field_ptr<float>(s, field, level), nullptr, dst, loc, layout, st);
+        Ops<float>::io(s->L.d, field_ptr<float>(s, field, level), nullptr, dst, loc, layout,
+                       field == YY_T ? (const double *)s->g32.tref : nullptr, st);
     }
     return hip_status(hipGetLastError());
 }
@@ -884,10 +960,10 @@ int yy_set_forcing(yy_shell *s, int32_t field, const double *src, hipStream_t st
     s->version++;
     if (s->L.prec == YY_FP64) {
         s->s64.force[c] = src ? (double *)s->force_ptr[c] : nullptr;
-        if (src) Ops<double>::io(s->L.d, (double *)s->force_ptr[c], src, nullptr, loc, YY_MAC, st);
+        if (src) Ops<double>::io(s->L.d, (double *)s->force_ptr[c], src, nullptr, loc, YY_MAC, nullptr, st);
     } else {
         s->s32.force[c] = src ? (float *)s->force_ptr[c] : nullptr;
-        if (src) Ops<float>::io(s->L.d, (float *)s->force_ptr[c], src, nullptr, loc, YY_MAC, st);
+        if (src) Ops<float>::io(s->L.d, (float *)s->force_ptr[c], src, nullptr, loc, YY_MAC, nullptr, st);
     }
     return hip_status(hipGetLastError());
 }
@@ -905,6 +981,7 @@ int yy_set_t_bc(yy_shell *s, int32_t wall, double a, double b)
     s->gd.rho_t[wall] = s->tb.rho[wall];
     s->g64.rho_t[wall] = s->tb.rho[wall];
     s->g32.rho_t[wall] = (float)s->tb.rho[wall];
+    update_tshift(s);
     s->need_fill = true;
     s->version++;
     return YY_OK;

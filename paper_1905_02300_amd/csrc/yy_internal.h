@@ -86,12 +86,23 @@ template <typename R> struct Geo {
     CPtr<R> fr_lo, fr_up, fr_di, ft_lo, ft_up, ft_di;
     // T's wall rule of the correction, c_ghost = -rho_t c_in (1: Dirichlet)
     R rho_t[2];
+    // FP32-mixed stores T as its deviation T - Tref from the discrete
+    // conductive profile Tref(r) of the wall temperatures (tdev = 1): Tref
+    // at centres (FP64, index i+1, i = -1..nr) and its centred radial
+    // difference (Tref(i+1) - Tref(i-1)) / (2 dr); FP64 keeps T itself
+    // (tdev = 0, tables zero)
+    int tdev;
+    CPtr<double> tref;
+    CPtr<R> dtref;
 };
 
 // T's Robin walls a T + b dT/dn = g: ghost = cg g - rho T_in (Dirichlet:
 // cg = 2, rho = 1)
 struct TRobin {
     double cg[2], rho[2];
+    // deviation storage of T (FP32-mixed): the ghost of T - Tref is
+    // cg g - shift - rho (T - Tref)_in with shift = rho Tref_in + Tref_ghost
+    double shift[2];
 };
 constexpr int NTAB_R = 14;   // per-r coefficient tables (length nr+3)
 constexpr int NTAB_T = 20;   // per-theta coefficient tables (length nt+3)
@@ -188,8 +199,12 @@ template <typename R> struct Ops {
     static void pressure(const Dims &d, const Geo<R> &g, const Geo<double> &gd, const State<R> &s,
                          int sys, double *partial_inc, double *partial_div, int *nblocks, int nring,
                          hipStream_t st);
+    // prof (or null): a radial profile (index i+1, i = -1..nr) subtracted
+    // on the way in and added on the way out (T's deviation storage)
     static void io(const Dims &d, R *internal, const double *ext, double *ext_out, int field_loc,
-                   int layout, hipStream_t st);
+                   int layout, const double *prof, hipStream_t st);
+    // a[i][j][k] += prof[i+1] over the whole padded array (both patches)
+    static void add_profile(const Dims &d, R *a, const double *prof, hipStream_t st);
     // Algorithm step 4 on a filled velocity level: make each patch's boundary
     // normal data carry no net mass flux (both systems); partial: 4 * MF_BLOCKS
     // doubles of scratch; S = sum of the squared boundary flux weights

@@ -497,7 +497,7 @@ __global__ void k_fill_vector(Dims d, const FillVector *__restrict__ tab, int nt
 // its wall faces.  Both velocity systems take the same data.  Thread =
 // padded (j, k) point of patch blockIdx.y.
 template <typename R>
-__global__ void k_walls(Dims d, State<R> s, int lev, R t_in, R t_out, TRobin tb, WallLev w, int pmask)
+__global__ void k_walls(Dims d, State<R> s, int lev, double t_in, double t_out, TRobin tb, WallLev w, int pmask)
 {
     const int p = blockIdx.y;
     if (!((pmask >> p) & 1)) return;
@@ -510,8 +510,10 @@ __global__ void k_walls(Dims d, State<R> s, int lev, R t_in, R t_out, TRobin tb,
     const int64_t wq = ((int64_t)p * nj + (j + 1)) * nk + (k + 1);
     auto wv = [&](int c, int side, R dflt) { return w.v[c][side] ? (R)w.v[c][side][wq] : dflt; };
     R *T = s.T[lev];
-    T[qm] = (R)tb.cg[0] * wv(0, 0, t_in) - (R)tb.rho[0] * T[q0];
-    T[qp] = (R)tb.cg[1] * wv(0, 1, t_out) - (R)tb.rho[1] * T[q1];
+    // the wall value and the reference profile's part in FP64, rounded once
+    const double g0 = w.v[0][0] ? w.v[0][0][wq] : t_in, g1 = w.v[0][1] ? w.v[0][1][wq] : t_out;
+    T[qm] = (R)(tb.cg[0] * g0 - tb.shift[0]) - (R)tb.rho[0] * T[q0];
+    T[qp] = (R)(tb.cg[1] * g1 - tb.shift[1]) - (R)tb.rho[1] * T[q1];
     const R a0 = wv(2, 0, R(0)), a1 = wv(2, 1, R(0)), b0 = wv(3, 0, R(0)), b1 = wv(3, 1, R(0));
     const R c0 = wv(1, 0, R(0)), c1 = wv(1, 1, R(0));
     for (int y = 0; y < 2; y++) {
@@ -552,8 +554,8 @@ void Ops<R>::fill(const Dims &d, const State<R> &s, int lev, const FillScalar *c
                            (const R *)ut, (const R *)up, up, d.nr, pmask);
     }
     n = (d.np + 2) * (d.nt + 2);
-    hipLaunchKernelGGL(k_walls<R>, dim3((n + 255) / 256, 2), dim3(256), 0, st, d, s, lev, (R)t_in,
-                       (R)t_out, tb, walls, pmask);
+    hipLaunchKernelGGL(k_walls<R>, dim3((n + 255) / 256, 2), dim3(256), 0, st, d, s, lev, t_in, t_out, tb,
+                       walls, pmask);
 }
 
 // ---------------------------------------------------------------------------
@@ -639,7 +641,7 @@ __global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R>
         w.c0 = wp[q - sI]; w.c1 = wp[q - sI + 1];        // w_p at (i-1, k), (i-1, k+1)
         w.e0 = us1[q - sI]; w.e1 = us1[q - sI + sJ];
         w.f0 = us2[q - sI]; w.f1 = us2[q - sI + 1];
-        w.tg = (double)Tn[q - sI] + (double)Tk[q - sI];
+        w.tg = (double)Tn[q - sI] + (double)Tk[q - sI] + 2.0 * g.tref[i0];
         w.pm = ptl(q - sI);
     } else if (L == CC) {
         w.a0 = wr[q];                                    // w_r at face i
@@ -679,7 +681,7 @@ __global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R>
             // -d_r p~ + Pr Ra T^{n+1/2}: the hydrostatic balance cancels
             // two large terms, so they are combined in FP64 before rounding
             const double pt = ptl(q);
-            const double tg = (double)Tn[q] + (double)Tk[q];
+            const double tg = (double)Tn[q] + (double)Tk[q] + 2.0 * g.tref[i + 1];
             S += (R)(g.prra_d * 0.25 * (w.tg + tg) - (pt - w.pm) * (double)g.idr);
             w.a0 = t0; w.a1 = t1; w.c0 = p0; w.c1 = p1;
             w.e0 = e0; w.e1 = e1; w.f0 = f0; w.f1 = f1;
@@ -746,6 +748,9 @@ __global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R>
         const R lp = ps[q + 1] - R(2) * x0 + ps[q - 1];
         Rv += nu * ((g.r12 * ir2 - R(1)) * lt + (ir2 * is2 * g.idph2 - g.cphat) * lp);
         Rv += S;
+        // T's deviation storage: the advection of the reference profile
+        // (its diffusion vanishes: Tref is the discrete conductive state)
+        if (L == CC && g.tdev) Rv -= ar * g.dtref[i + 1];
         Rv -= (pk[q] - pn[q]) * g.inv_tau;
         st(out, q, g.tau * Rv);
         w.bm = w.b0;
@@ -1876,7 +1881,7 @@ void zero_doubles(double *p, int64_t n, hipStream_t st)
 // field I/O: MAC or padded double arrays <-> internal layout
 // ---------------------------------------------------------------------------
 template <typename TT>
-__global__ void k_io(Dims d, TT *in, const double *src, double *dst, int loc, int layout)
+__global__ void k_io(Dims d, TT *in, const double *src, double *dst, int loc, int layout, const double *prof)
 {
     const int fr = loc == FR, ft = loc == FT, fp = loc == FP;
     int n0, n1, n2, o;
@@ -1889,24 +1894,44 @@ __global__ void k_io(Dims d, TT *in, const double *src, double *dst, int loc, in
         const int64_t u = t % per;
         const int k = (int)(u % n2) + o, j = (int)((u / n2) % n1) + o, i = (int)(u / ((int64_t)n2 * n1)) + o;
         const int64_t q = ix(d, p, i, j, k);
-        if (src) in[q] = (TT)src[t];
-        else dst[t] = (double)in[q];
+        const double b = prof ? prof[i + 1] : 0.0;
+        if (src) in[q] = (TT)(src[t] - b);
+        else dst[t] = (double)in[q] + b;
+    }
+}
+
+template <typename TT> __global__ void k_add_profile(Dims d, TT *a, const double *prof)
+{
+    const int nk = d.np + 2, nj = d.nt + 2, ni = d.nr + 2;
+    const int64_t n = 2LL * ni * nj * nk;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)(t % nk) - 1, j = (int)((t / nk) % nj) - 1, i = (int)((t / ((int64_t)nk * nj)) % ni) - 1;
+        const int p = (int)(t / ((int64_t)nk * nj * ni));
+        const int64_t q = ix(d, p, i, j, k);
+        a[q] = (TT)((double)a[q] + prof[i + 1]);
     }
 }
 
 template <typename R>
 void Ops<R>::io(const Dims &d, R *internal, const double *src, double *dst, int loc, int layout,
-                hipStream_t st)
+                const double *prof, hipStream_t st)
 {
     const int64_t n = 2LL * (d.nr + 2) * (d.nt + 2) * (d.np + 2);
-    hipLaunchKernelGGL(k_io<R>, dim3(grid_for(n)), dim3(256), 0, st, d, internal, src, dst, loc, layout);
+    hipLaunchKernelGGL(k_io<R>, dim3(grid_for(n)), dim3(256), 0, st, d, internal, src, dst, loc, layout, prof);
+}
+
+template <typename R> void Ops<R>::add_profile(const Dims &d, R *a, const double *prof, hipStream_t st)
+{
+    const int64_t n = 2LL * (d.nr + 2) * (d.nt + 2) * (d.np + 2);
+    hipLaunchKernelGGL(k_add_profile<R>, dim3(grid_for(n)), dim3(256), 0, st, d, a, prof);
 }
 
 void io_double(const Dims &d, double *internal, const double *src, double *dst, int loc, int layout,
                hipStream_t st)
 {
     const int64_t n = 2LL * (d.nr + 2) * (d.nt + 2) * (d.np + 2);
-    hipLaunchKernelGGL(k_io<double>, dim3(grid_for(n)), dim3(256), 0, st, d, internal, src, dst, loc, layout);
+    hipLaunchKernelGGL(k_io<double>, dim3(grid_for(n)), dim3(256), 0, st, d, internal, src, dst, loc, layout,
+                       (const double *)nullptr);
 }
 
 // ---------------------------------------------------------------------------
