@@ -135,3 +135,50 @@ def test_geometry_rejects_extrapolating_overlap(oracle_lib):
     # every donor window
     with pytest.raises(ValueError):
         oracle_lib.Shell(4, 12, 36, delta=1e-9)
+
+
+def _nominal(th, ph):
+    """inside a patch's nominal region (overlap delta = 0, Sec. 2)"""
+    return (th >= math.pi / 4) & (th <= 3 * math.pi / 4) & (ph >= -3 * math.pi / 4) & (ph <= 3 * math.pi / 4)
+
+
+def test_nominal_patches_cover_the_sphere(oracle_lib):
+    """Every point of S^2 lies in Yin's nominal region or, mapped by the
+    oracle's involution, in Yang's (Sec. 2); the part covered twice has the
+    area 2 (3 pi / 2) sqrt(2) - 4 pi of the two regions' excess over the
+    sphere (each nominal region has area (3 pi / 2)(cos pi/4 - cos 3pi/4))."""
+    rng = np.random.default_rng(7)
+    n = 40000
+    v = rng.standard_normal((n, 3))
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    th = np.arccos(np.clip(v[:, 2], -1, 1))
+    ph = np.arctan2(v[:, 1], v[:, 0])
+    yin = _nominal(th, ph)
+    yang = np.array([_nominal(*oracle_lib.involution(a, b)) for a, b in zip(th, ph)])
+    assert np.all(yin | yang)
+    both = np.mean(yin & yang)
+    expect = (3 * math.sqrt(2) * math.pi - 4 * math.pi) / (4 * math.pi)
+    assert abs(both - expect) < 4 * math.sqrt(expect * (1 - expect) / n), (both, expect)
+
+
+def test_partitioned_area_converges_to_the_sphere(oracle_lib):
+    """Summing both patches' cell areas sin(theta) dtheta dphi with weight 1
+    where a cell centre is in its own nominal region only, 1/2 where it is
+    in both (the oracle's involution decides the other's), gives the
+    sphere's 4 pi; the sharp weights leave an O(h) boundary error, which
+    falls under refinement."""
+    errs = []
+    for m in (1, 2, 4, 8):
+        g = I.Grid(2, 12 * m, 36 * m)
+        _, t, p = g.axes(I.T)
+        TT, PP = np.meshgrid(t, p, indexing="ij")
+        own = _nominal(TT, PP)
+        oth = np.zeros_like(own)
+        for a in range(TT.shape[0]):
+            for b in range(TT.shape[1]):
+                oth[a, b] = _nominal(*oracle_lib.involution(TT[a, b], PP[a, b]))
+        w = np.where(own & oth, 0.5, np.where(own, 1.0, 0.0))
+        area = 2 * np.sum(w * np.sin(TT)) * g.dth * g.dph
+        errs.append(abs(area / (4 * math.pi) - 1))
+        assert errs[-1] < 2.0 * g.dth, (m, errs[-1])
+    assert errs[-1] < errs[0] / 8, errs
