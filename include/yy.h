@@ -182,9 +182,24 @@ int yy_set_pressure_exchange(yy_shell *s, int32_t nring);
  * wall (T_wall their mean, dT/dn their outward difference over dr): the
  * ghost is (g - T_in (a/2 - b/dr)) / (a/2 + b/dr), and the r-line
  * corrections of T take c_ghost = -(a/2 - b/dr)/(a/2 + b/dr) c_in.
- * Default (1, 0): Dirichlet.  The velocity walls stay Dirichlet.
+ * Default (1, 0): Dirichlet.
  * Errors: YY_ERR_ARG. */
 int yy_set_t_bc(yy_shell *s, int32_t wall, double a, double b);
+
+/* Wall condition of the tangential velocity (u_theta and u_phi, both
+ * systems) on one wall of radius R (0: R1, 1: R2): the Robin form
+ * a u + b R dn(u/r) = g (n the outward normal; a, b >= 0, a + b > 0), the
+ * Neumann/Robin class the paper states its method can take (Sec. 1).
+ * (0, 1) with g = 0 is the stress-free wall: with u_r = 0 on the wall the
+ * tangential stress is proportional to R d(u_t/r)/dr.  g is the wall data
+ * of u_theta / u_phi (yy_set_wall) or 0.  Discretised on the cell pair
+ * across the wall (centres r_g outside, r_i inside): u_wall the mean of
+ * the pair, dn(u/r) = (u_g/r_g - u_i/r_i)/dr, so the ghost is
+ * u_g = cg g - rho u_i with cg = 1/(a/2 + b R/(r_g dr)) and
+ * rho = (a/2 - b R/(r_i dr)) cg; the r-line corrections take
+ * c_ghost = -rho c_in.  u_r stays Dirichlet (no penetration).  Default
+ * (1, 0): Dirichlet.  Errors: YY_ERR_ARG. */
+int yy_set_u_bc(yy_shell *s, int32_t wall, double a, double b);
 
 /* Advance one time step n -> n+1 with n_schwarz Schwarz iterations
  * (Sec. 4 Algorithm with the splitting-error reduction eq. er): per

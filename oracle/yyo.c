@@ -50,6 +50,7 @@ struct yyo {
                                     from the other patch (0: off) */
     double *ptmp;                /* gathered ring pressures (both patches) */
     double t_bc[2][2];           /* T walls: a T + b dT/dn = g, (a, b) per wall */
+    double u_bc[2][2];           /* tangential velocity walls: a u + b R dn(u/r) = g */
     int64_t npatch;              /* doubles per patch array */
     double *lev[YYO_NF][NLEV];   /* levels n, n-1, working iterate k */
     double *star[YYO_NF];        /* 1.5 psi^n - 0.5 psi^{n-1} */
@@ -272,6 +273,7 @@ yyo *yyo_create(int nr, int nt, int np, double r1, double r2, double delta)
     }
     for (int c = 0; c < 4; c++) h->force[c] = NULL;
     for (int w = 0; w < 2; w++) { h->t_bc[w][0] = 1.0; h->t_bc[w][1] = 0.0; }
+    for (int w = 0; w < 2; w++) { h->u_bc[w][0] = 1.0; h->u_bc[w][1] = 0.0; }
     for (int c = 0; c < 4; c++)
         for (int l = 0; l < NLEV; l++) h->wall[c][l][0] = h->wall[c][l][1] = NULL;
     h->res = (double *)calloc(1, bytes);
@@ -339,6 +341,53 @@ static double t_rho(const yyo *h, int wall)
 static double t_cg(const yyo *h, int wall)
 {
     return 1.0 / (0.5 * h->t_bc[wall][0] + h->t_bc[wall][1] / h->dr);
+}
+
+int yyo_set_u_bc(yyo *h, int wall, double a, double b)
+{
+    if (!h || wall < 0 || wall > 1 || !(a >= 0.0) || !(b >= 0.0) || !(a + b > 0.0)) return -1;
+    h->u_bc[wall][0] = a;
+    h->u_bc[wall][1] = b;
+    h->filled = 0;
+    return 0;
+}
+
+/* Robin condition of the tangential velocity on a wall of radius R,
+ * a u + b R dn(u / r) = g (n the outward normal; (0, 1) with g = 0 is the
+ * stress-free wall: with u_r = 0 the tangential stress is proportional to
+ * R d(u_t / r)/dr), on the cell pair across the wall: u_wall = (u_ghost +
+ * u_in)/2 and dn(u/r) = (u_ghost / r_ghost - u_in / r_in)/dr, so
+ * u_ghost = cg g - rho u_in with cg = 1/(a/2 + b R/(r_ghost dr)) and
+ * rho = (a/2 - b R/(r_in dr)) cg.  Dirichlet (1, 0): 2 g - u_in. */
+static void u_wall_rule(const yyo *h, int wall, double *cg, double *rho)
+{
+    const double a = h->u_bc[wall][0], b = h->u_bc[wall][1];
+    const double R = wall == 0 ? h->r1 : h->r2;
+    const double rg = wall == 0 ? h->r1 - 0.5 * h->dr : h->r2 + 0.5 * h->dr;
+    const double ri = wall == 0 ? h->r1 + 0.5 * h->dr : h->r2 - 0.5 * h->dr;
+    *cg = 1.0 / (0.5 * a + b * R / (rg * h->dr));
+    *rho = (0.5 * a - b * R / (ri * h->dr)) * *cg;
+}
+static double u_rho(const yyo *h, int wall)
+{
+    double cg, rho;
+    u_wall_rule(h, wall, &cg, &rho);
+    return rho;
+}
+static double u_cg(const yyo *h, int wall)
+{
+    double cg, rho;
+    u_wall_rule(h, wall, &cg, &rho);
+    return cg;
+}
+
+/* correction rule c_ghost = -rho c_in of a field's r-lines at a wall */
+static double wall_rho(const yyo *h, int field, int wall)
+{
+    const int loc = loc_of(field);
+    if (field == YYO_T) return t_rho(h, wall);
+    if (loc == FT || loc == FP) return u_rho(h, wall);
+    return 1.0;
 }
 
 int yyo_set_mass_fix(yyo *h, int on)
@@ -532,8 +581,8 @@ static void wall_rules(const yyo *h, int level, int p)
             for (int q = 0; q < 4; q++) {
                 const int c = (q % 2 == 0) ? 2 : 3;
                 double *a = h->lev[tang[q]][level];
-                a[ix(h, p, -1, j, k)] = 2.0 * wall_value(h, c, level, 0, p, j, k, 0.0) - a[ix(h, p, 0, j, k)];
-                a[ix(h, p, nr, j, k)] = 2.0 * wall_value(h, c, level, 1, p, j, k, 0.0) - a[ix(h, p, nr - 1, j, k)];
+                a[ix(h, p, -1, j, k)] = u_cg(h, 0) * wall_value(h, c, level, 0, p, j, k, 0.0) - u_rho(h, 0) * a[ix(h, p, 0, j, k)];
+                a[ix(h, p, nr, j, k)] = u_cg(h, 1) * wall_value(h, c, level, 1, p, j, k, 0.0) - u_rho(h, 1) * a[ix(h, p, nr - 1, j, k)];
             }
             const double w0 = wall_value(h, 1, level, 0, p, j, k, 0.0), w1 = wall_value(h, 1, level, 1, p, j, k, 0.0);
             h->lev[YYO_U1R][level][ix(h, p, 0, j, k)] = w0;
@@ -992,8 +1041,9 @@ static void sweep_range(yyo *h, int field, int d, const double *x, double *y, in
     int a0 = ulo(loc, d1), a1 = uhi(h, loc, d1), b0 = ulo(loc, d2), b1 = uhi(h, loc, d2);
     int reflect = (d == 0 && !is_face(loc, 0));
     /* homogeneous wall rule of the correction: c_ghost = -rho c_in (rho = 1
-     * for Dirichlet data, T's Robin rule otherwise) */
-    const double rho0 = field == YYO_T ? t_rho(h, 0) : 1.0, rho1 = field == YYO_T ? t_rho(h, 1) : 1.0;
+     * for Dirichlet data, the Robin rules of T and the tangential
+     * velocity otherwise) */
+    const double rho0 = wall_rho(h, field, 0), rho1 = wall_rho(h, field, 1);
     double ht = 0.5 * h->tau;
     for (int p = p0; p < p1; p++) {
 #pragma omp parallel for collapse(2) schedule(static)
@@ -1103,7 +1153,7 @@ int yyo_apply_op(yyo *h, int field, int op, const double *x, double *y)
                     int idx[3] = { i, j, k };
                     int lo_i = ulo(loc, d), hi_i = uhi(h, loc, d), m = idx[d];
                     int reflect = (d == 0 && !is_face(loc, 0));
-                    const double rho0 = field == YYO_T ? t_rho(h, 0) : 1.0, rho1 = field == YYO_T ? t_rho(h, 1) : 1.0;
+                    const double rho0 = wall_rho(h, field, 0), rho1 = wall_rho(h, field, 1);
                     double xm, xp, x0 = x[ix(h, p, i, j, k)];
                     int im[3] = { i, j, k }, ip[3] = { i, j, k };
                     im[d]--; ip[d]++;

@@ -64,6 +64,12 @@ int yyo_set_pressure_exchange(yyo *h, int nring);
  * normal), a, b >= 0, a + b > 0; g = the wall data of T or the constant
  * wall temperature.  Default (1, 0): Dirichlet. */
 int yyo_set_t_bc(yyo *h, int wall, double a, double b);
+/* Robin condition a u + b R dn(u/r) = g of the tangential velocity (both
+ * components, both systems) on a wall of radius R (0: R1, 1: R2; n the
+ * outward normal), a, b >= 0, a + b > 0; g = the wall data of u_theta /
+ * u_phi or 0.  (0, 1): stress-free.  Default (1, 0): Dirichlet.  u_r stays
+ * Dirichlet (no penetration). */
+int yyo_set_u_bc(yyo *h, int wall, double a, double b);
 int64_t yyo_field_count(const yyo *h, int field, int layout);
 int yyo_set_field(yyo *h, int field, int level, int layout, const double *src);
 int yyo_get_field(const yyo *h, int field, int level, int layout, double *dst);

@@ -35,6 +35,7 @@ def load_library(path):
     L.yyo_set_mass_fix.argtypes = [vp, i]
     L.yyo_set_pressure_exchange.argtypes = [vp, i]
     L.yyo_set_t_bc.argtypes = [vp, i, d, d]
+    L.yyo_set_u_bc.argtypes = [vp, i, d, d]
     L.yyo_field_count.restype = ctypes.c_int64
     L.yyo_field_count.argtypes = [vp, i, i]
     L.yyo_set_field.argtypes = [vp, i, i, i, dp]
@@ -163,6 +164,12 @@ class Shell:
         """Robin condition a T + b dT/dn = g on a wall (0: R1, 1: R2)"""
         if self._L.yyo_set_t_bc(self.h, wall, a, b) != 0:
             raise RuntimeError("set_t_bc failed")
+
+    def set_u_bc(self, wall, a, b):
+        """Robin condition a u + b R dn(u/r) = g of the tangential velocity
+        on a wall (0: R1, 1: R2); (0, 1) is stress-free"""
+        if self._L.yyo_set_u_bc(self.h, wall, a, b) != 0:
+            raise RuntimeError("set_u_bc failed")
 
     def set_mass_fix(self, on):
         if self._L.yyo_set_mass_fix(self.h, 1 if on else 0) != 0:

@@ -365,6 +365,7 @@ template <typename R> void bind_geo(Geo<R> &g, const R *base, const Dims &d, con
     const double th1 = M_PI / 4.0 - F.delta;
     g.cphat = (R)(1.0 / (F.r1 * F.r1 * std::sin(th1) * std::sin(th1) * F.dph * F.dph));
     g.rho_t[0] = g.rho_t[1] = R(1);   // Dirichlet until yy_set_t_bc
+    g.rho_u[0] = g.rho_u[1] = R(1);   // Dirichlet until yy_set_u_bc
 }
 
 // parameter-dependent tables: Pr * (u_r radial) + (1/(2 chi)) * D11 per
@@ -452,6 +453,8 @@ struct yy_shell {
     // derived ghost coefficients
     double t_ab[2][2] = {{1.0, 0.0}, {1.0, 0.0}};
     TRobin tb = {{2.0, 2.0}, {1.0, 1.0}, {0.0, 0.0}};
+    // the tangential velocity's walls a u + b R dn(u/r) = g
+    URobin ub = {{2.0, 2.0}, {1.0, 1.0}};
     // FP32-mixed: T is stored as T - Tref, Tref the discrete conductive
     // profile of the wall temperatures (host copy, i = -1..nr)
     std::vector<double> tref;
@@ -552,7 +555,7 @@ template <typename R> void do_fill(yy_shell *s, int lev, int pmask, hipStream_t 
 {
     Timed tm(s, PC_FILL, st);
     Ops<R>::fill(s->L.d, state_of<R>(s), lev, s->fcc, (int)s->L.ncc, s->fvt, (int)s->L.nvt, s->fvp,
-                 (int)s->L.nvp, s->prm.t_inner, s->prm.t_outer, s->tb, walls_of(s, lev), pmask, st);
+                 (int)s->L.nvp, s->prm.t_inner, s->prm.t_outer, s->tb, s->ub, walls_of(s, lev), pmask, st);
     if (s->mass_fix) Ops<R>::mass_fix(s->L.d, s->gd, state_of<R>(s), lev, s->mf_S, s->mfp, pmask, st);
 }
 
@@ -982,6 +985,23 @@ int yy_set_t_bc(yy_shell *s, int32_t wall, double a, double b)
     s->g64.rho_t[wall] = s->tb.rho[wall];
     s->g32.rho_t[wall] = (float)s->tb.rho[wall];
     update_tshift(s);
+    s->need_fill = true;
+    s->version++;
+    return YY_OK;
+}
+
+int yy_set_u_bc(yy_shell *s, int32_t wall, double a, double b)
+{
+    if (!s || wall < 0 || wall > 1 || !(a >= 0.0) || !(b >= 0.0) || !(a + b > 0.0) || !std::isfinite(a) ||
+        !std::isfinite(b))
+        return YY_ERR_ARG;
+    const double dr = s->F.dr, R = wall == 0 ? s->F.r1 : s->F.r2;
+    const double rg = wall == 0 ? R - 0.5 * dr : R + 0.5 * dr, ri = wall == 0 ? R + 0.5 * dr : R - 0.5 * dr;
+    s->ub.cg[wall] = 1.0 / (0.5 * a + b * R / (rg * dr));
+    s->ub.rho[wall] = (0.5 * a - b * R / (ri * dr)) * s->ub.cg[wall];
+    s->gd.rho_u[wall] = s->ub.rho[wall];
+    s->g64.rho_u[wall] = s->ub.rho[wall];
+    s->g32.rho_u[wall] = (float)s->ub.rho[wall];
     s->need_fill = true;
     s->version++;
     return YY_OK;

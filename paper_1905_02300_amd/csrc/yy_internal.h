@@ -84,8 +84,10 @@ template <typename R> struct Geo {
     // parameter-dependent combinations (rebuilt when Pr or chi change):
     // Pr * rf_* + ic * gf_* (u_r radial operator) and Pr * ef_* + ic * gt_*
     CPtr<R> fr_lo, fr_up, fr_di, ft_lo, ft_up, ft_di;
-    // T's wall rule of the correction, c_ghost = -rho_t c_in (1: Dirichlet)
+    // wall rules of the correction, c_ghost = -rho c_in (1: Dirichlet): T,
+    // and the tangential velocity
     R rho_t[2];
+    R rho_u[2];
     // FP32-mixed stores T as its deviation T - Tref from the discrete
     // conductive profile Tref(r) of the wall temperatures (tdev = 1): Tref
     // at centres (FP64, index i+1, i = -1..nr) and its centred radial
@@ -103,6 +105,11 @@ struct TRobin {
     // deviation storage of T (FP32-mixed): the ghost of T - Tref is
     // cg g - shift - rho (T - Tref)_in with shift = rho Tref_in + Tref_ghost
     double shift[2];
+};
+// Robin walls of the tangential velocity a u + b R dn(u/r) = g: ghost =
+// cg g - rho u_in (Dirichlet: cg = 2, rho = 1)
+struct URobin {
+    double cg[2], rho[2];
 };
 constexpr int NTAB_R = 14;   // per-r coefficient tables (length nr+3)
 constexpr int NTAB_T = 20;   // per-theta coefficient tables (length nt+3)
@@ -187,8 +194,8 @@ template <typename R> struct Ops {
     static void extrap_copy(const Dims &d, const State<R> &s, hipStream_t st);
     static void fill(const Dims &d, const State<R> &s, int level, const FillScalar *cc, int ncc,
                      const FillVector *vt, int nvt, const FillVector *vp, int nvp,
-                     double t_in, double t_out, const TRobin &tb, const WallLev &walls, int patch_mask,
-                     hipStream_t st);
+                     double t_in, double t_out, const TRobin &tb, const URobin &ub, const WallLev &walls,
+                     int patch_mask, hipStream_t st);
     static void residual(const Dims &d, const Geo<R> &g, const State<R> &s, int field, R *out,
                          hipStream_t st);
     // one sweep; mode 0: y = solve(x); mode 1: psi_k += solve(x) and norm

@@ -497,7 +497,8 @@ __global__ void k_fill_vector(Dims d, const FillVector *__restrict__ tab, int nt
 // its wall faces.  Both velocity systems take the same data.  Thread =
 // padded (j, k) point of patch blockIdx.y.
 template <typename R>
-__global__ void k_walls(Dims d, State<R> s, int lev, double t_in, double t_out, TRobin tb, WallLev w, int pmask)
+__global__ void k_walls(Dims d, State<R> s, int lev, double t_in, double t_out, TRobin tb, URobin ub, WallLev w,
+                        int pmask)
 {
     const int p = blockIdx.y;
     if (!((pmask >> p) & 1)) return;
@@ -514,14 +515,18 @@ __global__ void k_walls(Dims d, State<R> s, int lev, double t_in, double t_out, 
     const double g0 = w.v[0][0] ? w.v[0][0][wq] : t_in, g1 = w.v[0][1] ? w.v[0][1][wq] : t_out;
     T[qm] = (R)(tb.cg[0] * g0 - tb.shift[0]) - (R)tb.rho[0] * T[q0];
     T[qp] = (R)(tb.cg[1] * g1 - tb.shift[1]) - (R)tb.rho[1] * T[q1];
-    const R a0 = wv(2, 0, R(0)), a1 = wv(2, 1, R(0)), b0 = wv(3, 0, R(0)), b1 = wv(3, 1, R(0));
+    // tangential velocity: cg g - rho u_in (Robin; Dirichlet cg = 2, rho = 1)
+    auto wd = [&](int c, int side) { return w.v[c][side] ? w.v[c][side][wq] : 0.0; };
+    const R a0 = (R)(ub.cg[0] * wd(2, 0)), a1 = (R)(ub.cg[1] * wd(2, 1));
+    const R b0 = (R)(ub.cg[0] * wd(3, 0)), b1 = (R)(ub.cg[1] * wd(3, 1));
+    const R r0 = (R)ub.rho[0], r1 = (R)ub.rho[1];
     const R c0 = wv(1, 0, R(0)), c1 = wv(1, 1, R(0));
     for (int y = 0; y < 2; y++) {
         R *a = s.u[y][1][lev], *b = s.u[y][2][lev], *c = s.u[y][0][lev];
-        a[qm] = R(2) * a0 - a[q0];
-        a[qp] = R(2) * a1 - a[q1];
-        b[qm] = R(2) * b0 - b[q0];
-        b[qp] = R(2) * b1 - b[q1];
+        a[qm] = a0 - r0 * a[q0];
+        a[qp] = a1 - r1 * a[q1];
+        b[qm] = b0 - r0 * b[q0];
+        b[qp] = b1 - r1 * b[q1];
         c[q0] = c0;
         c[ix(d, p, d.nr, j, k)] = c1;
     }
@@ -530,7 +535,8 @@ __global__ void k_walls(Dims d, State<R> s, int lev, double t_in, double t_out, 
 template <typename R>
 void Ops<R>::fill(const Dims &d, const State<R> &s, int lev, const FillScalar *cc, int ncc,
                   const FillVector *vt, int nvt, const FillVector *vp, int nvp, double t_in,
-                  double t_out, const TRobin &tb, const WallLev &walls, int pmask, hipStream_t st)
+                  double t_out, const TRobin &tb, const URobin &ub, const WallLev &walls, int pmask,
+                  hipStream_t st)
 {
     const int pl = lev == 0 ? 0 : 1;     // pressure keeps levels n and k
     // centre-type scalars: T, p1, p2 (radial 0..nr-1); u_r (faces 1..nr-1)
@@ -554,7 +560,7 @@ void Ops<R>::fill(const Dims &d, const State<R> &s, int lev, const FillScalar *c
                            (const R *)ut, (const R *)up, up, d.nr, pmask);
     }
     n = (d.np + 2) * (d.nt + 2);
-    hipLaunchKernelGGL(k_walls<R>, dim3((n + 255) / 256, 2), dim3(256), 0, st, d, s, lev, t_in, t_out, tb,
+    hipLaunchKernelGGL(k_walls<R>, dim3((n + 255) / 256, 2), dim3(256), 0, st, d, s, lev, t_in, t_out, tb, ub,
                        walls, pmask);
 }
 
@@ -809,9 +815,10 @@ __global__ void __launch_bounds__(256) k_sweep(Dims d, Geo<R> g, Geo<double> gd,
                 lo[b] = -ht * c.lo;
                 up[b] = -ht * c.up;
                 di[b] = R(1) - ht * c.di;
-                const bool tr = L == CC && !DIFF;
-                if (reflect && m == 0) di[b] = R(1) - ht * (c.di - (tr ? g.rho_t[0] : R(1)) * c.lo);
-                if (reflect && m == n - 1) di[b] = R(1) - ht * (c.di - (tr ? g.rho_t[1] : R(1)) * c.up);
+                const R rw0 = DIFF ? R(1) : (L == CC ? g.rho_t[0] : g.rho_u[0]);
+                const R rw1 = DIFF ? R(1) : (L == CC ? g.rho_t[1] : g.rho_u[1]);
+                if (reflect && m == 0) di[b] = R(1) - ht * (c.di - rw0 * c.lo);
+                if (reflect && m == n - 1) di[b] = R(1) - ht * (c.di - rw1 * c.up);
                 xv[b] = x[q];
             }
 #pragma unroll
@@ -999,10 +1006,12 @@ __device__ __forceinline__ void line_row_t(const Geo<R> &g, int ii, int jj, int 
     di = R(1) - g.ht * c.di;
     if (D == 0 && L != FR) {
         // wall rule of the correction c_ghost = -rho c_in: rho = 1 for
-        // Dirichlet walls, T's Robin rule otherwise
-        const bool t = L == CC && !DIFF;
-        if (gr == 0) di = R(1) - g.ht * (c.di - (t ? g.rho_t[0] : R(1)) * c.lo);
-        if (gr == n - 1) di = R(1) - g.ht * (c.di - (t ? g.rho_t[1] : R(1)) * c.up);
+        // Dirichlet walls, the Robin rules of T and of the tangential
+        // velocity otherwise
+        const R rw0 = DIFF ? R(1) : (L == CC ? g.rho_t[0] : g.rho_u[0]);
+        const R rw1 = DIFF ? R(1) : (L == CC ? g.rho_t[1] : g.rho_u[1]);
+        if (gr == 0) di = R(1) - g.ht * (c.di - rw0 * c.lo);
+        if (gr == n - 1) di = R(1) - g.ht * (c.di - rw1 * c.up);
     }
 }
 

@@ -27,7 +27,7 @@ EXPORTS = ["yy_workspace_bytes", "yy_create", "yy_set_params", "yy_set_field", "
            "yy_ensemble_workspace_bytes", "yy_ensemble_create", "yy_ensemble_shell",
            "yy_ensemble_step", "yy_ensemble_destroy", "yy_autotune", "yy_set_tuning", "yy_step_tol",
            "yy_set_wall", "yy_set_mass_fix", "yy_set_t_bc",
-           "yy_set_pressure_exchange", "yy_step_static"]
+           "yy_set_pressure_exchange", "yy_step_static", "yy_set_u_bc"]
 NPROF = 17
 
 
@@ -71,6 +71,7 @@ def load():
     L.yy_set_mass_fix.argtypes = [vp, i32]
     L.yy_set_pressure_exchange.argtypes = [vp, i32]
     L.yy_set_t_bc.argtypes = [vp, i32, ctypes.c_double, ctypes.c_double]
+    L.yy_set_u_bc.argtypes = [vp, i32, ctypes.c_double, ctypes.c_double]
     L.yy_step.argtypes = [vp, i32, vp]
     L.yy_step_static.argtypes = [vp, i32, vp]
     L.yy_step_tol.argtypes = [vp, i32, ctypes.c_double, P(i32), vp]
@@ -225,6 +226,11 @@ class Shell:
     def set_t_bc(self, wall, a, b):
         """Robin wall condition a T + b dT/dn = g of T (wall 0: R1, 1: R2)"""
         _check(load().yy_set_t_bc(self.h, wall, ctypes.c_double(a), ctypes.c_double(b)), "yy_set_t_bc")
+
+    def set_u_bc(self, wall, a, b):
+        """Robin wall condition a u + b R dn(u/r) = g of the tangential
+        velocity (wall 0: R1, 1: R2); (0, 1) is stress-free"""
+        _check(load().yy_set_u_bc(self.h, wall, ctypes.c_double(a), ctypes.c_double(b)), "yy_set_u_bc")
 
     def set_mass_fix(self, on):
         """Algorithm step 4 (boundary mass-flux correction) on every velocity fill"""

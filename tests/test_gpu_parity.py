@@ -106,6 +106,49 @@ def test_t_robin_parity(oracle_lib, yy):
         assert _rel(a, b) <= TOL, (I.FIELD_NAMES[f], _rel(a, b))
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_u_robin_parity(oracle_lib, yy, mode):
+    """Robin / stress-free walls of the tangential velocity (a u + b R
+    dn(u/r) = g): stress-free on R1, a Robin condition with wall data on R2;
+    the r-line solves of u_theta and u_phi alone, then 3 whole steps."""
+    print(f"case: velocity Robin walls mode {mode}", flush=True)
+    nr, nt, np_ = 8, 20, 60
+    o, g = _pair(oracle_lib, yy, nr, nt, np_, pr=0.8, ra=10.0, dt=1e-3, t_inner=1.0, mode=mode)
+    for sh in (o, g):
+        sh.set_u_bc(0, 0.0, 1.0)
+        sh.set_u_bc(1, 0.7, 0.4)
+    rng = np.random.default_rng(41)
+    _set_random(o, g, rng, [0, 1], scale=0.1)
+    grid = I.Grid(nr, nt, np_)
+
+    def walls(level):
+        for f in (I.U1T, I.U1P):
+            w = 0.05 * rng.uniform(-1, 1, (2, nt + 2, np_ + 2))
+            o.set_wall(f, level, 1, w)
+            g.set_wall(f, level, 1, w)
+
+    walls(0)
+    walls(1)
+    o.extrapolate()
+    g.extrapolate()
+    x = rng.uniform(-1, 1, o.padded_shape())
+    for f in (I.U2T, I.U2P):
+        ref = o.sweep(f, 0, x)
+        yt = g.internal_tensor()
+        g.sweep(f, 0, g.to_internal(x), yt)
+        got = g.from_internal(yt).cpu().numpy()
+        m = _unknown_mask(o.padded_shape(), f)
+        assert _rel(got[m], ref[m]) <= TOL, I.FIELD_NAMES[f]
+    for _ in range(3):
+        walls(2)
+        o.step(3)
+        g.step(3)
+    for f in range(9):
+        a = g.get_field(f).cpu().numpy()
+        b = o.get_field(f)
+        assert _rel(a, b) <= TOL, (I.FIELD_NAMES[f], _rel(a, b))
+
+
 def test_mass_fix_parity(oracle_lib, yy):
     """Algorithm step 4 (boundary mass-flux correction after each velocity
     fill): one fill of random data, then 3 manufactured steps (K=2), with
