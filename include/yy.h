@@ -312,6 +312,10 @@ int yy_residual(yy_shell *s, int32_t field, void *dev_out, hipStream_t stream);
  * YY_ERR_STATE, YY_ERR_HIP. */
 int yy_autotune(yy_shell *s, char *json_out, int32_t cap, hipStream_t stream);
 
+/* The shell's current tile choices in the JSON form of yy_autotune
+ * (NUL-terminated).  Errors: YY_ERR_ARG (null, or cap too small). */
+int yy_get_tuning(yy_shell *s, char *json_out, int32_t cap);
+
 /* Apply choices written by yy_autotune (a tuning cache).  Unknown keys are
  * ignored.  Errors: YY_ERR_ARG (NULL or malformed). */
 int yy_set_tuning(yy_shell *s, const char *json);
@@ -336,8 +340,17 @@ yy_shell *yy_ensemble_shell(yy_ensemble *e, int32_t s);
 /* Advance every shell one time step with n_schwarz Schwarz iterations.
  * The first call (and the first after any field or parameter change)
  * runs eagerly where a ghost refresh is pending, then captures the step of
- * all shells, each on its own forked stream, into hipGraphs (one per phase
- * of the time-level rotation) and replays them on later calls.
+ * all shells into hipGraphs (one per phase of the time-level rotation) and
+ * replays them on later calls.
+ * graph = 1: batched -- each launch of the step covers every shell: the
+ * shells' launches at one position of the step are grouped by kernel
+ * instance (tile) and block shape, and each group is one launch over a
+ * work list in which every shell owns a range of blocks (argument and
+ * block tables in the ensemble's workspace).  Shells whose steps do not
+ * line up (different Schwarz modes, the mass-flux correction or the
+ * pressure exchange on some only), or n_schwarz > 8, fall back to
+ * graph = 2.
+ * graph = 2: one forked stream per shell inside the graph.
  * graph = 0 enqueues the shells one after another on the stream instead.
  * A single-shell step (yy_step, yy_step_tol, yy_step_static) on a member
  * between graph steps is allowed: the graphs are captured again.  Shells
@@ -348,6 +361,23 @@ yy_shell *yy_ensemble_shell(yy_ensemble *e, int32_t s);
  * Errors: YY_ERR_ARG, YY_ERR_STATE (a shell without params, or with wall
  * data under graph = 1), YY_ERR_HIP. */
 int yy_ensemble_step(yy_ensemble *e, int32_t n_schwarz, int32_t graph, hipStream_t stream);
+
+/* Tile autotuning of an ensemble: every shell is tuned (yy_autotune), then
+ * one tile is kept per (unknown or diffusion-only, direction, line-length
+ * bucket 2^(b-1) < n <= 2^b) -- that of the bucket's largest shell -- and
+ * per (unknown, phi-extent bucket) for the residual columns, so that the
+ * batched launches group shells of similar lines.  The bucket choices go to
+ * json_out (NUL-terminated, at most cap bytes) if not NULL.  Synchronises
+ * the stream.  Errors: as yy_autotune. */
+int yy_ensemble_autotune(yy_ensemble *e, char *json_out, int32_t cap, hipStream_t stream);
+
+/* Whether the captured graphs hold batched launches (1) or per-shell
+ * streams (0, or not captured yet), the number of batched launches per
+ * step, and the number of the shells' own launches per step that they
+ * replace (both 0 unless batched).  Any output may be NULL.
+ * Errors: YY_ERR_ARG. */
+int yy_ensemble_info(const yy_ensemble *e, int32_t *batched, int64_t *launches_per_step,
+                     int64_t *shell_launches_per_step);
 
 int yy_ensemble_destroy(yy_ensemble *e);
 

@@ -1431,6 +1431,50 @@ extern "C" int yy_autotune(yy_shell *s, char *json_out, int32_t cap, hipStream_t
     return hip_status(hipGetLastError());
 }
 
+// the current tile choices of a shell, in the JSON form of yy_autotune
+static std::string tuning_json(yy_shell *s)
+{
+    const Tune &T = tune_of(s);
+    std::string js = "{";
+    for (int L = 0; L < 5; L++)
+        for (int dir = 0; dir < 3; dir++) {
+            char val[48];
+            if (dir < 2) {
+                const int m = T.m[L][dir] ? T.m[L][dir] : ((L == 2 && dir == 1) ? 12 : 16);
+                if (m == 1) std::snprintf(val, sizeof val, "t");
+                else std::snprintf(val, sizeof val, "m%dw%d%s", m, T.w[L][dir] ? T.w[L][dir] : 64, T.bl[L][dir] ? "b" : "");
+            } else {
+                if (T.wpl[L]) std::snprintf(val, sizeof val, "v%d", T.wpl[L]);
+                else std::snprintf(val, sizeof val, "l%d", T.lpb[L] ? T.lpb[L] : 1);
+            }
+            char key[16];
+            std::snprintf(key, sizeof key, "%s.%c", tune_field_name[L], dir_name[dir]);
+            if (js.size() > 1) js += ",";
+            js += "\"";
+            js += key;
+            js += "\":\"";
+            js += val;
+            js += "\"";
+        }
+    for (int L = 0; L < 4; L++) {
+        js += ",\"res.";
+        js += tune_field_name[L];
+        js += "\":\"";
+        js += RES_TILES[T.rt[L] >= 0 && T.rt[L] < N_RES_TILES ? T.rt[L] : 0].name;
+        js += "\"";
+    }
+    return js + "}";
+}
+
+extern "C" int yy_get_tuning(yy_shell *s, char *json_out, int32_t cap)
+{
+    if (!s || !json_out || cap < 1) return YY_ERR_ARG;
+    const std::string js = tuning_json(s);
+    if ((int64_t)js.size() >= cap) return YY_ERR_ARG;
+    std::memcpy(json_out, js.c_str(), js.size() + 1);
+    return YY_OK;
+}
+
 extern "C" int yy_set_tuning(yy_shell *s, const char *json)
 {
     if (!s || !json) return YY_ERR_ARG;
@@ -1501,8 +1545,14 @@ struct yy_ensemble {
     hipGraph_t graph[6] = {};
     hipGraphExec_t exec[6] = {};
     bool captured = false;
-    int phase = 0, K = 0;
+    bool batched = false;    // the graphs hold batched launches (else one stream per shell)
+    int phase = 0, K = 0, how = 0;
     std::vector<uint64_t> versions;
+    // device arena of the batched launches' argument and block tables
+    char *arena = nullptr;
+    uint64_t arena_bytes = 0;
+    int64_t batched_launches = 0;   // launches per captured step (all phases: / 6)
+    int64_t shell_launches = 0;     // the shells' own launches they replace (all phases)
 };
 
 namespace {
@@ -1620,6 +1670,148 @@ int capture(yy_ensemble *e, int K)
     return YY_OK;
 }
 
+// Batched capture (the ensemble's "one launch per phase"): the host side of
+// one step of every shell is run with the launch recorder installed, for
+// each of the six rotation phases.  At each position of the step's launch
+// sequence the shells' records are grouped by kernel instance (tile), block
+// shape and argument size; each group becomes one launch of the kernel's
+// batched twin over a 1-D grid in which each shell owns its own block range
+// (work list: off, nx, ny per shell).  The argument structs and block tables
+// are uploaded once into the arena; the six graphs hold only the launches.
+// Returns YY_ERR_STATE if the shells' step sequences do not line up (then
+// the per-shell stream capture is used).
+int capture_batched(yy_ensemble *e, int K)
+{
+    drop_graphs(e);
+    for (yy_shell *s : e->sh)
+        if (uses_walls(s) || walls_stale(s)) return YY_ERR_STATE;
+    const size_t n = e->sh.size();
+    std::vector<LevelState> snap;
+    for (yy_shell *s : e->sh) snap.push_back(save_levels(s));
+    std::vector<bool> prof(n);
+    for (size_t q = 0; q < n; q++) {
+        prof[q] = e->sh[q]->prof;
+        e->sh[q]->prof = false;
+    }
+    std::vector<std::vector<LaunchRecorder>> rec(6, std::vector<LaunchRecorder>(n));
+    int st = YY_OK;
+    for (int f = 0; f < 6 && st == YY_OK; f++)
+        for (size_t q = 0; q < n && st == YY_OK; q++) {
+            set_launch_recorder(&rec[f][q]);
+            st = shell_step(e->sh[q], K, e->cap);
+            set_launch_recorder(nullptr);
+        }
+    for (size_t q = 0; q < n; q++) {
+        restore_levels(e->sh[q], snap[q]);
+        e->sh[q]->prof = prof[q];
+    }
+    if (st != YY_OK) return st;
+    // every launch of the step needs a batched twin (the mass fix and the
+    // pressure exchange have none: such shells take the stream graph)
+    for (int f = 0; f < 6; f++)
+        for (size_t q = 0; q < n; q++)
+            if (rec[f][q].foreign) return YY_ERR_STATE;
+    // the step sequences must line up position by position
+    for (int f = 0; f < 6; f++)
+        for (size_t q = 1; q < n; q++)
+            if (rec[f][q].recs.size() != rec[f][0].recs.size()) return YY_ERR_STATE;
+    struct Group {
+        const void *multi;
+        dim3 block;
+        size_t lds;
+        uint64_t total;          // blocks
+        int nq;
+        std::vector<unsigned char> args;
+        std::vector<BatchEnt> ents;
+        uint64_t arg_off, ent_off;
+    };
+    std::vector<std::vector<Group>> groups(6);
+    uint64_t need = 0;
+    for (int f = 0; f < 6; f++) {
+        const size_t npos = rec[f][0].recs.size();
+        for (size_t i = 0; i < npos; i++) {
+            std::vector<Group> gs;
+            for (size_t q = 0; q < n; q++) {
+                const LaunchRec &r = rec[f][q].recs[i];
+                Group *g = nullptr;
+                for (Group &c : gs)
+                    if (c.multi == r.multi && c.block.x == r.block.x && c.block.y == r.block.y &&
+                        c.block.z == r.block.z && c.args.size() / std::max(c.nq, 1) == r.arg_size)
+                        g = &c;
+                if (!g) {
+                    gs.push_back(Group{r.multi, r.block, 0, 0, 0, {}, {}, 0, 0});
+                    g = &gs.back();
+                }
+                if (r.grid.z != 1) return YY_ERR_STATE;
+                const uint64_t nb = (uint64_t)r.grid.x * r.grid.y;
+                if (g->total + nb >= (1ull << 31)) return YY_ERR_STATE;
+                g->ents.push_back(BatchEnt{(int32_t)g->total, (int32_t)r.grid.x, (int32_t)r.grid.y, 0});
+                g->total += nb;
+                g->lds = std::max(g->lds, r.lds);
+                g->nq++;
+                const unsigned char *a = rec[f][q].args.data() + r.arg_off;
+                g->args.insert(g->args.end(), a, a + r.arg_size);
+            }
+            for (Group &g : gs) {
+                g.arg_off = need;
+                need += (uint64_t)align_up((int64_t)g.args.size(), ALIGN);
+                g.ent_off = need;
+                need += (uint64_t)align_up((int64_t)(g.ents.size() * sizeof(BatchEnt)), ALIGN);
+                groups[f].push_back(std::move(g));
+            }
+        }
+    }
+    if (need > e->arena_bytes) return YY_ERR_STATE;
+    std::vector<unsigned char> host(need, 0);
+    int64_t launches = 0;
+    for (int f = 0; f < 6; f++)
+        for (Group &g : groups[f]) {
+            std::memcpy(host.data() + g.arg_off, g.args.data(), g.args.size());
+            std::memcpy(host.data() + g.ent_off, g.ents.data(), g.ents.size() * sizeof(BatchEnt));
+            launches++;
+        }
+    if (hipMemcpy(e->arena, host.data(), need, hipMemcpyHostToDevice) != hipSuccess) return YY_ERR_HIP;
+    for (int f = 0; f < 6 && st == YY_OK; f++) {
+        hipError_t h = hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal);
+        for (Group &g : groups[f]) {
+            if (h != hipSuccess) break;
+            const void *list = e->arena + g.arg_off;
+            const BatchEnt *ents = (const BatchEnt *)(e->arena + g.ent_off);
+            int nq = g.nq;
+            void *args[3] = {(void *)&list, (void *)&ents, (void *)&nq};
+            h = hipLaunchKernel(g.multi, dim3((unsigned)g.total), g.block, args, g.lds, e->cap);
+        }
+        hipGraph_t gr = nullptr;
+        const hipError_t h2 = hipStreamEndCapture(e->cap, &gr);
+        if (h == hipSuccess) h = h2;
+        if (h == hipSuccess) h = hipGraphInstantiate(&e->exec[f], gr, nullptr, nullptr, 0);
+        e->graph[f] = gr;
+        if (h != hipSuccess) st = YY_ERR_HIP;
+    }
+    if (st != YY_OK) {
+        drop_graphs(e);
+        return st;
+    }
+    e->captured = true;
+    e->batched = true;
+    e->phase = 0;
+    e->K = K;
+    e->batched_launches = launches;
+    e->shell_launches = 0;
+    for (int f = 0; f < 6; f++)
+        for (size_t q = 0; q < n; q++) e->shell_launches += (int64_t)rec[f][q].recs.size();
+    for (size_t q = 0; q < n; q++) e->versions[q] = e->sh[q]->version;
+    return YY_OK;
+}
+
+// arena of the batched launches: every recorded launch of one step for K
+// <= 8 iterations, 6 phases, with the largest argument struct, per shell
+uint64_t arena_bytes_for(int32_t n)
+{
+    const uint64_t launches = 41ull * 8 + 16;     // fill 10, 7 solves x 4, 2 pressures, 1 reduce per iteration
+    return 6ull * launches * (uint64_t)n * (4096 + 64) + (1u << 20);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1634,7 +1826,7 @@ int yy_ensemble_workspace_bytes(int32_t n, const yy_grid *grids, int32_t prec, u
         if (st != YY_OK) return st;
         tot += (uint64_t)align_up((int64_t)b, ALIGN);
     }
-    *bytes = tot;
+    *bytes = tot + (uint64_t)align_up((int64_t)arena_bytes_for(n), ALIGN);
     return YY_OK;
 }
 
@@ -1675,6 +1867,8 @@ int yy_ensemble_create(int32_t n, const yy_grid *grids, int32_t prec, void *dev_
         if (st == YY_OK) e->sh.push_back(sh);
         base += align_up((int64_t)b, ALIGN);
     }
+    e->arena = base;
+    e->arena_bytes = arena_bytes_for(n);
     hipError_t h = hipSuccess;
     if (st == YY_OK) {
         e->streams.resize(n, nullptr);
@@ -1719,11 +1913,20 @@ int yy_ensemble_step(yy_ensemble *e, int32_t K, int32_t graph, hipStream_t strea
     // wall data must be set before every step, which a replay cannot do
     for (yy_shell *s : e->sh)
         if (uses_walls(s)) return YY_ERR_STATE;
-    bool stale = !e->captured || e->K != K;
+    bool stale = !e->captured || e->K != K || e->how != graph;
     for (size_t q = 0; q < e->sh.size() && !stale; q++)
         if (e->sh[q]->version != e->versions[q]) stale = true;
     bool pending = false;
     for (yy_shell *s : e->sh) pending = pending || s->need_fill;
+    // graph 1: batched launches (one per phase and tile bin), else, or if
+    // the shells' steps do not line up, one forked stream per shell; 2:
+    // forked streams
+    auto capture_any = [&]() -> int {
+        e->how = graph;
+        if (graph == 1 && K <= 8 && capture_batched(e, K) == YY_OK) return YY_OK;
+        e->batched = false;
+        return capture(e, K);
+    };
     if (stale && pending) {
         // this step runs eagerly (it performs the pending ghost refresh);
         // the graphs are captured for the following steps
@@ -1731,10 +1934,10 @@ int yy_ensemble_step(yy_ensemble *e, int32_t K, int32_t graph, hipStream_t strea
             const int st = shell_step(s, K, stream);
             if (st != YY_OK) return st;
         }
-        return capture(e, K);
+        return capture_any();
     }
     if (stale) {
-        const int st = capture(e, K);
+        const int st = capture_any();
         if (st != YY_OK) return st;
     }
     for (yy_shell *s : e->sh)
@@ -1742,6 +1945,104 @@ int yy_ensemble_step(yy_ensemble *e, int32_t K, int32_t graph, hipStream_t strea
     if (hipGraphLaunch(e->exec[e->phase], stream) != hipSuccess) return YY_ERR_HIP;
     for (yy_shell *s : e->sh) shell_rotate(s);
     e->phase = (e->phase + 1) % 6;
+    return YY_OK;
+}
+
+int yy_ensemble_autotune(yy_ensemble *e, char *json_out, int32_t cap, hipStream_t stream)
+{
+    if (!e) return YY_ERR_ARG;
+    const size_t n = e->sh.size();
+    for (yy_shell *s : e->sh) {
+        const int st = yy_autotune(s, nullptr, 0, stream);
+        if (st != YY_OK) return st;
+    }
+    auto cells = [](const yy_shell *s) { return (int64_t)s->L.d.nr * s->L.d.nt * s->L.d.np; };
+    auto bucket = [](int len) {
+        int b = 0;
+        while ((1 << b) < len) b++;
+        return b;
+    };
+    std::string js = "{";
+    // line-solve tiles per (unknown or diffusion-only, direction, line-length bucket)
+    for (int L = 0; L < 5; L++)
+        for (int dir = 0; dir < 3; dir++) {
+            std::vector<int> rep(64, -1);
+            std::vector<int> bk(n);
+            for (size_t q = 0; q < n; q++) {
+                const Dims &d = e->sh[q]->L.d;
+                const int len = (dir == 0 ? d.nr : dir == 1 ? d.nt : d.np) - (L == dir + 1 ? 1 : 0);
+                bk[q] = bucket(len);
+                if (rep[bk[q]] < 0 || cells(e->sh[q]) > cells(e->sh[rep[bk[q]]])) rep[bk[q]] = (int)q;
+            }
+            for (size_t q = 0; q < n; q++) {
+                const Tune &src = tune_of(e->sh[rep[bk[q]]]);
+                Tune &dst = tune_of(e->sh[q]);
+                if (dir < 2) {
+                    dst.m[L][dir] = src.m[L][dir];
+                    dst.w[L][dir] = src.w[L][dir];
+                    dst.bl[L][dir] = src.bl[L][dir];
+                } else {
+                    dst.lpb[L] = src.lpb[L];
+                    dst.wpl[L] = src.wpl[L];
+                }
+            }
+            for (int b = 0; b < 64; b++) {
+                if (rep[b] < 0) continue;
+                const Tune &t = tune_of(e->sh[rep[b]]);
+                char val[64];
+                if (dir < 2) {
+                    if (t.m[L][dir] == 1) std::snprintf(val, sizeof val, "t");
+                    else std::snprintf(val, sizeof val, "m%dw%d%s", t.m[L][dir], t.w[L][dir], t.bl[L][dir] ? "b" : "");
+                } else {
+                    if (t.wpl[L]) std::snprintf(val, sizeof val, "v%d", t.wpl[L]);
+                    else std::snprintf(val, sizeof val, "l%d", t.lpb[L]);
+                }
+                char key[48];
+                std::snprintf(key, sizeof key, "%s.%c.n<=%d", tune_field_name[L], dir_name[dir], 1 << b);
+                js += js.size() > 1 ? ",\"" : "\"";
+                js += key;
+                js += "\":\"";
+                js += val;
+                js += "\"";
+            }
+        }
+    // residual column tiles per (unknown, phi-extent bucket)
+    for (int L = 0; L < 4; L++) {
+        std::vector<int> rep(64, -1);
+        std::vector<int> bk(n);
+        for (size_t q = 0; q < n; q++) {
+            bk[q] = bucket(e->sh[q]->L.d.np);
+            if (rep[bk[q]] < 0 || cells(e->sh[q]) > cells(e->sh[rep[bk[q]]])) rep[bk[q]] = (int)q;
+        }
+        for (size_t q = 0; q < n; q++) tune_of(e->sh[q]).rt[L] = tune_of(e->sh[rep[bk[q]]]).rt[L];
+        for (int b = 0; b < 64; b++) {
+            if (rep[b] < 0) continue;
+            char key[48];
+            std::snprintf(key, sizeof key, "res.%s.np<=%d", tune_field_name[L], 1 << b);
+            js += ",\"";
+            js += key;
+            js += "\":\"";
+            js += RES_TILES[tune_of(e->sh[rep[b]]).rt[L]].name;
+            js += "\"";
+        }
+    }
+    js += "}";
+    for (yy_shell *s : e->sh) s->version++;
+    if (json_out && cap > 0) {
+        std::strncpy(json_out, js.c_str(), (size_t)cap - 1);
+        json_out[cap - 1] = 0;
+    }
+    return YY_OK;
+}
+
+int yy_ensemble_info(const yy_ensemble *e, int32_t *batched, int64_t *launches_per_step,
+                     int64_t *shell_launches_per_step)
+{
+    if (!e) return YY_ERR_ARG;
+    const bool b = e->captured && e->batched;
+    if (batched) *batched = b ? 1 : 0;
+    if (launches_per_step) *launches_per_step = b ? e->batched_launches / 6 : 0;
+    if (shell_launches_per_step) *shell_launches_per_step = b ? e->shell_launches / 6 : 0;
     return YY_OK;
 }
 

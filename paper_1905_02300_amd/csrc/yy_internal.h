@@ -10,6 +10,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <vector>
 
 namespace yy {
 
@@ -186,6 +187,39 @@ constexpr int64_t STATIC_FIELD_BYTES = (int64_t)32 << 20;
 constexpr int64_t STATIC_PARTIAL_BYTES = (int64_t)NSLOT * 2 * NBMAX * 8;
 constexpr int64_t STATIC_MF_BYTES = (int64_t)4 * MF_BLOCKS * 8;
 constexpr int64_t STATIC_SCRATCH_BYTES = 2 * STATIC_FIELD_BYTES + STATIC_PARTIAL_BYTES + STATIC_MF_BYTES;
+
+// ---- batched launches (ensembles) ----
+
+// shell q of a batched launch owns the logical blocks [off, off + nx ny) of
+// its 1-D grid, which it sees as a grid of nx x ny blocks
+struct BatchEnt {
+    int32_t off, nx, ny, pad;
+};
+
+// While installed (set_launch_recorder), every kernel launch of the step is
+// recorded instead of issued: the batched twin of the kernel (taking a
+// device table of argument structs and a BatchEnt table), the shell's grid,
+// block and LDS bytes, and its argument struct.
+struct LaunchRec {
+    const void *multi;       // k_multi<K> instance
+    dim3 grid, block;
+    size_t lds;
+    size_t arg_off, arg_size;   // the argument struct in LaunchRecorder::args
+};
+struct LaunchRecorder {
+    std::vector<LaunchRec> recs;
+    std::vector<unsigned char> args;
+    bool foreign = false;    // a launch with no batched twin was asked for (and skipped)
+    void push(const void *multi, dim3 grid, dim3 block, size_t lds, const void *a, size_t n)
+    {
+        LaunchRec r{multi, grid, block, lds, args.size(), n};
+        const unsigned char *b = (const unsigned char *)a;
+        args.insert(args.end(), b, b + n);
+        recs.push_back(r);
+    }
+};
+void set_launch_recorder(LaunchRecorder *r);
+LaunchRecorder *launch_recorder();
 
 // ---- launchers (yy_kernels.hip) ----
 template <typename R> struct Ops {

@@ -9,6 +9,16 @@
 
 namespace yy {
 
+// This file is compiled twice, once per compute precision (YY_ONLY_DOUBLE,
+// YY_ONLY_FLOAT), so that the two halves build in parallel; the functions
+// that are not templates live in the FP64 object.
+#if !defined(YY_ONLY_FLOAT)
+// the launch recorder of the calling thread (null: launch normally)
+static thread_local LaunchRecorder *t_recorder = nullptr;
+void set_launch_recorder(LaunchRecorder *r) { t_recorder = r; }
+LaunchRecorder *launch_recorder() { return t_recorder; }
+#endif
+
 template <typename R> struct Tri { R lo, di, up; };
 
 // ---------------------------------------------------------------------------
@@ -294,6 +304,60 @@ __device__ __forceinline__ void xcd_block(unsigned &bx, unsigned &by)
     by = l / gx;
 }
 
+// ---------------------------------------------------------------------------
+// Launches.  Every kernel of the step is a body taking its argument struct
+// and a virtual block (x, y of a grid nx x ny).  k_single runs one shell: its
+// hardware grid is the virtual grid (XCD-remapped where the body asks for
+// it).  k_multi runs many shells in one launch: shell q owns the logical
+// blocks [off_q, off_q + nx_q ny_q) of a 1-D grid (XCD-remapped as a whole)
+// and reads its arguments from a device table.
+// ---------------------------------------------------------------------------
+struct Blk { unsigned x, y, nx, ny; };
+
+__device__ __forceinline__ unsigned xcd_linear(unsigned b, unsigned n)
+{
+    const unsigned x = b & 7u, pos = b >> 3, q = n >> 3, r = n & 7u;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + pos;
+}
+
+template <class K> __global__ void __launch_bounds__(K::bounds) k_single(typename K::Args a)
+{
+    Blk b = {blockIdx.x, blockIdx.y, gridDim.x, gridDim.y};
+    if (K::xcd) {
+        const unsigned l = xcd_linear(b.x + b.y * b.nx, b.nx * b.ny);
+        b.x = l % b.nx;
+        b.y = l / b.nx;
+    }
+    K::body(a, b);
+}
+
+template <class K>
+__global__ void __launch_bounds__(K::bounds) k_multi(const typename K::Args *__restrict__ list,
+                                                     const BatchEnt *__restrict__ ents, int nq)
+{
+    const unsigned l = xcd_linear(blockIdx.x, gridDim.x);
+    int lo = 0, hi = nq - 1;                 // last entry with off <= l
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((unsigned)ents[mid].off <= l) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchEnt e = ents[lo];
+    const unsigned loc = l - (unsigned)e.off;
+    const Blk b = {loc % (unsigned)e.nx, loc / (unsigned)e.nx, (unsigned)e.nx, (unsigned)e.ny};
+    K::body(list[lo], b);
+}
+
+// launch one shell's kernel, or hand it to the launch recorder
+template <class K> void launch(dim3 grid, dim3 block, size_t lds, hipStream_t st, const typename K::Args &a)
+{
+    if (LaunchRecorder *r = launch_recorder()) {
+        r->push((const void *)k_multi<K>, grid, block, lds, &a, sizeof a);
+        return;
+    }
+    hipLaunchKernelGGL(k_single<K>, grid, block, lds, st, a);
+}
+
 // Column kernels: a block of (COL_K, COL_J) threads owns a COL_K x COL_J tile
 // of (k, j) columns, so the theta neighbours j-1, j+1 of most columns are read
 // by waves of the same block.  (Holding the waves at one radial level with a
@@ -380,20 +444,29 @@ template <typename R> struct PtrStep {
 };
 
 template <typename R>
-__global__ void k_extrap_copy(PtrStep<R> a, int64_t n)
-{
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
-         q += (int64_t)gridDim.x * blockDim.x) {
+struct ExtrapCopyArgs { PtrStep<R> p; int64_t n; };
+template <typename R> struct KExtrapCopy {
+    using Args = ExtrapCopyArgs<R>;
+    static constexpr int bounds = 256;
+    static constexpr bool xcd = false;
+    static __device__ __forceinline__ void body(const Args &a, const Blk &blk)
+    {
+        const PtrStep<R> &pa = a.p;
+        const int64_t n = a.n;
+
+    for (int64_t q = blk.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)blk.nx * blockDim.x) {
 #pragma unroll
         for (int f = 0; f < 7; f++) {
-            const R v = a.n[f][q];
-            a.s[f][q] = R(1.5) * v - R(0.5) * a.m[f][q];
-            a.k[f][q] = v;
+            const R v = pa.n[f][q];
+            pa.s[f][q] = R(1.5) * v - R(0.5) * pa.m[f][q];
+            pa.k[f][q] = v;
         }
-        a.p0k[q] = a.p0[q];
-        a.p1k[q] = a.p1[q];
+        pa.p0k[q] = pa.p0[q];
+        pa.p1k[q] = pa.p1[q];
     }
-}
+    }
+};
 
 static int grid_for(int64_t n, int bs = 256)
 {
@@ -413,6 +486,10 @@ template <typename R> void Ops<R>::extrap(const Dims &d, const State<R> &s, hipS
             a.m[f] = s.u[y][c][1];
         }
     const int64_t n = 2 * d.sP;
+    if (LaunchRecorder *r = launch_recorder()) {
+        r->foreign = true;
+        return;
+    }
     hipLaunchKernelGGL(k_extrap<R>, dim3(grid_for(n)), dim3(256), 0, st, a, n);
 }
 
@@ -431,7 +508,7 @@ template <typename R> void Ops<R>::extrap_copy(const Dims &d, const State<R> &s,
     a.p0 = s.p[0][0]; a.p0k = s.p[0][1];
     a.p1 = s.p[1][0]; a.p1k = s.p[1][1];
     const int64_t n = 2 * d.sP;
-    hipLaunchKernelGGL(k_extrap_copy<R>, dim3(grid_for(n)), dim3(256), 0, st, a, n);
+    launch<KExtrapCopy<R>>(dim3(grid_for(n)), dim3(256), 0, st, ExtrapCopyArgs<R>{a, n});
 }
 
 
@@ -457,30 +534,50 @@ __device__ __forceinline__ double gather16(const TT *__restrict__ a, int64_t bas
 // Targets of one scalar field (targets of patch blockIdx.y read the other
 // patch); thread = (target, radial index).
 template <typename TT>
-__global__ void k_fill_scalar(Dims d, const FillScalar *__restrict__ tab, int ntab, TT *a,
-                              int ilo, int ni, int pmask)
-{
-    const int p = blockIdx.y;
+struct FillScalarArgs { Dims d; const FillScalar *tab; int ntab; TT *a; int ilo, ni, pmask; };
+template <typename TT> struct KFillScalar {
+    using Args = FillScalarArgs<TT>;
+    static constexpr int bounds = 256;
+    static constexpr bool xcd = false;
+    static __device__ __forceinline__ void body(const Args &a, const Blk &blk)
+    {
+        const Dims &d = a.d;
+        const FillScalar *__restrict__ tab = a.tab;
+        const int ntab = a.ntab, ilo = a.ilo, ni = a.ni, pmask = a.pmask;
+        TT *fa = a.a;
+
+    const int p = blk.y;
     if (!((pmask >> p) & 1)) return;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blk.x * blockDim.x + threadIdx.x;
     if (t >= ntab * ni) return;
     const int e = t % ntab;
     const int i = ilo + t / ntab;
     const FillScalar &f = tab[e];
-    const double v = gather16(a, ix(d, 1 - p, i, f.dj, f.dk), d.sJ, f.wt, f.wp);
-    a[ix(d, p, i, f.tj, f.tk)] = (TT)v;
-}
+    const double v = gather16(fa, ix(d, 1 - p, i, f.dj, f.dk), d.sJ, f.wt, f.wp);
+    fa[ix(d, p, i, f.tj, f.tk)] = (TT)v;
+    }
+};
 
 // Tangential velocity targets: interpolate the other patch's u_theta (on
 // its theta-face grid) and u_phi (on its phi-face grid) to the target and
 // rotate into this patch's basis.
 template <typename R>
-__global__ void k_fill_vector(Dims d, const FillVector *__restrict__ tab, int ntab, const R *ut,
-                              const R *up, R *dst, int ni, int pmask)
-{
-    const int p = blockIdx.y;
+struct FillVectorArgs { Dims d; const FillVector *tab; int ntab; const R *ut, *up; R *dst; int ni, pmask; };
+template <typename R> struct KFillVector {
+    using Args = FillVectorArgs<R>;
+    static constexpr int bounds = 256;
+    static constexpr bool xcd = false;
+    static __device__ __forceinline__ void body(const Args &a, const Blk &blk)
+    {
+        const Dims &d = a.d;
+        const FillVector *__restrict__ tab = a.tab;
+        const int ntab = a.ntab, ni = a.ni, pmask = a.pmask;
+        const R *ut = a.ut, *up = a.up;
+        R *dst = a.dst;
+
+    const int p = blk.y;
     if (!((pmask >> p) & 1)) return;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blk.x * blockDim.x + threadIdx.x;
     if (t >= ntab * ni) return;
     const int e = t % ntab;
     const int i = t / ntab;
@@ -488,7 +585,8 @@ __global__ void k_fill_vector(Dims d, const FillVector *__restrict__ tab, int nt
     const double vt = gather16(ut, ix(d, 1 - p, i, f.tjA, f.tkA), d.sJ, f.wtA, f.wpA);
     const double vp = gather16(up, ix(d, 1 - p, i, f.tjB, f.tkB), d.sJ, f.wtB, f.wpB);
     dst[ix(d, p, i, f.tj, f.tk)] = (R)(f.ma * vt + f.mb * vp);
-}
+    }
+};
 
 // Walls r = R1, R2 (eq. eq_ns, eq_heat_convec): u_r = 0 on the wall faces;
 // reflection ghosts psi_{-1} = 2 psi_wall - psi_0 for T and the tangential
@@ -497,12 +595,24 @@ __global__ void k_fill_vector(Dims d, const FillVector *__restrict__ tab, int nt
 // its wall faces.  Both velocity systems take the same data.  Thread =
 // padded (j, k) point of patch blockIdx.y.
 template <typename R>
-__global__ void k_walls(Dims d, State<R> s, int lev, double t_in, double t_out, TRobin tb, URobin ub, WallLev w,
-                        int pmask)
-{
-    const int p = blockIdx.y;
+struct WallsArgs { Dims d; State<R> s; int lev; double t_in, t_out; TRobin tb; URobin ub; WallLev w; int pmask; };
+template <typename R> struct KWalls {
+    using Args = WallsArgs<R>;
+    static constexpr int bounds = 256;
+    static constexpr bool xcd = false;
+    static __device__ __forceinline__ void body(const Args &a, const Blk &blk)
+    {
+        const Dims &d = a.d;
+        const State<R> &s = a.s;
+        const int lev = a.lev, pmask = a.pmask;
+        const double t_in = a.t_in, t_out = a.t_out;
+        const TRobin &tb = a.tb;
+        const URobin &ub = a.ub;
+        const WallLev &w = a.w;
+
+    const int p = blk.y;
     if (!((pmask >> p) & 1)) return;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blk.x * blockDim.x + threadIdx.x;
     const int nk = d.np + 2, nj = d.nt + 2;
     if (t >= nk * nj) return;
     const int j = t / nk - 1, k = t % nk - 1;
@@ -530,7 +640,8 @@ __global__ void k_walls(Dims d, State<R> s, int lev, double t_in, double t_out, 
         c[q0] = c0;
         c[ix(d, p, d.nr, j, k)] = c1;
     }
-}
+    }
+};
 
 template <typename R>
 void Ops<R>::fill(const Dims &d, const State<R> &s, int lev, const FillScalar *cc, int ncc,
@@ -542,26 +653,25 @@ void Ops<R>::fill(const Dims &d, const State<R> &s, int lev, const FillScalar *c
     // centre-type scalars: T, p1, p2 (radial 0..nr-1); u_r (faces 1..nr-1)
     int n = ncc * d.nr;
     dim3 g((n + 255) / 256, 2);
-    hipLaunchKernelGGL(k_fill_scalar<R>, g, dim3(256), 0, st, d, cc, ncc, s.T[lev], 0, d.nr, pmask);
-    hipLaunchKernelGGL(k_fill_scalar<double>, g, dim3(256), 0, st, d, cc, ncc, s.p[0][pl], 0, d.nr, pmask);
-    hipLaunchKernelGGL(k_fill_scalar<double>, g, dim3(256), 0, st, d, cc, ncc, s.p[1][pl], 0, d.nr, pmask);
+    launch<KFillScalar<R>>(g, dim3(256), 0, st, FillScalarArgs<R>{d, cc, ncc, s.T[lev], 0, d.nr, pmask});
+    launch<KFillScalar<double>>(g, dim3(256), 0, st, FillScalarArgs<double>{d, cc, ncc, s.p[0][pl], 0, d.nr, pmask});
+    launch<KFillScalar<double>>(g, dim3(256), 0, st, FillScalarArgs<double>{d, cc, ncc, s.p[1][pl], 0, d.nr, pmask});
     n = ncc * (d.nr - 1);
     dim3 g1((n + 255) / 256, 2);
     for (int y = 0; y < 2; y++)
-        hipLaunchKernelGGL(k_fill_scalar<R>, g1, dim3(256), 0, st, d, cc, ncc, s.u[y][0][lev], 1,
-                           d.nr - 1, pmask);
+        launch<KFillScalar<R>>(g1, dim3(256), 0, st, FillScalarArgs<R>{d, cc, ncc, s.u[y][0][lev], 1, d.nr - 1, pmask});
     for (int y = 0; y < 2; y++) {
         R *ut = s.u[y][1][lev], *up = s.u[y][2][lev];
         n = nvt * d.nr;
-        hipLaunchKernelGGL(k_fill_vector<R>, dim3((n + 255) / 256, 2), dim3(256), 0, st, d, vt, nvt,
-                           (const R *)ut, (const R *)up, ut, d.nr, pmask);
+        launch<KFillVector<R>>(dim3((n + 255) / 256, 2), dim3(256), 0, st,
+                               FillVectorArgs<R>{d, vt, nvt, ut, up, ut, d.nr, pmask});
         n = nvp * d.nr;
-        hipLaunchKernelGGL(k_fill_vector<R>, dim3((n + 255) / 256, 2), dim3(256), 0, st, d, vp, nvp,
-                           (const R *)ut, (const R *)up, up, d.nr, pmask);
+        launch<KFillVector<R>>(dim3((n + 255) / 256, 2), dim3(256), 0, st,
+                               FillVectorArgs<R>{d, vp, nvp, ut, up, up, d.nr, pmask});
     }
     n = (d.np + 2) * (d.nt + 2);
-    hipLaunchKernelGGL(k_walls<R>, dim3((n + 255) / 256, 2), dim3(256), 0, st, d, s, lev, t_in, t_out, tb, ub,
-                       walls, pmask);
+    launch<KWalls<R>>(dim3((n + 255) / 256, 2), dim3(256), 0, st,
+                      WallsArgs<R>{d, s, lev, t_in, t_out, tb, ub, walls, pmask});
 }
 
 // ---------------------------------------------------------------------------
@@ -614,12 +724,24 @@ template <typename R> struct Col {
     double tg;       // T^n + T^k at i-1 (FR), in FP64
 };
 
-template <typename R, int L>
-__global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R> s, RhsIn<R> in, R *out,
-                                                      int jfast)
-{
+template <typename R>
+struct ResArgs { Dims d; Geo<R> g; State<R> s; RhsIn<R> in; R *out; int jfast; };
+template <typename R, int L> struct KResidual {
+    using Args = ResArgs<R>;
+    static constexpr int bounds = 256;
+    static constexpr bool xcd = true;
+    static __device__ __forceinline__ void body(const Args &a, const Blk &blk)
+    {
+        const Dims &d = a.d;
+        const Geo<R> &g = a.g;
+        const State<R> &s = a.s;
+        const RhsIn<R> &in = a.in;
+        R *out = a.out;
+        const int jfast = a.jfast;
+
     unsigned bx, by;
-    xcd_block(bx, by);
+    bx = blk.x;
+    by = blk.y;
     const int p = d.p0 + (int)by;
     const int j0 = ulo<L>(1), k0 = ulo<L>(2), i0 = ulo<L>(0);
     const int nj = d.nt - j0;
@@ -762,7 +884,8 @@ __global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R>
         w.bm = w.b0;
         w.b0 = w.bp;
     }
-}
+    }
+};
 
 // ---------------------------------------------------------------------------
 // a5: line sweeps (I - tau/2 L_{L,D}) y = x, Thomas algorithm per line.
@@ -772,11 +895,26 @@ __global__ void __launch_bounds__(256) k_residual_col(Dims d, Geo<R> g, State<R>
 // l2 norm of the increment into per-block partial sums.
 // Thread = line; lines along r and theta are coalesced over k.
 // ---------------------------------------------------------------------------
-template <typename R, int L, int D, int MODE, int DIFF>
-__global__ void __launch_bounds__(256) k_sweep(Dims d, Geo<R> g, Geo<double> gd, State<R> s,
-                                               const R *x, R *y, R *cb, R *psi, double *partial)
-{
-    const int p = d.p0 + blockIdx.y;
+template <typename R>
+struct SweepArgs { Dims d; Geo<R> g; Geo<double> gd; State<R> s; const R *x; R *y; R *cb; R *psi; double *partial; int P, mc; };
+template <typename R, int L, int D, int MODE, int DIFF> struct KThomas {
+    using Args = SweepArgs<R>;
+    static constexpr int bounds = 256;
+    static constexpr bool xcd = false;
+    static __device__ __forceinline__ void body(const Args &a, const Blk &blk)
+    {
+        const Dims &d = a.d;
+        const Geo<R> &g = a.g;
+        const Geo<double> &gd = a.gd;
+        const State<R> &s = a.s;
+        const R *x = a.x;
+        R *y = a.y;
+        R *cb = a.cb;
+        R *psi = a.psi;
+        double *partial = a.partial;
+        (void)cb; (void)gd; (void)partial;
+
+    const int p = d.p0 + blk.y;
     const int i0 = ulo<L>(0), j0 = ulo<L>(1), k0 = ulo<L>(2);
     // the two indices that label a line, and the along-line range
     const int nA = D == 0 ? d.nt - j0 : d.nr - i0;          // slow label
@@ -789,8 +927,8 @@ __global__ void __launch_bounds__(256) k_sweep(Dims d, Geo<R> g, Geo<double> gd,
     const R ht = g.ht;
     double acc = 0.0;
     const int64_t nlines = (int64_t)nA * nB;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nlines;
-         t += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t t = blk.x * (int64_t)blockDim.x + threadIdx.x; t < nlines;
+         t += (int64_t)blk.nx * blockDim.x) {
         const int a = (int)(t / nB), b = (int)(t % nB);
         int i, j, k;
         if (D == 0) { j = j0 + a; k = k0 + b; i = m0; }
@@ -869,9 +1007,10 @@ __global__ void __launch_bounds__(256) k_sweep(Dims d, Geo<R> g, Geo<double> gd,
     }
     if (MODE == 1) {
         const double tot = block_sum(acc);
-        if (threadIdx.x == 0) partial[p * NBMAX + blockIdx.x] = tot;
+        if (threadIdx.x == 0) partial[p * NBMAX + blk.x] = tot;
     }
-}
+    }
+};
 
 // ---------------------------------------------------------------------------
 // a5 (register-resident form): partitioned line solve.  A line of n
@@ -1042,16 +1181,30 @@ __host__ __device__ inline int sweep_ktiles(int np, int W) { return (np + W - 1)
 // elimination, rows past the chunk's end repeating its last row, so that
 // they are in flight together (more registers); otherwise each row is
 // loaded as it is eliminated.  The autotuner picks per sweep.
-template <typename R, int L, int D, int MODE, int DIFF, int M, bool BL>
-__global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<double> gd, State<R> s,
-                                                        const R *x, R *y, R *psi, double *partial)
-{
+template <typename R, int L, int D, int MODE, int DIFF, int M, bool BL> struct KStrided {
+    using Args = SweepArgs<R>;
+    static constexpr int bounds = 512;
+    static constexpr bool xcd = true;
+    static __device__ __forceinline__ void body(const Args &a, const Blk &blk)
+    {
+        const Dims &d = a.d;
+        const Geo<R> &g = a.g;
+        const Geo<double> &gd = a.gd;
+        const State<R> &s = a.s;
+        const R *x = a.x;
+        R *y = a.y;
+        R *cb = a.cb;
+        R *psi = a.psi;
+        double *partial = a.partial;
+        (void)cb; (void)gd; (void)partial;
+
     extern __shared__ unsigned char smem_raw[];
     R *sm = reinterpret_cast<R *>(smem_raw);
     const int W = blockDim.x, P = blockDim.y;
     const int lane = threadIdx.x, t = threadIdx.y;
     unsigned bx, by;
-    xcd_block(bx, by);
+    bx = blk.x;
+    by = blk.y;
     const int p = d.p0 + (int)by;
     const int i0 = ulo<L>(0), j0 = ulo<L>(1), k0 = ulo<L>(2);
     const int m0 = D == 0 ? i0 : j0;
@@ -1074,7 +1227,7 @@ __global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<dou
     }
     __syncthreads();
     double acc = 0.0;
-    for (int task = (int)bx; task < ntile * nother; task += gridDim.x) {
+    for (int task = (int)bx; task < ntile * nother; task += blk.nx) {
         const int tile = task % ntile, oth = task / ntile;
         const int k = tile * W + lane;
         const bool live = k >= k0 && k < d.np;
@@ -1205,7 +1358,8 @@ __global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<dou
             partial[p * NBMAX + bx] = tot;
         }
     }
-}
+    }
+};
 
 // Contiguous lines (D = 2, phi).  One wave per line (LPB lines per block).
 // Phase A, coalesced: lane e%64 assembles row e (coefficients from the
@@ -1215,14 +1369,27 @@ __global__ void __launch_bounds__(512) k_sweep_strided(Dims d, Geo<R> g, Geo<dou
 // in registers, the reduced system is solved by PCR over wave shuffles, and
 // the chunk's solution goes back to LDS.  Phase C, coalesced: write y (or
 // psi += y and the increment norm).
-template <typename R, int L, int MODE, int DIFF, int M>
-__global__ void __launch_bounds__(256) k_sweep_contig(Dims d, Geo<R> g, Geo<double> gd, State<R> s,
-                                                      const R *x, R *y, R *psi, double *partial,
-                                                      int P, int mc)
-{
+template <typename R, int L, int MODE, int DIFF, int M> struct KContig {
+    using Args = SweepArgs<R>;
+    static constexpr int bounds = 256;
+    static constexpr bool xcd = false;
+    static __device__ __forceinline__ void body(const Args &a, const Blk &blk)
+    {
+        const Dims &d = a.d;
+        const Geo<R> &g = a.g;
+        const Geo<double> &gd = a.gd;
+        const State<R> &s = a.s;
+        const R *x = a.x;
+        R *y = a.y;
+        R *cb = a.cb;
+        R *psi = a.psi;
+        double *partial = a.partial;
+        (void)cb; (void)gd; (void)partial;
+        const int P = a.P, mc = a.mc;
+
     extern __shared__ unsigned char smem_raw[];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lpb = blockDim.x >> 6;
-    const int p = d.p0 + blockIdx.y;
+    const int p = d.p0 + blk.y;
     const int i0 = ulo<L>(0), j0 = ulo<L>(1), k0 = ulo<L>(2);
     const int n = d.np - k0;
     const int ni = d.nr - i0, nj = d.nt - j0;
@@ -1234,7 +1401,7 @@ __global__ void __launch_bounds__(256) k_sweep_contig(Dims d, Geo<R> g, Geo<doub
     const R nu = (L == CC && !DIFF) ? R(1) : g.pr;
     const int mt = lane < P ? (lane < P - 1 ? mc : n - (P - 1) * mc) : 0;
     double acc = 0.0;
-    for (int64_t base = (int64_t)blockIdx.x * lpb; base < nlines; base += (int64_t)gridDim.x * lpb) {
+    for (int64_t base = (int64_t)blk.x * lpb; base < nlines; base += (int64_t)blk.nx * lpb) {
         const int64_t line = base + w;
         const bool lv = line < nlines;
         const int i = i0 + (int)(lv ? line / nj : 0), j = j0 + (int)(lv ? line % nj : 0);
@@ -1336,23 +1503,37 @@ __global__ void __launch_bounds__(256) k_sweep_contig(Dims d, Geo<R> g, Geo<doub
     }
     if (MODE == 1) {
         const double tot = block_sum(acc);
-        if (threadIdx.x == 0) partial[p * NBMAX + blockIdx.x] = tot;
+        if (threadIdx.x == 0) partial[p * NBMAX + blk.x] = tot;
     }
-}
+    }
+};
 
 // Contiguous lines, V = blockDim.x / 64 waves per line (one line per block
 // at a time): P = 64 V chunks of mc rows, so each lane holds a few rows
 // (fewer registers, more waves per SIMD).  Phases as in k_sweep_contig; the
 // reduced system spans the waves, so its PCR goes through LDS, reusing the
 // staging arrays of the coefficients once the chunks have consumed them.
-template <typename R, int L, int MODE, int DIFF, int M>
-__global__ void __launch_bounds__(512) k_sweep_contig_mw(Dims d, Geo<R> g, Geo<double> gd, State<R> s,
-                                                         const R *x, R *y, R *psi, double *partial,
-                                                         int P, int mc)
-{
+template <typename R, int L, int MODE, int DIFF, int M> struct KContigMw {
+    using Args = SweepArgs<R>;
+    static constexpr int bounds = 512;
+    static constexpr bool xcd = false;
+    static __device__ __forceinline__ void body(const Args &a, const Blk &blk)
+    {
+        const Dims &d = a.d;
+        const Geo<R> &g = a.g;
+        const Geo<double> &gd = a.gd;
+        const State<R> &s = a.s;
+        const R *x = a.x;
+        R *y = a.y;
+        R *cb = a.cb;
+        R *psi = a.psi;
+        double *partial = a.partial;
+        (void)cb; (void)gd; (void)partial;
+        const int P = a.P, mc = a.mc;
+
     extern __shared__ unsigned char smem_raw[];
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int p = d.p0 + blockIdx.y;
+    const int p = d.p0 + blk.y;
     const int i0 = ulo<L>(0), j0 = ulo<L>(1), k0 = ulo<L>(2);
     const int n = d.np - k0;
     const int ni = d.nr - i0, nj = d.nt - j0;
@@ -1374,7 +1555,7 @@ __global__ void __launch_bounds__(512) k_sweep_contig_mw(Dims d, Geo<R> g, Geo<d
     constexpr bool PRE = DIFF || AdvNeed<L, 2>::N <= 4;
     constexpr int NA = (PRE && !DIFF) ? AdvNeed<L, 2>::N : 1;
     double acc = 0.0;
-    for (int64_t line = blockIdx.x; line < nlines; line += gridDim.x) {
+    for (int64_t line = blk.x; line < nlines; line += blk.nx) {
         const int i = i0 + (int)(line / nj), j = j0 + (int)(line % nj);
         const int64_t q0 = ix(d, p, i, j, k0);
         // the diffusion-only operators have one (lower, diagonal, upper)
@@ -1501,14 +1682,16 @@ __global__ void __launch_bounds__(512) k_sweep_contig_mw(Dims d, Geo<R> g, Geo<d
     }
     if (MODE == 1) {
         const double tot = block_sum(acc);
-        if (tid == 0) partial[p * NBMAX + blockIdx.x] = tot;
+        if (tid == 0) partial[p * NBMAX + blk.x] = tot;
     }
-}
+    }
+};
 
 // Block shape of a strided partitioned solve of lines of n unknowns with
 // chunks of <= M rows: W lanes (consecutive k) x P chunks, W * P <= 512 and
 // a whole number of 64-lane waves, every chunk >= 2 rows.  False if the
 // line does not fit (then the per-line Thomas kernel runs).
+#if !defined(YY_ONLY_FLOAT)
 bool strided_tile(int n, int M, int wmax, int &W, int &P)
 {
     P = (n + M - 1) / M;
@@ -1522,6 +1705,7 @@ bool strided_tile(int n, int M, int wmax, int &W, int &P)
     if (2 * P > n && n > 1) return false;
     return true;
 }
+#endif
 
 // Launch the partitioned solver when the line fits the register chunks,
 // else the per-line Thomas kernel.  Returns false if it fell back.
@@ -1548,9 +1732,9 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
         if (nblocks) *nblocks = (int)b;
         const size_t lds = ((size_t)4 * P * W + (size_t)ntabs<L, D>() * n) * sizeof(R);
         const bool bl = s.tune.bl[TL][D] != 0;
+        const SweepArgs<R> sa{d, g, gd, s, x, y, s.cb, psi, partial, P, 0};
 #define YY_ST(MM, BB)                                                                                     \
-    hipLaunchKernelGGL((k_sweep_strided<R, L, D, MODE, DIFF, MM, BB>), dim3((unsigned)b, d.npatch),      \
-                       dim3(W, P), lds, st, d, g, gd, s, x, y, psi, partial)
+    launch<KStrided<R, L, D, MODE, DIFF, MM, BB>>(dim3((unsigned)b, d.npatch), dim3(W, P), lds, st, sa)
 #define YY_STM(MM) \
     do { if (bl) YY_ST(MM, true); else YY_ST(MM, false); } while (0)
         if (M == 4) YY_STM(4);
@@ -1589,9 +1773,8 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
                 if (nblocks) *nblocks = (int)b;
                 const size_t lds = (size_t)4 * mcv * (Pv + 1) * sizeof(R);
                 const dim3 grid((unsigned)b, d.npatch), block(64 * V);
-#define YY_MW(MM)                                                                                      \
-    hipLaunchKernelGGL((k_sweep_contig_mw<R, L, MODE, DIFF, MM>), grid, block, lds, st, d, g, gd, s, x, y, \
-                       psi, partial, Pv, mcv)
+                const SweepArgs<R> sa{d, g, gd, s, x, y, s.cb, psi, partial, Pv, mcv};
+#define YY_MW(MM) launch<KContigMw<R, L, MODE, DIFF, MM>>(grid, block, lds, st, sa)
                 if (mcv <= 4) YY_MW(4);
                 else if (mcv <= 6) YY_MW(6);
                 else if (mcv <= 8) YY_MW(8);
@@ -1611,20 +1794,21 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
         if (nblocks) *nblocks = (int)b;
         const size_t lds = per_line * lpb;
         const dim3 grid((unsigned)b, d.npatch), block(64 * lpb);
-        if (mc <= 8)
-            hipLaunchKernelGGL((k_sweep_contig<R, L, MODE, DIFF, 8>), grid, block, lds, st, d, g, gd, s, x, y, psi, partial, P, mc);
-        else if (mc <= 16)
-            hipLaunchKernelGGL((k_sweep_contig<R, L, MODE, DIFF, 16>), grid, block, lds, st, d, g, gd, s, x, y, psi, partial, P, mc);
-        else if (mc <= 24)
-            hipLaunchKernelGGL((k_sweep_contig<R, L, MODE, DIFF, 24>), grid, block, lds, st, d, g, gd, s, x, y, psi, partial, P, mc);
-        else
-            hipLaunchKernelGGL((k_sweep_contig<R, L, MODE, DIFF, 32>), grid, block, lds, st, d, g, gd, s, x, y, psi, partial, P, mc);
+        const SweepArgs<R> sa{d, g, gd, s, x, y, s.cb, psi, partial, P, mc};
+        if (mc <= 8) launch<KContig<R, L, MODE, DIFF, 8>>(grid, block, lds, st, sa);
+        else if (mc <= 16) launch<KContig<R, L, MODE, DIFF, 16>>(grid, block, lds, st, sa);
+        else if (mc <= 24) launch<KContig<R, L, MODE, DIFF, 24>>(grid, block, lds, st, sa);
+        else launch<KContig<R, L, MODE, DIFF, 32>>(grid, block, lds, st, sa);
         return true;
     }
 }
 
+bool partitioned_on();
+#if !defined(YY_ONLY_FLOAT)
 static bool use_partitioned = true;
 void set_partitioned(bool on) { use_partitioned = on; }
+bool partitioned_on() { return use_partitioned; }
+#endif
 
 template <typename R, int L, int D, int MODE, int DIFF>
 static void launch_sweep(const Dims &d, const Geo<R> &g, const Geo<double> &gd, const State<R> &s,
@@ -1633,13 +1817,13 @@ static void launch_sweep(const Dims &d, const Geo<R> &g, const Geo<double> &gd, 
     const int i0 = ulo<L>(0), j0 = ulo<L>(1), k0 = ulo<L>(2);
     const int nA = D == 0 ? d.nt - j0 : d.nr - i0;
     const int nB = D == 2 ? d.nt - j0 : d.np - k0;
-    if (use_partitioned && launch_partitioned<R, L, D, MODE, DIFF>(d, g, gd, s, x, y, psi, partial, nblocks, st))
+    if (partitioned_on() && launch_partitioned<R, L, D, MODE, DIFF>(d, g, gd, s, x, y, psi, partial, nblocks, st))
         return;
     int64_t b = ((int64_t)nA * nB + 255) / 256;
     if (MODE == 1 && b > SWEEP_BLOCKS) b = SWEEP_BLOCKS;
     if (nblocks) *nblocks = (int)b;
-    hipLaunchKernelGGL((k_sweep<R, L, D, MODE, DIFF>), dim3((unsigned)b, d.npatch), dim3(256), 0, st, d, g,
-                       gd, s, x, y, s.cb, psi, partial);
+    launch<KThomas<R, L, D, MODE, DIFF>>(dim3((unsigned)b, d.npatch), dim3(256), 0, st,
+                                         SweepArgs<R>{d, g, gd, s, x, y, s.cb, psi, partial, 0, 0});
 }
 
 template <typename R, int L, int MODE>
@@ -1728,10 +1912,11 @@ void Ops<R>::residual(const Dims &d, const Geo<R> &g, const State<R> &s, int fie
     const ResTile &t = RES_TILES[ti];
     const dim3 gr((unsigned)col_blocks_t(d.nt - j0, d.np, t), d.npatch), bl(t.ck, t.cj);
     const int jf = t.jfast;
-    if (L == CC) hipLaunchKernelGGL((k_residual_col<R, CC>), gr, bl, 0, st, d, g, s, in, out, jf);
-    else if (L == FR) hipLaunchKernelGGL((k_residual_col<R, FR>), gr, bl, 0, st, d, g, s, in, out, jf);
-    else if (L == FT) hipLaunchKernelGGL((k_residual_col<R, FT>), gr, bl, 0, st, d, g, s, in, out, jf);
-    else hipLaunchKernelGGL((k_residual_col<R, FP>), gr, bl, 0, st, d, g, s, in, out, jf);
+    const ResArgs<R> ra{d, g, s, in, out, jf};
+    if (L == CC) launch<KResidual<R, CC>>(gr, bl, 0, st, ra);
+    else if (L == FR) launch<KResidual<R, FR>>(gr, bl, 0, st, ra);
+    else if (L == FT) launch<KResidual<R, FT>>(gr, bl, 0, st, ra);
+    else launch<KResidual<R, FP>>(gr, bl, 0, st, ra);
 }
 
 // ---------------------------------------------------------------------------
@@ -1747,16 +1932,27 @@ void Ops<R>::residual(const Dims &d, const Geo<R> &g, const State<R> &s, int fie
 // they are not updated and leave the increment norm; the divergence norm
 // still covers every cell.
 template <typename R>
-__global__ void __launch_bounds__(256) k_pressure(Dims d, Geo<double> gd, State<R> s, int sys,
-                                                  double *pinc, double *pdiv, int nring)
-{
+struct PressArgs { Dims d; Geo<double> gd; State<R> s; int sys; double *pinc, *pdiv; int nring; };
+template <typename R> struct KPressure {
+    using Args = PressArgs<R>;
+    static constexpr int bounds = 256;
+    static constexpr bool xcd = true;
+    static __device__ __forceinline__ void body(const Args &a, const Blk &blk)
+    {
+        const Dims &d = a.d;
+        const Geo<double> &gd = a.gd;
+        const State<R> &s = a.s;
+        const int sys = a.sys, nring = a.nring;
+        double *pinc = a.pinc, *pdiv = a.pdiv;
+
     unsigned bx, by;
-    xcd_block(bx, by);
+    bx = blk.x;
+    by = blk.y;
     const int p = d.p0 + (int)by;
     const int y = sys - 1;
     double ai = 0.0, ad = 0.0;
     const unsigned ntile = (unsigned)col_blocks(d.nt, d.np);
-    for (unsigned tile = bx; tile < ntile; tile += gridDim.x) {
+    for (unsigned tile = bx; tile < ntile; tile += blk.nx) {
         int j, k;
         if (!col_of(tile, d.nt, d.np, 0, 0, j, k)) continue;
         const uint32_t sI = (uint32_t)d.sI, sJ = (uint32_t)d.sJ;
@@ -1798,7 +1994,8 @@ __global__ void __launch_bounds__(256) k_pressure(Dims d, Geo<double> gd, State<
         pinc[p * NBMAX + bx] = ti;
         if (sys == 2) pdiv[p * NBMAX + bx] = td;
     }
-}
+    }
+};
 
 template <typename R>
 void Ops<R>::pressure(const Dims &d, const Geo<R> &g, const Geo<double> &gd, const State<R> &s,
@@ -1808,8 +2005,8 @@ void Ops<R>::pressure(const Dims &d, const Geo<R> &g, const Geo<double> &gd, con
     int64_t b = col_blocks(d.nt, d.np);        // one thread per (j, k) column
     if (b > NBMAX) b = NBMAX;                   // then blocks loop over tiles
     *nb = (int)b;
-    hipLaunchKernelGGL(k_pressure<R>, dim3((unsigned)b, d.npatch), dim3(COL_K, COL_J), 0, st, d, gd, s, sys,
-                       pinc, pdiv, nring);
+    launch<KPressure<R>>(dim3((unsigned)b, d.npatch), dim3(COL_K, COL_J), 0, st,
+                         PressArgs<R>{d, gd, s, sys, pinc, pdiv, nring});
 }
 
 // ---------------------------------------------------------------------------
@@ -1821,6 +2018,7 @@ void Ops<R>::pressure(const Dims &d, const Geo<R> &g, const Geo<double> &gd, con
 // pressure update left them (ring cells are donors of the other patch's
 // ring).  Thread = (target, radial index).
 // ---------------------------------------------------------------------------
+#if !defined(YY_ONLY_FLOAT)
 __global__ void k_pring_gather(Dims d, const FillScalar *__restrict__ tab, int ntab, const double *a,
                                double *tmp)
 {
@@ -1831,7 +2029,9 @@ __global__ void k_pring_gather(Dims d, const FillScalar *__restrict__ tab, int n
     const FillScalar &f = tab[e];
     tmp[(int64_t)p * ntab * d.nr + t] = gather16(a, ix(d, 1 - p, i, f.dj, f.dk), d.sJ, f.wt, f.wp);
 }
+#endif
 
+#if !defined(YY_ONLY_FLOAT)
 __global__ void k_pring_scatter(Dims d, const FillScalar *__restrict__ tab, int ntab, double *a,
                                 const double *tmp)
 {
@@ -1842,49 +2042,72 @@ __global__ void k_pring_scatter(Dims d, const FillScalar *__restrict__ tab, int 
     const FillScalar &f = tab[e];
     a[ix(d, p, i, f.tj, f.tk)] = tmp[(int64_t)p * ntab * d.nr + t];
 }
+#endif
 
+#if !defined(YY_ONLY_FLOAT)
 void pressure_exchange(const Dims &d, double *p, const FillScalar *tab, int ntab, double *tmp,
                        hipStream_t st)
 {
+    if (LaunchRecorder *r = launch_recorder()) {
+        r->foreign = true;
+        return;
+    }
     const int n = ntab * d.nr;
     const dim3 g((unsigned)((n + 255) / 256), (unsigned)d.npatch);
     hipLaunchKernelGGL(k_pring_gather, g, dim3(256), 0, st, d, tab, ntab, (const double *)p, tmp);
     hipLaunchKernelGGL(k_pring_scatter, g, dim3(256), 0, st, d, tab, ntab, p, (const double *)tmp);
 }
+#endif
 
 // ---------------------------------------------------------------------------
 // norms: fixed-order reduction of the per-block partial sums
 // ---------------------------------------------------------------------------
 struct NB { int n[NSLOT]; };
 
-__global__ void k_reduce(const double *partial, NB nb, double *out)
-{
-    const int slot = blockIdx.x >> 1, p = blockIdx.x & 1;
+struct ReduceArgs { const double *partial; NB nb; double *out; };
+struct KReduce {
+    using Args = ReduceArgs;
+    static constexpr int bounds = 1024;
+    static constexpr bool xcd = false;
+    static __device__ __forceinline__ void body(const Args &a, const Blk &blk)
+    {
+        const double *partial = a.partial;
+        const NB &nb = a.nb;
+        double *out = a.out;
+
+    const int slot = blk.x >> 1, p = blk.x & 1;
     const double *src = partial + (int64_t)(slot * 2 + p) * NBMAX;
     double v = 0.0;
     for (int b = threadIdx.x; b < nb.n[slot]; b += blockDim.x) v += src[b];
     const double t = block_sum(v);
     if (threadIdx.x == 0) out[p * NSLOT + slot] = sqrt(t);
-}
+    }
+};
 
+#if !defined(YY_ONLY_FLOAT)
 void reduce_norms(const double *partial, const int *nblocks, double *out, hipStream_t st)
 {
     NB nb;
     for (int q = 0; q < NSLOT; q++) nb.n[q] = nblocks[q];
-    hipLaunchKernelGGL(k_reduce, dim3(2 * NSLOT), dim3(1024), 0, st, partial, nb, out);
+    launch<KReduce>(dim3(2 * NSLOT), dim3(1024), 0, st, ReduceArgs{partial, nb, out});
 }
+#endif
 
+#if !defined(YY_ONLY_FLOAT)
 __global__ void k_zero(double *p, int64_t n)
 {
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * blockDim.x)
         p[q] = 0.0;
 }
+#endif
 
+#if !defined(YY_ONLY_FLOAT)
 void zero_doubles(double *p, int64_t n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_zero, dim3(grid_for(n)), dim3(256), 0, st, p, n);
 }
+#endif
 
 // ---------------------------------------------------------------------------
 // field I/O: MAC or padded double arrays <-> internal layout
@@ -1935,6 +2158,7 @@ template <typename R> void Ops<R>::add_profile(const Dims &d, R *a, const double
     hipLaunchKernelGGL(k_add_profile<R>, dim3(grid_for(n)), dim3(256), 0, st, d, a, prof);
 }
 
+#if !defined(YY_ONLY_FLOAT)
 void io_double(const Dims &d, double *internal, const double *src, double *dst, int loc, int layout,
                hipStream_t st)
 {
@@ -1942,6 +2166,7 @@ void io_double(const Dims &d, double *internal, const double *src, double *dst, 
     hipLaunchKernelGGL(k_io<double>, dim3(grid_for(n)), dim3(256), 0, st, d, internal, src, dst, loc, layout,
                        (const double *)nullptr);
 }
+#endif
 
 // ---------------------------------------------------------------------------
 // Algorithm step 4 (mass-flux correction of the interpolated boundary data).
@@ -2039,13 +2264,21 @@ template <typename R>
 void Ops<R>::mass_fix(const Dims &d, const Geo<double> &gd, const State<R> &s, int lev, double S,
                       double *partial, int pmask, hipStream_t st)
 {
+    if (LaunchRecorder *r = launch_recorder()) {
+        r->foreign = true;
+        return;
+    }
     const dim3 g(MF_BLOCKS, 2, 2);
     hipLaunchKernelGGL(k_mflux<R>, g, dim3(256), 0, st, d, gd, s, lev, partial, pmask);
     hipLaunchKernelGGL(k_mfix<R>, dim3(64, 2, 2), dim3(256), 0, st, d, gd, s, lev, S, (const double *)partial,
                        pmask);
 }
 
+#if !defined(YY_ONLY_FLOAT)
 template struct Ops<double>;
+#endif
+#if !defined(YY_ONLY_DOUBLE)
 template struct Ops<float>;
+#endif
 
 }  // namespace yy

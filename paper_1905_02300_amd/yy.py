@@ -27,7 +27,8 @@ EXPORTS = ["yy_workspace_bytes", "yy_create", "yy_set_params", "yy_set_field", "
            "yy_ensemble_workspace_bytes", "yy_ensemble_create", "yy_ensemble_shell",
            "yy_ensemble_step", "yy_ensemble_destroy", "yy_autotune", "yy_set_tuning", "yy_step_tol",
            "yy_set_wall", "yy_set_mass_fix", "yy_set_t_bc",
-           "yy_set_pressure_exchange", "yy_step_static", "yy_set_u_bc"]
+           "yy_set_pressure_exchange", "yy_step_static", "yy_set_u_bc", "yy_ensemble_autotune",
+           "yy_ensemble_info", "yy_get_tuning"]
 NPROF = 17
 
 
@@ -95,8 +96,11 @@ def load():
     L.yy_ensemble_shell.restype = vp
     L.yy_ensemble_step.argtypes = [vp, i32, i32, vp]
     L.yy_ensemble_destroy.argtypes = [vp]
+    L.yy_ensemble_autotune.argtypes = [vp, ctypes.c_char_p, i32, vp]
+    L.yy_ensemble_info.argtypes = [vp, P(i32), P(i64), P(i64)]
     L.yy_autotune.argtypes = [vp, ctypes.c_char_p, i32, vp]
     L.yy_set_tuning.argtypes = [vp, ctypes.c_char_p]
+    L.yy_get_tuning.argtypes = [vp, ctypes.c_char_p, i32]
     _lib = L
     return L
 
@@ -307,6 +311,12 @@ class Shell:
         _check(load().yy_autotune(self.h, buf, 4096, _stream_ptr(stream)), "yy_autotune")
         return buf.value.decode()
 
+    def tuning_json(self):
+        """the current tile choices (JSON)"""
+        buf = ctypes.create_string_buffer(4096)
+        _check(load().yy_get_tuning(self.h, buf, len(buf)), "yy_get_tuning")
+        return buf.value.decode()
+
     def set_tuning(self, js):
         _check(load().yy_set_tuning(self.h, js.encode()), "yy_set_tuning")
 
@@ -364,10 +374,26 @@ class Ensemble:
                                      arr[q].delta, prec, device, _handle=sh, _ws=self.ws))
 
     def step(self, K, graph=True, stream=None):
-        _check(load().yy_ensemble_step(self.h, K, 1 if graph else 0, _stream_ptr(stream)),
-               "yy_ensemble_step")
+        """graph: True / 1 batched launches in a graph, 2 one stream per
+        shell in a graph, False / 0 the shells one after another"""
+        g = 1 if graph is True else (0 if graph is False else int(graph))
+        _check(load().yy_ensemble_step(self.h, K, g, _stream_ptr(stream)), "yy_ensemble_step")
         for sh in self.shells:
             sh.K = K
+
+    def autotune(self, stream=None):
+        """per-bucket tiles (unknown, direction, line-length bucket); returns the JSON"""
+        buf = ctypes.create_string_buffer(65536)
+        _check(load().yy_ensemble_autotune(self.h, buf, len(buf), _stream_ptr(stream)), "yy_ensemble_autotune")
+        return buf.value.decode()
+
+    def info(self):
+        """(batched, batched launches per step, the shells' own launches per
+        step they replace) of the captured graphs"""
+        b, n, m = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        _check(load().yy_ensemble_info(self.h, ctypes.byref(b), ctypes.byref(n), ctypes.byref(m)),
+               "yy_ensemble_info")
+        return bool(b.value), n.value, m.value
 
     def close(self):
         if getattr(self, "h", None):

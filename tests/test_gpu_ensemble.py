@@ -99,6 +99,38 @@ def test_ensemble_fp32_graph_autotuned(yy):
             assert rel <= lim, (q, I.FIELD_NAMES[f], rel)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_ensemble_batched_equals_streams_and_eager(yy, prec):
+    """The batched graph (one launch per step position and tile bin, each
+    shell owning a range of blocks) with per-bucket tiles from the ensemble
+    autotuner gives bitwise the results of the per-shell stream graph and
+    of graph-free stepping, over more than one rotation cycle; and it is
+    batched: fewer launches per step than the shells' launches together."""
+    print(f"case: ensemble batched vs streams vs eager, prec {prec}", flush=True)
+    states = _states()
+    ens = [_load_ensemble(yy, prec, states) for _ in range(3)]
+    tiles = ens[0].autotune()
+    assert "n<=" in tiles
+    # the same tiles on every copy (the tuner's timings may pick others)
+    for e in ens[1:]:
+        for sh, src in zip(e.shells, ens[0].shells):
+            sh.set_tuning(src.tuning_json())
+    for _ in range(8):
+        ens[0].step(K, graph=1)
+        ens[1].step(K, graph=2)
+        ens[2].step(K, graph=0)
+    batched, launches, own = ens[0].info()
+    print(f"  batched launches per step {launches}, the shells' own {own}", flush=True)
+    assert batched and 0 < launches < own
+    for q in range(len(GRIDS)):
+        for f in range(9):
+            a = ens[0].shells[q].get_field(f).cpu().numpy()
+            b = ens[1].shells[q].get_field(f).cpu().numpy()
+            c = ens[2].shells[q].get_field(f).cpu().numpy()
+            assert np.array_equal(a, b) and np.array_equal(a, c), (q, I.FIELD_NAMES[f])
+        assert np.array_equal(ens[0].shells[q].norms(), ens[2].shells[q].norms())
+
+
 def test_ensemble_member_steps_between_graph_steps(yy):
     """A single-shell step on one member between graph steps (the level
     pointers then rotate outside the captured graphs): the graphs are
@@ -144,6 +176,36 @@ def test_ensemble_graph_refuses_wall_data(yy):
         g = I.Grid(*GRIDS[0])
         e.shells[0].set_wall(I.T, 2, 0, np.ones((2, g.nt + 2, g.np + 2)))
         e.step(K, graph=False)
+    for q in range(len(GRIDS)):
+        for f in range(9):
+            x = a.shells[q].get_field(f).cpu().numpy()
+            y = b.shells[q].get_field(f).cpu().numpy()
+            assert np.array_equal(x, y), (q, I.FIELD_NAMES[f])
+
+
+def test_ensemble_batched_falls_back_for_mass_fix_and_exchange(yy):
+    """The mass fix and the pressure exchange have no batched kernels: an
+    ensemble with such a shell is captured as per-shell streams instead
+    (info reports not batched), and stays bitwise equal to graph-free
+    stepping; without them it is batched again."""
+    print("case: ensemble batched fallback (mass fix, pressure exchange)", flush=True)
+    states = _states()
+    a = _load_ensemble(yy, yy.YY_FP64, states)
+    b = _load_ensemble(yy, yy.YY_FP64, states)
+    for e in (a, b):
+        e.shells[0].set_mass_fix(1)
+        e.shells[2].set_pressure_exchange(1)
+    for _ in range(3):
+        a.step(K, graph=1)
+        b.step(K, graph=0)
+    assert a.info()[0] is False
+    for e in (a, b):
+        e.shells[0].set_mass_fix(0)
+        e.shells[2].set_pressure_exchange(0)
+    for _ in range(3):
+        a.step(K, graph=1)
+        b.step(K, graph=0)
+    assert a.info()[0] is True
     for q in range(len(GRIDS)):
         for f in range(9):
             x = a.shells[q].get_field(f).cpu().numpy()
