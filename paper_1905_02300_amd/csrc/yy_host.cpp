@@ -18,6 +18,9 @@ namespace {
 
 constexpr int MAXK = 64;
 constexpr int64_t ALIGN = 256;
+// independent chains of batched launches in an ensemble graph (one per
+// hardware queue a process gets by default)
+constexpr size_t BATCH_BRANCHES = 4;
 
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
@@ -1676,8 +1679,11 @@ int capture(yy_ensemble *e, int K)
 // sequence the shells' records are grouped by kernel instance (tile), block
 // shape and argument size; each group becomes one launch of the kernel's
 // batched twin over a 1-D grid in which each shell owns its own block range
-// (work list: off, nx, ny per shell).  The argument structs and block tables
-// are uploaded once into the arena; the six graphs hold only the launches.
+// (work list: off, nx, ny per shell).  The shells are dealt to up to four
+// branches of similar cell counts, each a chain of such launches, and the
+// branches run side by side (so one launch's tail overlaps another's
+// work).  The argument structs and block tables are uploaded once into the
+// arena; the six graphs hold only the launches.
 // Returns YY_ERR_STATE if the shells' step sequences do not line up (then
 // the per-shell stream capture is used).
 int capture_batched(yy_ensemble *e, int K)
@@ -1725,39 +1731,83 @@ int capture_batched(yy_ensemble *e, int K)
         std::vector<BatchEnt> ents;
         uint64_t arg_off, ent_off;
     };
-    std::vector<std::vector<Group>> groups(6);
+    // branches: the shells are dealt to up to BATCH_BRANCHES independent
+    // chains of batched launches (largest shells first, each to the chain
+    // with the fewest cells so far), which the graph runs side by side
+    const int nbr = (int)std::min<size_t>(BATCH_BRANCHES, n);
+    std::vector<std::vector<size_t>> branch(nbr);
+    {
+        std::vector<size_t> order(n);
+        for (size_t q = 0; q < n; q++) order[q] = q;
+        auto cells = [&](size_t q) { return (int64_t)e->sh[q]->L.d.nr * e->sh[q]->L.d.nt * e->sh[q]->L.d.np; };
+        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cells(a) > cells(b); });
+        std::vector<int64_t> load(nbr, 0);
+        for (size_t q : order) {
+            const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            branch[b].push_back(q);
+            load[b] += cells(q);
+        }
+        for (auto &br : branch) std::sort(br.begin(), br.end());
+    }
+    // groups[f][b]: the launches of branch b in phase f, in order
+    std::vector<std::vector<std::vector<Group>>> groups(6, std::vector<std::vector<Group>>(nbr));
     uint64_t need = 0;
     for (int f = 0; f < 6; f++) {
         const size_t npos = rec[f][0].recs.size();
+        for (int br = 0; br < nbr; br++)
         for (size_t i = 0; i < npos; i++) {
+            // members of each group: the shells whose launch at this
+            // position is the same kernel instance, block shape and
+            // argument size
             std::vector<Group> gs;
-            for (size_t q = 0; q < n; q++) {
+            std::vector<std::vector<size_t>> mem;
+            for (size_t q : branch[br]) {
                 const LaunchRec &r = rec[f][q].recs[i];
-                Group *g = nullptr;
-                for (Group &c : gs)
-                    if (c.multi == r.multi && c.block.x == r.block.x && c.block.y == r.block.y &&
-                        c.block.z == r.block.z && c.args.size() / std::max(c.nq, 1) == r.arg_size)
-                        g = &c;
-                if (!g) {
-                    gs.push_back(Group{r.multi, r.block, 0, 0, 0, {}, {}, 0, 0});
-                    g = &gs.back();
-                }
                 if (r.grid.z != 1) return YY_ERR_STATE;
-                const uint64_t nb = (uint64_t)r.grid.x * r.grid.y;
-                if (g->total + nb >= (1ull << 31)) return YY_ERR_STATE;
-                g->ents.push_back(BatchEnt{(int32_t)g->total, (int32_t)r.grid.x, (int32_t)r.grid.y, 0});
-                g->total += nb;
-                g->lds = std::max(g->lds, r.lds);
-                g->nq++;
-                const unsigned char *a = rec[f][q].args.data() + r.arg_off;
-                g->args.insert(g->args.end(), a, a + r.arg_size);
+                size_t gi = gs.size();
+                for (size_t c = 0; c < gs.size(); c++)
+                    if (gs[c].multi == r.multi && gs[c].block.x == r.block.x && gs[c].block.y == r.block.y &&
+                        gs[c].block.z == r.block.z && rec[f][mem[c][0]].recs[i].arg_size == r.arg_size)
+                        gi = c;
+                if (gi == gs.size()) {
+                    gs.push_back(Group{r.multi, r.block, 0, 0, 0, {}, {}, 0, 0});
+                    mem.emplace_back();
+                }
+                mem[gi].push_back(q);
+            }
+            // the heaviest blocks (most cells per block) are dispatched
+            // first; each shell's range starts on a multiple of 8 blocks and
+            // is padded to one, so that its blocks spread evenly over the
+            // 8 XCDs (the batched kernel remaps within the shell's range)
+            for (size_t c = 0; c < gs.size(); c++) {
+                Group &g = gs[c];
+                auto weight = [&](size_t q) {
+                    const LaunchRec &r = rec[f][q].recs[i];
+                    const Dims &d = e->sh[q]->L.d;
+                    return (double)d.nr * d.nt * d.np / ((double)r.grid.x * r.grid.y);
+                };
+                std::stable_sort(mem[c].begin(), mem[c].end(),
+                                 [&](size_t a, size_t b) { return weight(a) > weight(b); });
+                for (size_t q : mem[c]) {
+                    const LaunchRec &r = rec[f][q].recs[i];
+                    const uint64_t nb = (uint64_t)r.grid.x * r.grid.y;
+                    const uint64_t padded = (nb + 7) & ~7ull;
+                    if (g.total + padded >= (1ull << 31)) return YY_ERR_STATE;
+                    g.ents.push_back(BatchEnt{(int32_t)g.total, (int32_t)r.grid.x, (int32_t)r.grid.y,
+                                              (int32_t)padded});
+                    g.total += padded;
+                    g.lds = std::max(g.lds, r.lds);
+                    g.nq++;
+                    const unsigned char *a = rec[f][q].args.data() + r.arg_off;
+                    g.args.insert(g.args.end(), a, a + r.arg_size);
+                }
             }
             for (Group &g : gs) {
                 g.arg_off = need;
                 need += (uint64_t)align_up((int64_t)g.args.size(), ALIGN);
                 g.ent_off = need;
                 need += (uint64_t)align_up((int64_t)(g.ents.size() * sizeof(BatchEnt)), ALIGN);
-                groups[f].push_back(std::move(g));
+                groups[f][br].push_back(std::move(g));
             }
         }
     }
@@ -1765,21 +1815,29 @@ int capture_batched(yy_ensemble *e, int K)
     std::vector<unsigned char> host(need, 0);
     int64_t launches = 0;
     for (int f = 0; f < 6; f++)
-        for (Group &g : groups[f]) {
-            std::memcpy(host.data() + g.arg_off, g.args.data(), g.args.size());
-            std::memcpy(host.data() + g.ent_off, g.ents.data(), g.ents.size() * sizeof(BatchEnt));
-            launches++;
-        }
+        for (auto &gb : groups[f])
+            for (Group &g : gb) {
+                std::memcpy(host.data() + g.arg_off, g.args.data(), g.args.size());
+                std::memcpy(host.data() + g.ent_off, g.ents.data(), g.ents.size() * sizeof(BatchEnt));
+                launches++;
+            }
     if (hipMemcpy(e->arena, host.data(), need, hipMemcpyHostToDevice) != hipSuccess) return YY_ERR_HIP;
     for (int f = 0; f < 6 && st == YY_OK; f++) {
         hipError_t h = hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal);
-        for (Group &g : groups[f]) {
-            if (h != hipSuccess) break;
-            const void *list = e->arena + g.arg_off;
-            const BatchEnt *ents = (const BatchEnt *)(e->arena + g.ent_off);
-            int nq = g.nq;
-            void *args[3] = {(void *)&list, (void *)&ents, (void *)&nq};
-            h = hipLaunchKernel(g.multi, dim3((unsigned)g.total), g.block, args, g.lds, e->cap);
+        if (h == hipSuccess) h = hipEventRecord(e->fork, e->cap);
+        for (int br = 0; br < nbr && h == hipSuccess; br++) {
+            hipStream_t bs = e->streams[br];
+            h = hipStreamWaitEvent(bs, e->fork, 0);
+            for (Group &g : groups[f][br]) {
+                if (h != hipSuccess) break;
+                const void *list = e->arena + g.arg_off;
+                const BatchEnt *ents = (const BatchEnt *)(e->arena + g.ent_off);
+                int nq = g.nq;
+                void *args[3] = {(void *)&list, (void *)&ents, (void *)&nq};
+                h = hipLaunchKernel(g.multi, dim3((unsigned)g.total), g.block, args, g.lds, bs);
+            }
+            if (h == hipSuccess) h = hipEventRecord(e->join[br], bs);
+            if (h == hipSuccess) h = hipStreamWaitEvent(e->cap, e->join[br], 0);
         }
         hipGraph_t gr = nullptr;
         const hipError_t h2 = hipStreamEndCapture(e->cap, &gr);

@@ -192,8 +192,11 @@ constexpr int64_t STATIC_SCRATCH_BYTES = 2 * STATIC_FIELD_BYTES + STATIC_PARTIAL
 
 // shell q of a batched launch owns the logical blocks [off, off + nx ny) of
 // its 1-D grid, which it sees as a grid of nx x ny blocks
+// one shell's part of a batched launch: blocks [off, off + padded) of the
+// 1-D grid (off and padded multiples of 8), of which the first nx*ny are
+// the shell's grid nx x ny
 struct BatchEnt {
-    int32_t off, nx, ny, pad;
+    int32_t off, nx, ny, padded;
 };
 
 // While installed (set_launch_recorder), every kernel launch of the step is

@@ -308,9 +308,10 @@ __device__ __forceinline__ void xcd_block(unsigned &bx, unsigned &by)
 // Launches.  Every kernel of the step is a body taking its argument struct
 // and a virtual block (x, y of a grid nx x ny).  k_single runs one shell: its
 // hardware grid is the virtual grid (XCD-remapped where the body asks for
-// it).  k_multi runs many shells in one launch: shell q owns the logical
-// blocks [off_q, off_q + nx_q ny_q) of a 1-D grid (XCD-remapped as a whole)
-// and reads its arguments from a device table.
+// it).  k_multi runs many shells in one launch: shell q owns the blocks
+// [off_q, off_q + padded_q) of a 1-D grid (multiples of 8; XCD-remapped
+// within the range where the body asks for it, the padding blocks exit) and
+// reads its arguments from a device table.
 // ---------------------------------------------------------------------------
 struct Blk { unsigned x, y, nx, ny; };
 
@@ -335,15 +336,19 @@ template <class K>
 __global__ void __launch_bounds__(K::bounds) k_multi(const typename K::Args *__restrict__ list,
                                                      const BatchEnt *__restrict__ ents, int nq)
 {
-    const unsigned l = xcd_linear(blockIdx.x, gridDim.x);
-    int lo = 0, hi = nq - 1;                 // last entry with off <= l
+    const unsigned hb = blockIdx.x;
+    int lo = 0, hi = nq - 1;                 // last entry with off <= hb
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if ((unsigned)ents[mid].off <= l) lo = mid;
+        if ((unsigned)ents[mid].off <= hb) lo = mid;
         else hi = mid - 1;
     }
     const BatchEnt e = ents[lo];
-    const unsigned loc = l - (unsigned)e.off;
+    // the shell's range starts on a multiple of 8, so hb - off keeps the
+    // XCD residue: the remap spreads the shell evenly over the XCDs
+    unsigned loc = hb - (unsigned)e.off;
+    if (K::xcd) loc = xcd_linear(loc, (unsigned)e.padded);
+    if (loc >= (unsigned)e.nx * (unsigned)e.ny) return;
     const Blk b = {loc % (unsigned)e.nx, loc / (unsigned)e.nx, (unsigned)e.nx, (unsigned)e.ny};
     K::body(list[lo], b);
 }

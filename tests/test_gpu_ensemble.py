@@ -25,14 +25,14 @@ def yy():
     return mod
 
 
-def _states():
-    return [I.convection_state(I.Grid(*g), 1.0, ra, seed=1000 + q) for q, (g, ra) in enumerate(zip(GRIDS, RAS))]
+def _states(grids=GRIDS, ras=RAS):
+    return [I.convection_state(I.Grid(*g), 1.0, ra, seed=1000 + q) for q, (g, ra) in enumerate(zip(grids, ras))]
 
 
-def _load_ensemble(yy, prec, states):
-    e = yy.Ensemble(GRIDS, prec=prec)
+def _load_ensemble(yy, prec, states, grids=GRIDS, ras=RAS):
+    e = yy.Ensemble(grids, prec=prec)
     for q, sh in enumerate(e.shells):
-        sh.set_params(pr=1.0, ra=RAS[q], dt=DT, t_inner=1.0)
+        sh.set_params(pr=1.0, ra=ras[q], dt=DT, t_inner=1.0)
         for f in range(9):
             sh.set_field(f, 0, states[q][f])
             if f not in (I.P1, I.P2):
@@ -101,14 +101,18 @@ def test_ensemble_fp32_graph_autotuned(yy):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_ensemble_batched_equals_streams_and_eager(yy, prec):
-    """The batched graph (one launch per step position and tile bin, each
-    shell owning a range of blocks) with per-bucket tiles from the ensemble
+    """The batched graph (per branch of shells, one launch per step position
+    and tile bin, each shell owning a range of blocks) with per-bucket tiles
+    from the ensemble
     autotuner gives bitwise the results of the per-shell stream graph and
     of graph-free stepping, over more than one rotation cycle; and it is
     batched: fewer launches per step than the shells' launches together."""
     print(f"case: ensemble batched vs streams vs eager, prec {prec}", flush=True)
-    states = _states()
-    ens = [_load_ensemble(yy, prec, states) for _ in range(3)]
+    # eight shells, so that the four branches batch two shells each
+    grids = GRIDS + [(6, 14, 42), (12, 12, 36), (6, 12, 36), (10, 22, 66), (8, 18, 54)]
+    ras = RAS + [3e3, 3e4, 1e3, 1e5, 1e4]
+    states = _states(grids, ras)
+    ens = [_load_ensemble(yy, prec, states, grids, ras) for _ in range(3)]
     tiles = ens[0].autotune()
     assert "n<=" in tiles
     # the same tiles on every copy (the tuner's timings may pick others)
@@ -122,7 +126,7 @@ def test_ensemble_batched_equals_streams_and_eager(yy, prec):
     batched, launches, own = ens[0].info()
     print(f"  batched launches per step {launches}, the shells' own {own}", flush=True)
     assert batched and 0 < launches < own
-    for q in range(len(GRIDS)):
+    for q in range(len(grids)):
         for f in range(9):
             a = ens[0].shells[q].get_field(f).cpu().numpy()
             b = ens[1].shells[q].get_field(f).cpu().numpy()
