@@ -144,15 +144,17 @@ struct Tune {
     int8_t rt[4];            // residual column tile per location (index into RES_TILES)
 };
 
-// Column tiles of the residual kernels: (k extent, j extent) of a
-// 256-thread block and the order in which consecutive blocks take tiles
-// (k-tiles fastest, or j-tiles fastest so that blocks sharing theta-halo
-// rows run together).  Index 0 is the default.
-struct ResTile { int ck, cj, jfast; const char *name; };
-constexpr int N_RES_TILES = 8;
+// Column tiles of the residual kernels: (k extent, j extent) of a block
+// and the order in which consecutive blocks take tiles (k-tiles fastest, or
+// j-tiles fastest so that blocks sharing theta-halo rows run together);
+// lds: the neighbours are staged in LDS planes (64 x cj threads), else read
+// from memory (256 threads).  Index 0 is the default.
+struct ResTile { int ck, cj, jfast, lds; const char *name; };
+constexpr int N_RES_TILES = 12;
 constexpr ResTile RES_TILES[N_RES_TILES] = {
-    {64, 4, 0, "64x4k"}, {64, 4, 1, "64x4j"}, {128, 2, 1, "128x2j"}, {256, 1, 1, "256x1j"},
-    {128, 2, 0, "128x2k"}, {32, 8, 1, "32x8j"}, {32, 8, 0, "32x8k"}, {16, 16, 0, "16x16k"}};
+    {64, 4, 0, 0, "64x4k"}, {64, 4, 1, 0, "64x4j"}, {128, 2, 1, 0, "128x2j"}, {256, 1, 1, 0, "256x1j"},
+    {128, 2, 0, 0, "128x2k"}, {32, 8, 1, 0, "32x8j"}, {32, 8, 0, 0, "32x8k"}, {16, 16, 0, 0, "16x16k"},
+    {64, 4, 0, 1, "lds64x4k"}, {64, 8, 0, 1, "lds64x8k"}, {64, 8, 1, 1, "lds64x8j"}, {64, 16, 0, 1, "lds64x16k"}};
 
 // pointers of one step (compute precision R; pressures double)
 template <typename R> struct State {

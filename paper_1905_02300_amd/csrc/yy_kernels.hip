@@ -5,6 +5,8 @@
 // the FP32-mixed mode, where pressure accumulation, the divergence and all
 // norms stay in double).  Memory-bound throughout: no dense contraction, so
 // no MFMA; coalescing is along phi (k), the fastest index.
+#include <type_traits>
+
 #include "yy_internal.h"
 
 namespace yy {
@@ -321,7 +323,13 @@ __device__ __forceinline__ unsigned xcd_linear(unsigned b, unsigned n)
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + pos;
 }
 
-template <class K> __global__ void __launch_bounds__(K::bounds) k_single(typename K::Args a)
+// waves per SIMD a kernel asks to keep (its register budget), 1 if it names none
+template <class K, class = void> struct WpeOf { static constexpr int v = 1; };
+template <class K> struct WpeOf<K, std::void_t<decltype(K::wpe)>> { static constexpr int v = K::wpe; };
+
+template <class K>
+__global__ void __launch_bounds__(K::bounds) __attribute__((amdgpu_waves_per_eu(WpeOf<K>::v)))
+k_single(typename K::Args a)
 {
     Blk b = {blockIdx.x, blockIdx.y, gridDim.x, gridDim.y};
     if (K::xcd) {
@@ -333,8 +341,8 @@ template <class K> __global__ void __launch_bounds__(K::bounds) k_single(typenam
 }
 
 template <class K>
-__global__ void __launch_bounds__(K::bounds) k_multi(const typename K::Args *__restrict__ list,
-                                                     const BatchEnt *__restrict__ ents, int nq)
+__global__ void __launch_bounds__(K::bounds) __attribute__((amdgpu_waves_per_eu(WpeOf<K>::v)))
+k_multi(const typename K::Args *__restrict__ list, const BatchEnt *__restrict__ ents, int nq)
 {
     const unsigned hb = blockIdx.x;
     int lo = 0, hi = nq - 1;                 // last entry with off <= hb
@@ -719,7 +727,10 @@ __device__ __forceinline__ double ptilde(const RhsIn<R> &in, int64_t q)
 // Residual, column-marching form: a thread owns one (patch, j, k) column
 // and walks i upwards, keeping every value it needs at i-1 / i / i+1 of the
 // same (j, k) offset in registers (sliding windows), so each r-neighbour is
-// fetched once.  The arithmetic is the point form above, term by term.
+// fetched once.  The arithmetic is the point form above, term by term; it
+// is written once (res_point) and fed by two kernels that differ only in
+// where the theta and phi neighbours come from: memory (KResidual) or
+// planes staged in LDS (KResidualLds).
 template <typename R> struct Col {
     // psibar = (psi^n + psi^{k-1})/2 at i-1, i, i+1
     R bm, b0, bp;
@@ -729,8 +740,228 @@ template <typename R> struct Col {
     double tg;       // T^n + T^k at i-1 (FR), in FP64
 };
 
+// The values one point update at (i, j, k) reads besides its windows.
+// Common: psibar at i+1 (own) and at the theta/phi neighbours at i; psi* at
+// the point and its four neighbours; forcing; psi^k - psi^n at the point.
+// Location-specific (names as in res_point):
+//   CC  wr1 = w_r at face i+1; t0, t1 = w_t at j, j+1; p0, p1 = w_p at k, k+1
+//   FR  wr0 = w_r; t0, t1, p0, p1 as CC; e0, e1 = u*_t at j, j+1;
+//       f0, f1 = u*_p at k, k+1; Tn, Tk; pt = p~
+//   FT  r0, r1 = w_r at (i+1, j-1), (i+1, j); t0 = w_t; p0..p3 = w_p at
+//       (j-1,k), (j-1,k+1), (j,k), (j,k+1); u0, u1 = 2 ubar_r at (i+1, j-1),
+//       (i+1, j); s0..s3 = u*_p at (j,k+1), (j,k), (j-1,k+1), (j-1,k);
+//       pt, pm = p~ at j, j-1
+//   FP  r0, r1 = w_r at (i+1, k-1), (i+1, k); p0 = w_p; t0..t3 = w_t at
+//       (j,k-1), (j+1,k-1), (j,k), (j+1,k); u0, u1 = 2 ubar_r at (i+1, k-1),
+//       (i+1, k); h0..h3 = u^n_t + u^k_t at (j,k), (j+1,k), (j,k-1),
+//       (j+1,k-1); pt, pm = p~ at k, k-1
+template <typename R> struct ResNb {
+    R bp, bjm, bjp, bkm, bkp;
+    R x0, xjm, xjp, xkm, xkp;
+    R f, dk;
+    R wr0, wr1, r0, r1, u0, u1;
+    R t0, t1, t2, t3, p0, p1, p2, p3;
+    R e0, e1, f0, f1, s0, s1, s2, s3, h0, h1, h2, h3;
+    R Tn, Tk;
+    double pt, pm;
+};
+
+// one point update; returns tau R^k and advances the radial windows
+template <typename R, int L>
+__device__ __forceinline__ R res_point(const Geo<R> &g, int i, int j, const ResNb<R> &n, Col<R> &w)
+{
+    const R nu = L == CC ? R(1) : g.pr;
+    w.bp = n.bp;
+    R ar, at, ap, S = n.f;
+    if (L == CC) {
+        const R wr1 = n.wr1;
+        ar = R(0.5) * (w.a0 + wr1);
+        at = R(0.5) * (n.t0 + n.t1);
+        ap = R(0.5) * (n.p0 + n.p1);
+        w.a0 = wr1;
+    } else if (L == FR) {
+        const R t0 = n.t0, t1 = n.t1, p0 = n.p0, p1 = n.p1;
+        ar = n.wr0;
+        at = R(0.25) * ((w.a0 + w.a1) + (t0 + t1));
+        ap = R(0.25) * ((w.c0 + w.c1) + (p0 + p1));
+        const R e0 = n.e0, e1 = n.e1, f0 = n.f0, f1 = n.f1;
+        // (D12 u_t* + D13 u_p*)/(2 chi)
+        const R dtc = g.ir_c[i + 1] * (g.dt_p[j + 1] * e1 - g.dt_m[j + 1] * e0);
+        const R dtm = g.ir_c[i] * (g.dt_p[j + 1] * w.e1 - g.dt_m[j + 1] * w.e0);
+        const R dpc = g.ir_c[i + 1] * g.dp_c[j + 1] * (f1 - f0);
+        const R dpm = g.ir_c[i] * g.dp_c[j + 1] * (w.f1 - w.f0);
+        S += g.ic * g.idr * ((dtc - dtm) + (dpc - dpm));
+        const R vt = R(0.25) * ((w.e0 + w.e1) + (e0 + e1));
+        const R vp = R(0.25) * ((w.f0 + w.f1) + (f0 + f1));
+        S += (at * vt + ap * vp) * g.ir_f[i + 1];
+        // -d_r p~ + Pr Ra T^{n+1/2}: the hydrostatic balance cancels
+        // two large terms, so they are combined in FP64 before rounding
+        const double pt = n.pt;
+        const double tg = (double)n.Tn + (double)n.Tk + 2.0 * g.tref[i + 1];
+        S += (R)(g.prra_d * 0.25 * (w.tg + tg) - (pt - w.pm) * (double)g.idr);
+        w.a0 = t0; w.a1 = t1; w.c0 = p0; w.c1 = p1;
+        w.e0 = e0; w.e1 = e1; w.f0 = f0; w.f1 = f1;
+        w.tg = tg; w.pm = pt;
+    } else if (L == FT) {
+        const R r0 = n.r0, r1 = n.r1;
+        ar = R(0.25) * ((w.a0 + r0) + (w.a1 + r1));
+        at = n.t0;
+        ap = R(0.25) * ((n.p0 + n.p1) + (n.p2 + n.p3));
+        const R ir = g.ir_c[i + 1], ir2 = g.ir2_c[i + 1], cot = g.cot_f[j + 1];
+        const R u0 = n.u0;                        // 2 ubar_r at (i+1, j-1)
+        const R u1 = n.u1;                        // 2 ubar_r at (i+1, j)
+        // Div_r of ubar at centres (i, j) and (i, j-1), times 2
+        const R dj0 = g.dr_p[i + 1] * u1 - g.dr_m[i + 1] * w.c1;
+        const R dj1 = g.dr_p[i + 1] * u0 - g.dr_m[i + 1] * w.c0;
+        const R d23 = g.ir_c[i + 1] * (g.dp_c[j + 1] * (n.s0 - n.s1) -
+                                       g.dp_c[j] * (n.s2 - n.s3));
+        S += g.ic * ir * g.idth * (R(0.5) * (dj0 - dj1) + d23);
+        const R dth_ur = R(0.5) * ((R(0.5) * w.c1 - R(0.5) * w.c0) + (R(0.5) * u1 - R(0.5) * u0)) * g.idth;
+        const R fp2 = g.rf[i + 2] * g.rf[i + 2], fm2 = g.rf[i + 1] * g.rf[i + 1];
+        const R dr_r2ur = R(0.5) * ((fp2 * R(0.5) * u0 - fm2 * R(0.5) * w.c0) +
+                                    (fp2 * R(0.5) * u1 - fm2 * R(0.5) * w.c1)) * g.idr;
+        S += g.pr * R(2) * ir2 * (dth_ur + cot * ir * dr_r2ur);
+        const R vp = R(0.25) * ((n.s3 + n.s2) + (n.s1 + n.s0));
+        S += ap * vp * cot * ir;
+        S -= (R)((n.pt - n.pm) * (double)ir * (double)g.idth);
+        w.a0 = r0; w.a1 = r1; w.c0 = u0; w.c1 = u1;
+    } else {
+        const R r0 = n.r0, r1 = n.r1;
+        ar = R(0.25) * ((w.a0 + r0) + (w.a1 + r1));
+        at = R(0.25) * ((n.t0 + n.t1) + (n.t2 + n.t3));
+        ap = n.p0;
+        const R ir = g.ir_c[i + 1], ir2 = g.ir2_c[i + 1], isn = g.is_c[j + 1], cot = g.cot_c[j + 1];
+        const R igg = ir * g.dp_c[j + 1];
+        const R u0 = n.u0;                        // 2 ubar_r at (i+1, k-1)
+        const R u1 = n.u1;                        // 2 ubar_r at (i+1, k)
+        const R a0 = g.dr_p[i + 1] * u1 - g.dr_m[i + 1] * w.c1;
+        const R a1 = g.dr_p[i + 1] * u0 - g.dr_m[i + 1] * w.c0;
+        const R th00 = n.h0, th01 = n.h1, thm0 = n.h2, thm1 = n.h3;
+        const R b0 = ir * (g.dt_p[j + 1] * th01 - g.dt_m[j + 1] * th00);
+        const R b1 = ir * (g.dt_p[j + 1] * thm1 - g.dt_m[j + 1] * thm0);
+        S += g.ic * igg * R(0.5) * ((a0 - a1) + (b0 - b1));
+        const R dph_ur = R(0.5) * ((R(0.5) * w.c1 - R(0.5) * w.c0) + (R(0.5) * u1 - R(0.5) * u0)) * g.idph;
+        const R dph_ut = R(0.5) * ((R(0.5) * th00 - R(0.5) * thm0) + (R(0.5) * th01 - R(0.5) * thm1)) * g.idph;
+        S += g.pr * R(2) * ir2 * isn * (dph_ur + cot * dph_ut);
+        S -= (R)((n.pt - n.pm) * (double)igg);
+        w.a0 = r0; w.a1 = r1; w.c0 = u0; w.c1 = u1;
+    }
+    const Tri<R> c0 = coef<L, 0>(g, i, j, ar, at, ap, nu);
+    const Tri<R> c1 = coef<L, 1>(g, i, j, ar, at, ap, nu);
+    const Tri<R> c2 = coef<L, 2>(g, i, j, ar, at, ap, nu);
+    R Rv = c0.lo * w.bm + c0.di * w.b0 + c0.up * w.bp;
+    Rv += c1.lo * n.bjm + c1.di * w.b0 + c1.up * n.bjp;
+    Rv += c2.lo * n.bkm + c2.di * w.b0 + c2.up * n.bkp;
+    const R ir2 = L == FR ? g.ir2_f[i + 1] : g.ir2_c[i + 1];
+    const R hlo = L == FT ? g.tf_lo[j + 1] : g.tc_lo[j + 1];
+    const R hup = L == FT ? g.tf_up[j + 1] : g.tc_up[j + 1];
+    const R is2 = L == FT ? g.is2_f[j + 1] : g.is2_c[j + 1];
+    const R x0 = n.x0;
+    const R lt = hup * (n.xjp - x0) - hlo * (x0 - n.xjm);
+    const R lp = n.xkp - R(2) * x0 + n.xkm;
+    Rv += nu * ((g.r12 * ir2 - R(1)) * lt + (ir2 * is2 * g.idph2 - g.cphat) * lp);
+    Rv += S;
+    // T's deviation storage: the advection of the reference profile
+    // (its diffusion vanishes: Tref is the discrete conductive state)
+    if (L == CC && g.tdev) Rv -= ar * g.dtref[i + 1];
+    Rv -= n.dk * g.inv_tau;
+    w.bm = w.b0;
+    w.b0 = w.bp;
+    return g.tau * Rv;
+}
+
 template <typename R>
 struct ResArgs { Dims d; Geo<R> g; State<R> s; RhsIn<R> in; R *out; int jfast; };
+
+// the arrays a residual reads, as 32-bit-indexed views
+template <typename R> struct ResSrc {
+    FV<R> pn, pk, ps, fin, wr, wt, wp, un0, uk0, un1, uk1, us1, us2, Tn, Tk;
+    FV<double> psn, p1n, p1k;
+    int sys;
+    __device__ __forceinline__ explicit ResSrc(const ResArgs<R> &a)
+        : pn(a.in.pn), pk(a.in.pk), ps(a.in.ps), fin(a.in.f), wr(a.s.us[1][0]), wt(a.s.us[1][1]),
+          wp(a.s.us[1][2]), un0(a.in.un[0]), uk0(a.in.uk[0]), un1(a.in.un[1]), uk1(a.in.uk[1]),
+          us1(a.in.us[1]), us2(a.in.us[2]), Tn(a.in.Tn), Tk(a.in.Tk), psn(a.in.psn), p1n(a.in.p1n),
+          p1k(a.in.p1k), sys(a.in.sys)
+    {
+    }
+    __device__ __forceinline__ R bar(uint32_t q) const { return R(0.5) * (pn[q] + pk[q]); }
+    __device__ __forceinline__ double ptl(uint32_t q) const
+    {
+        return sys == 1 ? psn[q] : psn[q] + 0.5 * (p1k[q] - p1n[q]);
+    }
+    // the radial windows at the column's first point (q = point i0)
+    template <int L> __device__ __forceinline__ void prime(const Geo<R> &g, int i0, uint32_t q, uint32_t sI,
+                                                           uint32_t sJ, Col<R> &w) const
+    {
+        w.bm = bar(q - sI);
+        w.b0 = bar(q);
+        // windows whose lower radial point is i-1 (FR) are primed with i-1
+        if (L == FR) {
+            w.a0 = wt[q - sI]; w.a1 = wt[q - sI + sJ];       // w_t at (i-1, j), (i-1, j+1)
+            w.c0 = wp[q - sI]; w.c1 = wp[q - sI + 1];        // w_p at (i-1, k), (i-1, k+1)
+            w.e0 = us1[q - sI]; w.e1 = us1[q - sI + sJ];
+            w.f0 = us2[q - sI]; w.f1 = us2[q - sI + 1];
+            w.tg = (double)Tn[q - sI] + (double)Tk[q - sI] + 2.0 * g.tref[i0];
+            w.pm = ptl(q - sI);
+        } else if (L == CC) {
+            w.a0 = wr[q];                                    // w_r at face i
+        } else if (L == FT) {
+            w.a0 = wr[q - sJ]; w.a1 = wr[q];                 // w_r at face i, (j-1) and j
+            w.c0 = un0[q - sJ] + uk0[q - sJ];      // 2 ubar_r at face i, j-1
+            w.c1 = un0[q] + uk0[q];                // 2 ubar_r at face i, j
+        } else {
+            w.a0 = wr[q - 1]; w.a1 = wr[q];                  // w_r at face i, (k-1) and k
+            w.c0 = un0[q - 1] + uk0[q - 1];
+            w.c1 = un0[q] + uk0[q];
+        }
+    }
+    // the values of the point only this column reads
+    template <int L> __device__ __forceinline__ void own(uint32_t q, uint32_t sI, ResNb<R> &n) const
+    {
+        n.bp = bar(q + sI);
+        n.f = fin.p ? fin[q] : R(0);
+        n.dk = pk[q] - pn[q];
+        if (L == CC) n.wr1 = wr[q + sI];
+        if (L == FR) {
+            n.wr0 = wr[q];
+            n.Tn = Tn[q];
+            n.Tk = Tk[q];
+            n.pt = ptl(q);
+        }
+        if (L == FT) n.t0 = wt[q];
+        if (L == FP) n.p0 = wp[q];
+    }
+    // the neighbour values, from memory
+    template <int L> __device__ __forceinline__ void nbrs(uint32_t q, uint32_t sI, uint32_t sJ, ResNb<R> &n) const
+    {
+        n.bjm = bar(q - sJ); n.bjp = bar(q + sJ); n.bkm = bar(q - 1); n.bkp = bar(q + 1);
+        n.x0 = ps[q]; n.xjm = ps[q - sJ]; n.xjp = ps[q + sJ]; n.xkm = ps[q - 1]; n.xkp = ps[q + 1];
+        if (L == CC) {
+            n.t0 = wt[q]; n.t1 = wt[q + sJ];
+            n.p0 = wp[q]; n.p1 = wp[q + 1];
+        } else if (L == FR) {
+            n.t0 = wt[q]; n.t1 = wt[q + sJ]; n.p0 = wp[q]; n.p1 = wp[q + 1];
+            n.e0 = us1[q]; n.e1 = us1[q + sJ]; n.f0 = us2[q]; n.f1 = us2[q + 1];
+        } else if (L == FT) {
+            n.r0 = wr[q - sJ + sI]; n.r1 = wr[q + sI];
+            n.p0 = wp[q - sJ]; n.p1 = wp[q - sJ + 1]; n.p2 = wp[q]; n.p3 = wp[q + 1];
+            n.u0 = un0[q - sJ + sI] + uk0[q - sJ + sI];
+            n.u1 = un0[q + sI] + uk0[q + sI];
+            n.s0 = us2[q + 1]; n.s1 = us2[q]; n.s2 = us2[q - sJ + 1]; n.s3 = us2[q - sJ];
+            n.pt = ptl(q); n.pm = ptl(q - sJ);
+        } else {
+            n.r0 = wr[q - 1 + sI]; n.r1 = wr[q + sI];
+            n.t0 = wt[q - 1]; n.t1 = wt[q - 1 + sJ]; n.t2 = wt[q]; n.t3 = wt[q + sJ];
+            n.u0 = un0[q - 1 + sI] + uk0[q - 1 + sI];
+            n.u1 = un0[q + sI] + uk0[q + sI];
+            n.h0 = un1[q] + uk1[q]; n.h1 = un1[q + sJ] + uk1[q + sJ];
+            n.h2 = un1[q - 1] + uk1[q - 1]; n.h3 = un1[q - 1 + sJ] + uk1[q - 1 + sJ];
+            n.pt = ptl(q); n.pm = ptl(q - 1);
+        }
+    }
+};
+
 template <typename R, int L> struct KResidual {
     using Args = ResArgs<R>;
     static constexpr int bounds = 256;
@@ -739,156 +970,246 @@ template <typename R, int L> struct KResidual {
     {
         const Dims &d = a.d;
         const Geo<R> &g = a.g;
-        const State<R> &s = a.s;
-        const RhsIn<R> &in = a.in;
-        R *out = a.out;
-        const int jfast = a.jfast;
-
-    unsigned bx, by;
-    bx = blk.x;
-    by = blk.y;
-    const int p = d.p0 + (int)by;
-    const int j0 = ulo<L>(1), k0 = ulo<L>(2), i0 = ulo<L>(0);
-    const int nj = d.nt - j0;
-    int j, k;
-    if (!col_of_t(bx, nj, d.np, j0, k0, jfast, j, k)) return;
-    // 32-bit element indices (each field is below 4 GiB: checked on the host)
-    const uint32_t sI = (uint32_t)d.sI, sJ = (uint32_t)d.sJ;
-    const R nu = L == CC ? R(1) : g.pr;
-    const FV<R> pn(in.pn), pk(in.pk), ps(in.ps), fin(in.f);
-    const FV<R> wr(s.us[1][0]), wt(s.us[1][1]), wp(s.us[1][2]);
-    const FV<R> un0(in.un[0]), uk0(in.uk[0]), un1(in.un[1]), uk1(in.uk[1]);
-    const FV<R> us1(in.us[1]), us2(in.us[2]), Tn(in.Tn), Tk(in.Tk);
-    const FV<double> psn(in.psn), p1n(in.p1n), p1k(in.p1k);
-    auto bar = [&](uint32_t qq) { return R(0.5) * (pn[qq] + pk[qq]); };
-    auto ptl = [&](uint32_t qq) {
-        return in.sys == 1 ? psn[qq] : psn[qq] + 0.5 * (p1k[qq] - p1n[qq]);
-    };
-    uint32_t q = (uint32_t)ix(d, p, i0, j, k);
-    Col<R> w;
-    w.bm = bar(q - sI);
-    w.b0 = bar(q);
-    // windows whose lower radial point is i-1 (FR) are primed with i-1
-    if (L == FR) {
-        w.a0 = wt[q - sI]; w.a1 = wt[q - sI + sJ];       // w_t at (i-1, j), (i-1, j+1)
-        w.c0 = wp[q - sI]; w.c1 = wp[q - sI + 1];        // w_p at (i-1, k), (i-1, k+1)
-        w.e0 = us1[q - sI]; w.e1 = us1[q - sI + sJ];
-        w.f0 = us2[q - sI]; w.f1 = us2[q - sI + 1];
-        w.tg = (double)Tn[q - sI] + (double)Tk[q - sI] + 2.0 * g.tref[i0];
-        w.pm = ptl(q - sI);
-    } else if (L == CC) {
-        w.a0 = wr[q];                                    // w_r at face i
-    } else if (L == FT) {
-        w.a0 = wr[q - sJ]; w.a1 = wr[q];                 // w_r at face i, (j-1) and j
-        w.c0 = un0[q - sJ] + uk0[q - sJ];      // 2 ubar_r at face i, j-1
-        w.c1 = un0[q] + uk0[q];                // 2 ubar_r at face i, j
-    } else {
-        w.a0 = wr[q - 1]; w.a1 = wr[q];                  // w_r at face i, (k-1) and k
-        w.c0 = un0[q - 1] + uk0[q - 1];
-        w.c1 = un0[q] + uk0[q];
-    }
-    for (int i = i0; i < d.nr; i++, q += sI) {
-        w.bp = bar(q + sI);
-        R ar, at, ap, S = fin.p ? fin[q] : R(0);
-        if (L == CC) {
-            const R wr1 = wr[q + sI];
-            ar = R(0.5) * (w.a0 + wr1);
-            at = R(0.5) * (wt[q] + wt[q + sJ]);
-            ap = R(0.5) * (wp[q] + wp[q + 1]);
-            w.a0 = wr1;
-        } else if (L == FR) {
-            const R t0 = wt[q], t1 = wt[q + sJ], p0 = wp[q], p1 = wp[q + 1];
-            ar = wr[q];
-            at = R(0.25) * ((w.a0 + w.a1) + (t0 + t1));
-            ap = R(0.25) * ((w.c0 + w.c1) + (p0 + p1));
-            const R e0 = us1[q], e1 = us1[q + sJ], f0 = us2[q], f1 = us2[q + 1];
-            // (D12 u_t* + D13 u_p*)/(2 chi)
-            const R dtc = g.ir_c[i + 1] * (g.dt_p[j + 1] * e1 - g.dt_m[j + 1] * e0);
-            const R dtm = g.ir_c[i] * (g.dt_p[j + 1] * w.e1 - g.dt_m[j + 1] * w.e0);
-            const R dpc = g.ir_c[i + 1] * g.dp_c[j + 1] * (f1 - f0);
-            const R dpm = g.ir_c[i] * g.dp_c[j + 1] * (w.f1 - w.f0);
-            S += g.ic * g.idr * ((dtc - dtm) + (dpc - dpm));
-            const R vt = R(0.25) * ((w.e0 + w.e1) + (e0 + e1));
-            const R vp = R(0.25) * ((w.f0 + w.f1) + (f0 + f1));
-            S += (at * vt + ap * vp) * g.ir_f[i + 1];
-            // -d_r p~ + Pr Ra T^{n+1/2}: the hydrostatic balance cancels
-            // two large terms, so they are combined in FP64 before rounding
-            const double pt = ptl(q);
-            const double tg = (double)Tn[q] + (double)Tk[q] + 2.0 * g.tref[i + 1];
-            S += (R)(g.prra_d * 0.25 * (w.tg + tg) - (pt - w.pm) * (double)g.idr);
-            w.a0 = t0; w.a1 = t1; w.c0 = p0; w.c1 = p1;
-            w.e0 = e0; w.e1 = e1; w.f0 = f0; w.f1 = f1;
-            w.tg = tg; w.pm = pt;
-        } else if (L == FT) {
-            const R r0 = wr[q - sJ + sI], r1 = wr[q + sI];
-            ar = R(0.25) * ((w.a0 + r0) + (w.a1 + r1));
-            at = wt[q];
-            ap = R(0.25) * ((wp[q - sJ] + wp[q - sJ + 1]) + (wp[q] + wp[q + 1]));
-            const R ir = g.ir_c[i + 1], ir2 = g.ir2_c[i + 1], cot = g.cot_f[j + 1];
-            const R u0 = un0[q - sJ + sI] + uk0[q - sJ + sI];    // 2 ubar_r at (i+1, j-1)
-            const R u1 = un0[q + sI] + uk0[q + sI];              // 2 ubar_r at (i+1, j)
-            // Div_r of ubar at centres (i, j) and (i, j-1), times 2
-            const R dj0 = g.dr_p[i + 1] * u1 - g.dr_m[i + 1] * w.c1;
-            const R dj1 = g.dr_p[i + 1] * u0 - g.dr_m[i + 1] * w.c0;
-            const FV<R> &u2s = us2;
-            const R d23 = g.ir_c[i + 1] * (g.dp_c[j + 1] * (u2s[q + 1] - u2s[q]) -
-                                           g.dp_c[j] * (u2s[q - sJ + 1] - u2s[q - sJ]));
-            S += g.ic * ir * g.idth * (R(0.5) * (dj0 - dj1) + d23);
-            const R dth_ur = R(0.5) * ((R(0.5) * w.c1 - R(0.5) * w.c0) + (R(0.5) * u1 - R(0.5) * u0)) * g.idth;
-            const R fp2 = g.rf[i + 2] * g.rf[i + 2], fm2 = g.rf[i + 1] * g.rf[i + 1];
-            const R dr_r2ur = R(0.5) * ((fp2 * R(0.5) * u0 - fm2 * R(0.5) * w.c0) +
-                                        (fp2 * R(0.5) * u1 - fm2 * R(0.5) * w.c1)) * g.idr;
-            S += g.pr * R(2) * ir2 * (dth_ur + cot * ir * dr_r2ur);
-            const R vp = R(0.25) * ((u2s[q - sJ] + u2s[q - sJ + 1]) + (u2s[q] + u2s[q + 1]));
-            S += ap * vp * cot * ir;
-            S -= (R)((ptl(q) - ptl(q - sJ)) * (double)ir * (double)g.idth);
-            w.a0 = r0; w.a1 = r1; w.c0 = u0; w.c1 = u1;
-        } else {
-            const R r0 = wr[q - 1 + sI], r1 = wr[q + sI];
-            ar = R(0.25) * ((w.a0 + r0) + (w.a1 + r1));
-            at = R(0.25) * ((wt[q - 1] + wt[q - 1 + sJ]) + (wt[q] + wt[q + sJ]));
-            ap = wp[q];
-            const R ir = g.ir_c[i + 1], ir2 = g.ir2_c[i + 1], isn = g.is_c[j + 1], cot = g.cot_c[j + 1];
-            const R igg = ir * g.dp_c[j + 1];
-            const R u0 = un0[q - 1 + sI] + uk0[q - 1 + sI];      // 2 ubar_r at (i+1, k-1)
-            const R u1 = un0[q + sI] + uk0[q + sI];              // 2 ubar_r at (i+1, k)
-            const R a0 = g.dr_p[i + 1] * u1 - g.dr_m[i + 1] * w.c1;
-            const R a1 = g.dr_p[i + 1] * u0 - g.dr_m[i + 1] * w.c0;
-            const FV<R> &tn = un1, &tk = uk1;
-            const R th00 = tn[q] + tk[q], th01 = tn[q + sJ] + tk[q + sJ];
-            const R thm0 = tn[q - 1] + tk[q - 1], thm1 = tn[q - 1 + sJ] + tk[q - 1 + sJ];
-            const R b0 = ir * (g.dt_p[j + 1] * th01 - g.dt_m[j + 1] * th00);
-            const R b1 = ir * (g.dt_p[j + 1] * thm1 - g.dt_m[j + 1] * thm0);
-            S += g.ic * igg * R(0.5) * ((a0 - a1) + (b0 - b1));
-            const R dph_ur = R(0.5) * ((R(0.5) * w.c1 - R(0.5) * w.c0) + (R(0.5) * u1 - R(0.5) * u0)) * g.idph;
-            const R dph_ut = R(0.5) * ((R(0.5) * th00 - R(0.5) * thm0) + (R(0.5) * th01 - R(0.5) * thm1)) * g.idph;
-            S += g.pr * R(2) * ir2 * isn * (dph_ur + cot * dph_ut);
-            S -= (R)((ptl(q) - ptl(q - 1)) * (double)igg);
-            w.a0 = r0; w.a1 = r1; w.c0 = u0; w.c1 = u1;
+        const int p = d.p0 + (int)blk.y;
+        const int j0 = ulo<L>(1), k0 = ulo<L>(2), i0 = ulo<L>(0);
+        const int nj = d.nt - j0;
+        int j, k;
+        if (!col_of_t(blk.x, nj, d.np, j0, k0, a.jfast, j, k)) return;
+        // 32-bit element indices (each field is below 4 GiB: checked on the host)
+        const uint32_t sI = (uint32_t)d.sI, sJ = (uint32_t)d.sJ;
+        const ResSrc<R> src(a);
+        uint32_t q = (uint32_t)ix(d, p, i0, j, k);
+        Col<R> w;
+        src.template prime<L>(g, i0, q, sI, sJ, w);
+        for (int i = i0; i < d.nr; i++, q += sI) {
+            ResNb<R> n;
+            src.template own<L>(q, sI, n);
+            src.template nbrs<L>(q, sI, sJ, n);
+            st(a.out, q, res_point<R, L>(g, i, j, n, w));
         }
-        const Tri<R> c0 = coef<L, 0>(g, i, j, ar, at, ap, nu);
-        const Tri<R> c1 = coef<L, 1>(g, i, j, ar, at, ap, nu);
-        const Tri<R> c2 = coef<L, 2>(g, i, j, ar, at, ap, nu);
-        R Rv = c0.lo * w.bm + c0.di * w.b0 + c0.up * w.bp;
-        Rv += c1.lo * bar(q - sJ) + c1.di * w.b0 + c1.up * bar(q + sJ);
-        Rv += c2.lo * bar(q - 1) + c2.di * w.b0 + c2.up * bar(q + 1);
-        const R ir2 = L == FR ? g.ir2_f[i + 1] : g.ir2_c[i + 1];
-        const R hlo = L == FT ? g.tf_lo[j + 1] : g.tc_lo[j + 1];
-        const R hup = L == FT ? g.tf_up[j + 1] : g.tc_up[j + 1];
-        const R is2 = L == FT ? g.is2_f[j + 1] : g.is2_c[j + 1];
-        const R x0 = ps[q];
-        const R lt = hup * (ps[q + sJ] - x0) - hlo * (x0 - ps[q - sJ]);
-        const R lp = ps[q + 1] - R(2) * x0 + ps[q - 1];
-        Rv += nu * ((g.r12 * ir2 - R(1)) * lt + (ir2 * is2 * g.idph2 - g.cphat) * lp);
-        Rv += S;
-        // T's deviation storage: the advection of the reference profile
-        // (its diffusion vanishes: Tref is the discrete conductive state)
-        if (L == CC && g.tdev) Rv -= ar * g.dtref[i + 1];
-        Rv -= (pk[q] - pn[q]) * g.inv_tau;
-        st(out, q, g.tau * Rv);
-        w.bm = w.b0;
-        w.b0 = w.bp;
     }
+};
+
+// Residual with the theta and phi neighbours staged in LDS.  A block of
+// 64 x CJ threads owns a 64 (k) x CJ (j) tile of columns and walks i with
+// them.  At each radial point every quantity read at a neighbour (psibar,
+// psi* and the location's velocity and pressure terms) is written into an
+// LDS plane covering the tile and the halo cells read from outside it; each
+// thread writes its own cell, and the halo cells are dealt one per thread.
+// The plane values of the next point are loaded while the current point is
+// computed.  So a value is fetched from memory once per tile rather than
+// once per column that reads it.  Two barriers per point: before the planes
+// are overwritten and before they are read.
+enum : int { QBAR, QPS, QWR, QWT, QWP, QUS1, QUS2, QUBR, QTH };
+// quantity, radial offset (0: at the point, 1: at i+1), halo sides held
+// (jm/jp: the rows j0-1 / j0+CJ over k0-1 .. k0+64; km/kp: the columns
+// k0-1 / k0+64 over the tile's rows)
+struct PlaneSpec { int q, off, jm, jp, km, kp; };
+template <int L> __host__ __device__ constexpr int res_nplanes() { return L == CC ? 4 : 6; }
+template <int L> __host__ __device__ constexpr PlaneSpec res_plane(int p)
+{
+    if (p == 0) return PlaneSpec{QBAR, 0, 1, 1, 1, 1};
+    if (p == 1) return PlaneSpec{QPS, 0, 1, 1, 1, 1};
+    if (L == CC) return p == 2 ? PlaneSpec{QWT, 0, 0, 1, 0, 0} : PlaneSpec{QWP, 0, 0, 0, 0, 1};
+    if (L == FR)
+        return p == 2 ? PlaneSpec{QWT, 0, 0, 1, 0, 0} : p == 3 ? PlaneSpec{QWP, 0, 0, 0, 0, 1}
+             : p == 4 ? PlaneSpec{QUS1, 0, 0, 1, 0, 0} : PlaneSpec{QUS2, 0, 0, 0, 0, 1};
+    if (L == FT)
+        return p == 2 ? PlaneSpec{QWR, 1, 1, 0, 0, 0} : p == 3 ? PlaneSpec{QWP, 0, 1, 0, 0, 1}
+             : p == 4 ? PlaneSpec{QUBR, 1, 1, 0, 0, 0} : PlaneSpec{QUS2, 0, 1, 0, 0, 1};
+    return p == 2 ? PlaneSpec{QWR, 1, 0, 0, 1, 0} : p == 3 ? PlaneSpec{QWT, 0, 0, 1, 1, 0}
+         : p == 4 ? PlaneSpec{QUBR, 1, 0, 0, 1, 0} : PlaneSpec{QTH, 0, 0, 1, 1, 0};
+}
+// the FP64 p~ plane (FT: its row j0-1; FP: its column k0-1)
+template <int L> __host__ __device__ constexpr PlaneSpec res_pplane()
+{
+    return L == FT ? PlaneSpec{0, 0, 1, 0, 0, 0} : PlaneSpec{0, 0, 0, 0, 1, 0};
+}
+
+template <typename R>
+__device__ __forceinline__ R plane_val(const ResSrc<R> &s, int qid, uint32_t q)
+{
+    switch (qid) {
+    case QBAR: return s.bar(q);
+    case QPS: return s.ps[q];
+    case QWR: return s.wr[q];
+    case QWT: return s.wt[q];
+    case QWP: return s.wp[q];
+    case QUS1: return s.us1[q];
+    case QUS2: return s.us2[q];
+    case QUBR: return s.un0[q] + s.uk0[q];
+    default: return s.un1[q] + s.uk1[q];
+    }
+}
+
+// halo cell h of a plane (rows first, then columns); false if h is past
+// the plane's halo
+template <int CJ>
+__device__ __forceinline__ bool halo_cell(const PlaneSpec &s, int h, int &jj, int &kk)
+{
+    if (s.jm) { if (h < 66) { jj = -1; kk = h - 1; return true; } h -= 66; }
+    if (s.jp) { if (h < 66) { jj = CJ; kk = h - 1; return true; } h -= 66; }
+    if (s.km) { if (h < CJ) { jj = h; kk = -1; return true; } h -= CJ; }
+    if (s.kp) { if (h < CJ) { jj = h; kk = 64; return true; } }
+    return false;
+}
+
+template <typename R, int L, int CJ> struct KResidualLds {
+    using Args = ResArgs<R>;
+    static constexpr int bounds = 64 * CJ;
+    // register budget: 4 waves per SIMD (128 VGPRs) where that holds the
+    // prefetched planes without spilling, else 3 (the FP64 velocities)
+    static constexpr int wpe = (L == CC || sizeof(R) == 4) ? 4 : 3;
+    static constexpr bool xcd = true;
+    static constexpr int W = 66, PL = (CJ + 2) * W, NT = 64 * CJ;
+    static constexpr int NPL = res_nplanes<L>();
+    static constexpr bool HASP = L == FT || L == FP;
+    // halo groups: psibar and psi* (all four sides); CC/FR: j+1 and k+1
+    // planes; FT/FP: the one-sided planes with p~, and the two-sided ones
+    // (plane NPL: p~)
+    static constexpr int NG = 3;
+    static __host__ __device__ constexpr int grp(int c) { return c < 2 ? 0 : (c == NPL || c % 2 == 0) ? 1 : 2; }
+    static __host__ __device__ constexpr int group_head(int c) { return c == 0 ? 0 : c == 1 ? 2 : 3; }
+    static __host__ __device__ constexpr int halo_count(const PlaneSpec &s)
+    {
+        return s.jm * W + s.jp * W + s.km * CJ + s.kp * CJ;
+    }
+    static __device__ __forceinline__ void body(const Args &a, const Blk &blk)
+    {
+        __shared__ R pl[NPL][PL];
+        __shared__ double pd[HASP ? PL : 1];
+        const Dims &d = a.d;
+        const Geo<R> &g = a.g;
+        const int p = d.p0 + (int)blk.y;
+        const int j0 = ulo<L>(1), k0 = ulo<L>(2), i0 = ulo<L>(0);
+        const int nj = d.nt - j0;
+        const unsigned ntk = (unsigned)((d.np + 63) / 64), ntj = (unsigned)((nj + CJ - 1) / CJ);
+        const int tk = (int)(a.jfast ? blk.x / ntj : blk.x % ntk);
+        const int tj = (int)(a.jfast ? blk.x % ntj : blk.x / ntk);
+        const int kt0 = tk * 64, jt0 = j0 + tj * CJ;
+        const int x = (int)threadIdx.x, y = (int)threadIdx.y, t = x + 64 * y;
+        const int j = jt0 + y, k = kt0 + x;
+        const bool active = j < d.nt && k >= k0 && k < d.np;
+        const uint32_t sI = (uint32_t)d.sI, sJ = (uint32_t)d.sJ;
+        const ResSrc<R> src(a);
+        // own cell (loads clamped to the ghost row / column past the tile)
+        const uint32_t ql = (uint32_t)ix(d, p, i0, j < d.nt ? j : d.nt, k < d.np ? k : d.np);
+        // this thread's halo cell of each group of planes with the same
+        // halo sides (if any); the groups' cells are dealt from staggered
+        // threads, so the halo loads spread over the waves
+        uint32_t qh[NG];
+        int hl[NG];
+        int base = 0;
+#pragma unroll
+        for (int c = 0; c < NG; c++) {
+            hl[c] = -1;
+            qh[c] = ql;
+            const PlaneSpec s = res_plane<L>(group_head(c));
+            const int h = (t + NT - base % NT) % NT;
+            base += halo_count(s);
+            int jj, kk;
+            if (halo_cell<CJ>(s, h, jj, kk)) {
+                const int jg = min(jt0 + jj, d.nt), kg = min(kt0 + kk, d.np);
+                hl[c] = (jj + 1) * W + (kk + 1);
+                qh[c] = (uint32_t)ix(d, p, i0, jg, kg);
+            }
+        }
+        // values of the next point: the planes (own cell and halo cell), the
+        // own psi^k - psi^n and forcing, and the location's own-cell terms
+        R ov[NPL], hv[NPL];
+        double pov = 0.0, phv = 0.0;
+        R dkn = R(0), fn = R(0), wrn = R(0), owa = R(0), Tnn = R(0), Tkn = R(0);
+        double ptn = 0.0;
+        // full: everything of point lev; else only psibar and psi^k - psi^n
+        // of the own cell (the last point's psibar at i+1)
+        auto fetch = [&](uint32_t lev, bool full) {
+            const R pkv = src.pk[ql + lev], pnv = src.pn[ql + lev];
+            ov[0] = R(0.5) * (pnv + pkv);
+            dkn = pkv - pnv;
+            if (!full) return;
+            hv[0] = hl[0] >= 0 ? src.bar(qh[0] + lev) : R(0);
+#pragma unroll
+            for (int c = 1; c < NPL; c++) {
+                const PlaneSpec s = res_plane<L>(c);
+                const uint32_t o = lev + (uint32_t)s.off * sI;
+                ov[c] = plane_val<R>(src, s.q, ql + o);
+                hv[c] = hl[grp(c)] >= 0 ? plane_val<R>(src, s.q, qh[grp(c)] + o) : R(0);
+            }
+            if (HASP) {
+                pov = src.ptl(ql + lev);
+                phv = hl[grp(NPL)] >= 0 ? src.ptl(qh[grp(NPL)] + lev) : 0.0;
+            }
+            fn = src.fin.p ? src.fin[ql + lev] : R(0);
+            if (L == CC) wrn = src.wr[ql + lev + sI];
+            if (L == FR) {
+                wrn = src.wr[ql + lev];
+                Tnn = src.Tn[ql + lev];
+                Tkn = src.Tk[ql + lev];
+                ptn = src.ptl(ql + lev);
+            }
+            if (L == FT) owa = src.wt[ql + lev];
+            if (L == FP) owa = src.wp[ql + lev];
+        };
+        Col<R> w;
+        uint32_t q = ql;
+        if (active) src.template prime<L>(g, i0, q, sI, sJ, w);
+        uint32_t lev = 0;                    // (i - i0) sI
+        fetch(lev, true);
+        const int me = (y + 1) * W + (x + 1);
+        for (int i = i0; i < d.nr; i++, q += sI) {
+            if (i > i0) __syncthreads();
+#pragma unroll
+            for (int c = 0; c < NPL; c++) {
+                pl[c][me] = ov[c];
+                if (hl[grp(c)] >= 0) pl[c][hl[grp(c)]] = hv[c];
+            }
+            if (HASP) {
+                pd[me] = pov;
+                if (hl[grp(NPL)] >= 0) pd[hl[grp(NPL)]] = phv;
+            }
+            ResNb<R> n;
+            n.dk = dkn;
+            n.f = fn;
+            if (L == CC) n.wr1 = wrn;
+            if (L == FR) {
+                n.wr0 = wrn;
+                n.Tn = Tnn;
+                n.Tk = Tkn;
+                n.pt = ptn;
+            }
+            if (L == FT) n.t0 = owa;
+            if (L == FP) n.p0 = owa;
+            lev += sI;
+            fetch(lev, i + 1 < d.nr);
+            n.bp = ov[0];
+            __syncthreads();
+            if (active) {
+                auto P = [&](int c, int dj, int dk) { return pl[c][me + dj * W + dk]; };
+                n.bjm = P(0, -1, 0); n.bjp = P(0, 1, 0); n.bkm = P(0, 0, -1); n.bkp = P(0, 0, 1);
+                n.x0 = P(1, 0, 0); n.xjm = P(1, -1, 0); n.xjp = P(1, 1, 0);
+                n.xkm = P(1, 0, -1); n.xkp = P(1, 0, 1);
+                if (L == CC) {
+                    n.t0 = P(2, 0, 0); n.t1 = P(2, 1, 0);
+                    n.p0 = P(3, 0, 0); n.p1 = P(3, 0, 1);
+                } else if (L == FR) {
+                    n.t0 = P(2, 0, 0); n.t1 = P(2, 1, 0); n.p0 = P(3, 0, 0); n.p1 = P(3, 0, 1);
+                    n.e0 = P(4, 0, 0); n.e1 = P(4, 1, 0); n.f0 = P(5, 0, 0); n.f1 = P(5, 0, 1);
+                } else if (L == FT) {
+                    n.r0 = P(2, -1, 0); n.r1 = P(2, 0, 0);
+                    n.p0 = P(3, -1, 0); n.p1 = P(3, -1, 1); n.p2 = P(3, 0, 0); n.p3 = P(3, 0, 1);
+                    n.u0 = P(4, -1, 0); n.u1 = P(4, 0, 0);
+                    n.s0 = P(5, 0, 1); n.s1 = P(5, 0, 0); n.s2 = P(5, -1, 1); n.s3 = P(5, -1, 0);
+                    n.pt = pd[me]; n.pm = pd[me - W];
+                } else {
+                    n.r0 = P(2, 0, -1); n.r1 = P(2, 0, 0);
+                    n.t0 = P(3, 0, -1); n.t1 = P(3, 1, -1); n.t2 = P(3, 0, 0); n.t3 = P(3, 1, 0);
+                    n.u0 = P(4, 0, -1); n.u1 = P(4, 0, 0);
+                    n.h0 = P(5, 0, 0); n.h1 = P(5, 1, 0); n.h2 = P(5, 0, -1); n.h3 = P(5, 1, -1);
+                    n.pt = pd[me]; n.pm = pd[me - 1];
+                }
+                st(a.out, q, res_point<R, L>(g, i, j, n, w));
+            }
+        }
     }
 };
 
@@ -1888,6 +2209,14 @@ void Ops<R>::sweep(const Dims &d, const Geo<R> &g, const Geo<double> &gd, const 
 #undef YY_SW
 }
 
+template <typename R, int L>
+void launch_res_lds(int cj, dim3 gr, dim3 bl, hipStream_t st, const ResArgs<R> &ra)
+{
+    if (cj == 4) launch<KResidualLds<R, L, 4>>(gr, bl, 0, st, ra);
+    else if (cj == 8) launch<KResidualLds<R, L, 8>>(gr, bl, 0, st, ra);
+    else launch<KResidualLds<R, L, 16>>(gr, bl, 0, st, ra);
+}
+
 template <typename R>
 void Ops<R>::residual(const Dims &d, const Geo<R> &g, const State<R> &s, int field, R *out,
                       hipStream_t st)
@@ -1918,6 +2247,13 @@ void Ops<R>::residual(const Dims &d, const Geo<R> &g, const State<R> &s, int fie
     const dim3 gr((unsigned)col_blocks_t(d.nt - j0, d.np, t), d.npatch), bl(t.ck, t.cj);
     const int jf = t.jfast;
     const ResArgs<R> ra{d, g, s, in, out, jf};
+    if (t.lds) {
+        if (L == CC) launch_res_lds<R, CC>(t.cj, gr, bl, st, ra);
+        else if (L == FR) launch_res_lds<R, FR>(t.cj, gr, bl, st, ra);
+        else if (L == FT) launch_res_lds<R, FT>(t.cj, gr, bl, st, ra);
+        else launch_res_lds<R, FP>(t.cj, gr, bl, st, ra);
+        return;
+    }
     if (L == CC) launch<KResidual<R, CC>>(gr, bl, 0, st, ra);
     else if (L == FR) launch<KResidual<R, FR>>(gr, bl, 0, st, ra);
     else if (L == FT) launch<KResidual<R, FT>>(gr, bl, 0, st, ra);

@@ -253,7 +253,8 @@ def test_residual_parity(oracle_lib, yy, field):
     assert _rel(got[m], ref[m]) <= TOL
 
 
-RES_TILES = ["64x4k", "64x4j", "128x2j", "256x1j", "128x2k", "32x8j", "32x8k", "16x16k"]
+RES_TILES = ["64x4k", "64x4j", "128x2j", "256x1j", "128x2k", "32x8j", "32x8k", "16x16k",
+             "lds64x4k", "lds64x8k", "lds64x8j", "lds64x16k"]
 
 
 @pytest.mark.parametrize("tile", RES_TILES)
@@ -276,6 +277,37 @@ def test_residual_parity_every_tile(oracle_lib, yy, tile):
         got = g.from_internal(out).cpu().numpy()
         m = _unknown_mask(o.padded_shape(), field)
         assert _rel(got[m], ref[m]) <= TOL, (tile, I.FIELD_NAMES[field])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_residual_lds_tiles_bitwise(yy, prec):
+    """The LDS-staged residual tiles feed the same point arithmetic with the
+    same values as the memory-read tiles, so every unknown's residual is
+    bitwise equal, on a grid (9x44x170) with ragged tiles in j and k, for
+    both velocity systems (p~ of system 2 reads p1 too)."""
+    print(f"case: residual LDS tiles bitwise, prec {prec}", flush=True)
+    nr, nt, np_ = 9, 44, 170
+    g = yy.Shell(nr, nt, np_, prec=prec)
+    g.set_params(pr=0.8, ra=50.0, dt=0.02, chi=0.9, t_inner=1.0, t_outer=0.0)
+    rng = np.random.default_rng(301)
+    shape = (2, nr + 2, nt + 2, np_ + 2)
+    for f in range(9):
+        for lev in (0, 1):
+            if f in (I.P1, I.P2) and lev == 1:
+                continue
+            g.set_field(f, lev, rng.uniform(-1, 1, shape), layout=1)
+    g.extrapolate()
+    outs = {}
+    for tile in ["64x4k", "lds64x4k", "lds64x8k", "lds64x8j", "lds64x16k"]:
+        g.set_tuning('{"res.T":"%s","res.u_r":"%s","res.u_t":"%s","res.u_p":"%s"}' % ((tile,) * 4))
+        for field in (I.T, I.U1R, I.U1T, I.U1P, I.U2R, I.U2T, I.U2P):
+            out = g.internal_tensor()
+            out.zero_()
+            g.residual(field, out)
+            outs[(tile, field)] = out.cpu()
+    for tile in ["lds64x4k", "lds64x8k", "lds64x8j", "lds64x16k"]:
+        for field in (I.T, I.U1R, I.U1T, I.U1P, I.U2R, I.U2T, I.U2P):
+            assert torch.equal(outs[(tile, field)], outs[("64x4k", field)]), (tile, I.FIELD_NAMES[field])
 
 
 def _mms_pair(oracle_lib, yy, nr, nt, np_, dt, prec=0, pr=1.0, ra=1e3, mode=0):
