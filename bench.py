@@ -69,6 +69,125 @@ def class_words():
     return W
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_1905_02300_amd", "csrc", "yy_kernels.hip")
+# residual class -> (unknown's tuning key, location index in the kernel name)
+RES_CLASSES = {"residual_T": ("T", 0), "residual_ur": ("u_r", 1), "residual_ut": ("u_t", 2),
+               "residual_up": ("u_p", 3)}
+
+
+def kernel_source_sha():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def stored_traffic(cls, prec, tiles):
+    """HBM bytes per launch of a kernel class from profiles/, or None when
+    the record is missing or stale (taken with other kernel sources or
+    another tile than this run's)"""
+    if cls not in RES_CLASSES or not tiles:
+        return None
+    tile = json.loads(tiles).get("res." + RES_CLASSES[cls][0])
+    tfile = os.path.join(ROOT, "profiles", "traffic_%s_%s_%s.json" % (cls, prec, tile))
+    if not os.path.exists(tfile):
+        return None
+    with open(tfile) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != kernel_source_sha() or rec.get("tile") != tile:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def copy_ceiling(gib=2, reps=20):
+    """HBM rate of the library's plain streaming copy (every word read once
+    and written once) over 2 GiB buffers: the practical ceiling of the
+    step's streaming kernels, read + write bytes per second"""
+    import torch
+    from paper_1905_02300_amd import yy
+    n = gib * (1 << 30) // 8
+    a = torch.rand(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        yy.stream_copy(b, a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        yy.stream_copy(b, a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ok = bool(torch.equal(a, b))
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes": 2 * n * 8, "ms": ms, "gbs": 2 * n * 8 / ms / 1e6, "copy_exact": ok}
+
+
+def traffic_summary(args):
+    """Per-launch HBM bytes of the residual kernels of the timed step, from
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the
+    counter reads for the step-start kernel, which streams 16 padded arrays
+    in and 16 out with no reuse."""
+    import re
+    import sqlite3
+    nr, nt, np_ = (int(v) for v in args.grid.split(","))
+    wb = 8 if args.prec == "fp64" else 4
+    pitch = -(-(np_ + 1 + 128 // wb) // (128 // wb)) * (128 // wb)
+    # FP64: every array in compute precision; the step start reads 14 + 2
+    # (p1, p2 in FP64) arrays and writes as many
+    arr = 2 * (nr + 2) * (nt + 2) * pitch
+    stream = 14 * arr * wb + 2 * arr * 8
+
+    def rows(db, counter):
+        cur = sqlite3.connect(db).cursor()
+        return list(cur.execute("select dispatch_id, name, counter_value from pmc_events "
+                                "where counter_name = ? order by dispatch_id", (counter,)))
+    fetch, write = rows(args.traffic[0], "FETCH_SIZE"), rows(args.traffic[1], "WRITE_SIZE")
+    rtype = "double" if args.prec == "fp64" else "float"
+
+    def last(rs, pat, n):
+        sel = [r for r in rs if re.search(pat, r[1])]
+        return sel[-n:]
+    cal_f = last(fetch, r"KExtrapCopy<%s>" % rtype, 1)
+    cal_w = last(write, r"KExtrapCopy<%s>" % rtype, 1)
+    ff = stream / (cal_f[0][2] * 1024.0)
+    fw = stream / (cal_w[0][2] * 1024.0)
+    W = class_words()
+    tiles = json.loads(args.tiles) if args.tiles else {}
+    sha = kernel_source_sha()
+    cells = 2 * nr * nt * np_
+    for cls, (key, L) in RES_CLASSES.items():
+        n = 3 if L == 0 else 6
+        pat = r"KResidual(Lds)?<%s, %d[,>]" % (rtype, L)
+        f, w = last(fetch, pat, n), last(write, pat, n)
+        names = sorted({r[1].split("(")[0] for r in f})
+        fb = sum(r[2] for r in f) / len(f) * 1024.0 * ff
+        wbytes = sum(r[2] for r in w) / len(w) * 1024.0 * fw
+        r, dw = W[cls]
+        alg = cells * (r * wb + dw * 8)
+        rec = {"class": cls, "kernel": names, "tile": tiles.get("res." + key),
+               "workload": f"{args.prec.upper()} 2x{nr}x{nt}x{np_}, K=3 (the timed step's launches averaged)",
+               "bytes_per_launch": fb + wbytes, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wbytes,
+               "alg_bytes_per_launch": alg, "ratio_to_algorithmic": (fb + wbytes) / alg, "dispatches": len(f),
+               "fetch_factor": ff, "write_factor": fw,
+               "calibration": "the step-start kernel reads 16 padded arrays (levels n and n-1 of T, u1, u2; "
+                              "p1, p2) and writes 16, %d elements each" % arr,
+               "commands": [
+                   "rocprofv3 --pmc FETCH_SIZE --kernel-trace -d <fetch> -o fetch -- python3 bench.py "
+                   "--steps 1 --warmup 0 --no-cpu --no-line --set-tiles '<tiles>'",
+                   "rocprofv3 --pmc WRITE_SIZE --kernel-trace -d <write> -o write -- python3 bench.py "
+                   "--steps 1 --warmup 0 --no-cpu --no-line --set-tiles '<tiles>'",
+                   "python3 bench.py --traffic <fetch>/fetch_results.db <write>/write_results.db --tiles '<tiles>'"],
+               "source_sha256": sha,
+               "note": "counters in KiB per dispatch, scaled by the factors; FETCH_SIZE counts L2 misses to "
+                       "the fabric, some of which the Infinity Cache serves; stale (ignored by bench.py) once "
+                       "the kernel source or the tile changes"}
+        out = os.path.join(ROOT, "profiles", "traffic_%s_%s_%s.json" % (cls, args.prec, rec["tile"]))
+        with open(out, "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps({cls: {"ratio": rec["ratio_to_algorithmic"], "kernel": names, "tile": rec["tile"]}}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,10 +228,20 @@ def main():
                     help="run the first N steps of the workload (--grid, --prec fp64, autotuned tiles) on "
                          "the GPU and on the oracle and report their difference per field")
     ap.add_argument("--out", default="", help="also write the --parity-oracle record to this file")
+    ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="turn the rocprofv3 databases of two PMC runs of the default workload "
+                         "(FETCH_SIZE, then WRITE_SIZE; --steps 1 --warmup 0 --no-cpu --no-line "
+                         "--set-tiles) into profiles/traffic_<class>_<prec>_<tile>.json for the "
+                         "residual classes")
+    ap.add_argument("--tiles", default="", help="with --traffic: the tiles JSON of the profiled run")
+    ap.add_argument("--set-tiles", default="", help="use these tiles (JSON) instead of the autotuner's")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.traffic:
+        traffic_summary(args)
+        return
     if args.mixed_error:
         mixed_error(args)
         return
@@ -147,7 +276,11 @@ def main():
             sh.set_field(f, 1, st[f])
     del st
     stream = torch.cuda.current_stream()
-    tiles = sh.autotune() if not args.no_tune else None
+    if args.set_tiles:
+        sh.set_tuning(args.set_tiles)
+        tiles = sh.tuning_json()
+    else:
+        tiles = sh.autotune() if not args.no_tune else None
     for _ in range(args.warmup):
         sh.step(K)
     torch.cuda.synchronize()
@@ -181,13 +314,13 @@ def main():
     roofline = {"kernel": dom, "bound": "hbm", "achieved": dk["gbs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": None,
                 "alg_bytes_per_launch": dk["alg_bytes"], "ms_avg": dk["ms_avg"]}
-    tfile = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (dom, args.prec))
-    if os.path.exists(tfile):
-        with open(tfile) as fh:
-            roofline["traffic"] = json.load(fh).get("bytes_per_launch")
+    roofline["traffic"] = stored_traffic(dom, args.prec, tiles)
 
     del sh
     torch.cuda.empty_cache()
+    copy = copy_ceiling()
+    roofline["copy_ceiling_gbs"] = copy["gbs"]
+    roofline["frac_of_copy_ceiling"] = dk["gbs"] / copy["gbs"]
     line = None if args.no_line else line_solve_bench()
 
     cpu = None
@@ -207,6 +340,7 @@ def main():
                    "Pr": pr, "Ra": ra, "dt": dt, "parallelism": "single-gpu"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "hbm_copy": copy,
         "line_solve": line,
         "tiles": tiles,
         "kernels": kernels,

@@ -381,6 +381,16 @@ int yy_ensemble_info(const yy_ensemble *e, int32_t *batched, int64_t *launches_p
 
 int yy_ensemble_destroy(yy_ensemble *e);
 
+/* ---- measurement ---- */
+
+/* Plain streaming copy of `bytes` bytes from device memory src to dst (both
+ * 16-byte aligned, bytes a multiple of 16, non-overlapping) on `stream`:
+ * the HBM rate a kernel that reads and writes every word once reaches, the
+ * practical ceiling of the step's streaming kernels.  Not part of a step.
+ * Errors: YY_ERR_ARG (null, misaligned or bytes not a multiple of 16),
+ * YY_ERR_HIP (launch). */
+int yy_stream_copy(void *dst, const void *src, uint64_t bytes, hipStream_t stream);
+
 /* ---- live per-kernel timing (HIP events on the caller's stream) ---- */
 
 /* Kernel classes timed by the profiler. */

@@ -2093,6 +2093,14 @@ int yy_ensemble_autotune(yy_ensemble *e, char *json_out, int32_t cap, hipStream_
     return YY_OK;
 }
 
+int yy_stream_copy(void *dst, const void *src, uint64_t bytes, hipStream_t stream)
+{
+    if (!dst || !src || bytes % 16 || ((uintptr_t)dst | (uintptr_t)src) % 16) return YY_ERR_ARG;
+    if (bytes == 0) return YY_OK;
+    stream_copy(dst, src, (int64_t)(bytes / 16), stream);
+    return hip_status(hipGetLastError());
+}
+
 int yy_ensemble_info(const yy_ensemble *e, int32_t *batched, int64_t *launches_per_step,
                      int64_t *shell_launches_per_step)
 {

@@ -266,6 +266,7 @@ void reduce_norms(const double *partial, const int *nblocks_dev, double *out, hi
 void pressure_exchange(const Dims &d, double *p, const FillScalar *tab, int ntab, double *tmp,
                        hipStream_t st);
 void zero_doubles(double *p, int64_t n, hipStream_t st);
+void stream_copy(void *dst, const void *src, int64_t words16, hipStream_t st);
 // choose the register-resident partitioned line solver (default) or the
 // per-line Thomas kernel
 void set_partitioned(bool on);

@@ -2451,6 +2451,33 @@ void zero_doubles(double *p, int64_t n, hipStream_t st)
 #endif
 
 // ---------------------------------------------------------------------------
+// plain streaming copy in 16-byte words (the HBM ceiling a streaming kernel
+// reaches on this part: every word read once and written once)
+// ---------------------------------------------------------------------------
+#if !defined(YY_ONLY_FLOAT)
+__global__ void __launch_bounds__(256) k_stream_copy(uint4 *__restrict__ dst, const uint4 *__restrict__ src,
+                                                     int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (; q + 3 * stride < n; q += 4 * stride) {
+        const uint4 a = src[q], b = src[q + stride], c = src[q + 2 * stride], e = src[q + 3 * stride];
+        dst[q] = a;
+        dst[q + stride] = b;
+        dst[q + 2 * stride] = c;
+        dst[q + 3 * stride] = e;
+    }
+    for (; q < n; q += stride) dst[q] = src[q];
+}
+
+void stream_copy(void *dst, const void *src, int64_t words16, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_stream_copy, dim3(256 * 16), dim3(256), 0, st, (uint4 *)dst, (const uint4 *)src,
+                       words16);
+}
+#endif
+
+// ---------------------------------------------------------------------------
 // field I/O: MAC or padded double arrays <-> internal layout
 // ---------------------------------------------------------------------------
 template <typename TT>

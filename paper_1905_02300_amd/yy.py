@@ -28,7 +28,7 @@ EXPORTS = ["yy_workspace_bytes", "yy_create", "yy_set_params", "yy_set_field", "
            "yy_ensemble_step", "yy_ensemble_destroy", "yy_autotune", "yy_set_tuning", "yy_step_tol",
            "yy_set_wall", "yy_set_mass_fix", "yy_set_t_bc",
            "yy_set_pressure_exchange", "yy_step_static", "yy_set_u_bc", "yy_ensemble_autotune",
-           "yy_ensemble_info", "yy_get_tuning"]
+           "yy_ensemble_info", "yy_get_tuning", "yy_stream_copy"]
 NPROF = 17
 
 
@@ -101,6 +101,7 @@ def load():
     L.yy_autotune.argtypes = [vp, ctypes.c_char_p, i32, vp]
     L.yy_set_tuning.argtypes = [vp, ctypes.c_char_p]
     L.yy_get_tuning.argtypes = [vp, ctypes.c_char_p, i32]
+    L.yy_stream_copy.argtypes = [vp, vp, u64, vp]
     _lib = L
     return L
 
@@ -129,6 +130,15 @@ def _stream_ptr(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def stream_copy(dst, src, stream=None):
+    """plain streaming copy of device tensor src into dst (same byte size)"""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("dst and src differ in size")
+    _check(load().yy_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nb,
+                                 _stream_ptr(stream)), "yy_stream_copy")
 
 
 class Shell:
