@@ -200,6 +200,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the line-solver tile autotuner")
     ap.add_argument("--no-line", action="store_true", help="skip the line-solve benchmark")
     ap.add_argument("--line-only", action="store_true", help="run only the line-solve benchmark")
+    ap.add_argument("--line-tiles", default="",
+                    help='with --line-only: time only these tiles, JSON {"fp64": {"r": tile, "t": tile, '
+                         '"p": tile}, "fp32": {...}} (for profiling the chosen kernels alone)')
     ap.add_argument("--cpu-grid", default="40,120,360")
     ap.add_argument("--ensemble-modes", default="sequential_eager,graph_streams,graph_batched",
                     help="ensemble modes to time (comma list)")
@@ -255,7 +258,9 @@ def main():
         ensemble(args)
         return
     if args.line_only:
-        print(json.dumps({"metric": "line-solve HBM GB/s", "line_solve": line_solve_bench()}), flush=True)
+        fixed = json.loads(args.line_tiles) if args.line_tiles else None
+        print(json.dumps({"metric": "line-solve HBM GB/s", "line_solve": line_solve_bench(fixed=fixed)}),
+              flush=True)
         return
 
     import torch
@@ -604,14 +609,15 @@ _LINE_TILES_RT = ["t"] + ["m%dw%d%s" % (m, w, b) for m in (4, 6, 8, 12, 16) for 
 _LINE_TILES_P = ["l1", "l2", "l4", "v2", "v4", "v8"]
 
 
-def line_solve_bench(nr=64, nt=192, np_=576, reps=20, nbuf=6):
+def line_solve_bench(nr=64, nt=192, np_=576, reps=20, nbuf=6, fixed=None):
     """The line-solve kernel alone: (I - tau/2 Pr D) y = x along r, theta,
     phi on both patches of a 2x64x192x576 grid (D = D_rr, Dhat_thth,
     Dhat_phph, and the true-metric D_thth, D_phph; tau = 1e-3, Pr = 1),
     FP64 and FP32, each with the fastest tile under these conditions.
     Algorithmic bytes per sweep: x read + y written = 2 words per cell.
     nbuf buffer pairs (> 1 GB in FP64) rotate so that the 256 MB
-    last-level cache cannot hold the working set."""
+    last-level cache cannot hold the working set.  fixed: {prec: {dir:
+    tile}} to time only these tiles (split metric), e.g. under a profiler."""
     import torch
     from paper_1905_02300_amd import inputs as I
     from paper_1905_02300_amd import yy
@@ -636,6 +642,8 @@ def line_solve_bench(nr=64, nt=192, np_=576, reps=20, nbuf=6):
             return a.elapsed_time(b) / n
 
         for metric, key in ((0, name), (1, name + "_true_metric")):
+            if fixed is not None and (metric == 1 or name not in fixed):
+                continue
             res = {}
             for d, dn in enumerate("rtp"):
                 if metric == 1 and d == 0:
@@ -643,10 +651,12 @@ def line_solve_bench(nr=64, nt=192, np_=576, reps=20, nbuf=6):
                 # the tile of this solve, chosen under the measurement's own
                 # conditions (rotating buffers, out of the last-level cache)
                 cands = _LINE_TILES_P if d == 2 else _LINE_TILES_RT
+                if fixed is not None:
+                    cands = [fixed[name][dn]]
                 best = None
                 for tile in cands:
                     sh.set_tuning('{"D.%s":"%s"}' % (dn, tile))
-                    ms = timed(d, metric, 6)
+                    ms = timed(d, metric, 6) if len(cands) > 1 else 0.0
                     if best is None or ms < best[0]:
                         best = (ms, tile)
                 sh.set_tuning('{"D.%s":"%s"}' % (dn, best[1]))

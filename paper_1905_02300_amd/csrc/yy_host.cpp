@@ -2096,6 +2096,7 @@ int yy_ensemble_autotune(yy_ensemble *e, char *json_out, int32_t cap, hipStream_
 int yy_stream_copy(void *dst, const void *src, uint64_t bytes, hipStream_t stream)
 {
     if (!dst || !src || bytes % 16 || ((uintptr_t)dst | (uintptr_t)src) % 16) return YY_ERR_ARG;
+    if (bytes / 16 > (uint64_t)0xffffffffu * 1024) return YY_ERR_ARG;     // grid limit
     if (bytes == 0) return YY_OK;
     stream_copy(dst, src, (int64_t)(bytes / 16), stream);
     return hip_status(hipGetLastError());

@@ -267,6 +267,7 @@ void pressure_exchange(const Dims &d, double *p, const FillScalar *tab, int ntab
                        hipStream_t st);
 void zero_doubles(double *p, int64_t n, hipStream_t st);
 void stream_copy(void *dst, const void *src, int64_t words16, hipStream_t st);
+int contig_pitch(int n, int P, int mc, int elem_bytes);
 // choose the register-resident partitioned line solver (default) or the
 // per-line Thomas kernel
 void set_partitioned(bool on);

@@ -1222,7 +1222,7 @@ template <typename R, int L, int CJ> struct KResidualLds {
 // Thread = line; lines along r and theta are coalesced over k.
 // ---------------------------------------------------------------------------
 template <typename R>
-struct SweepArgs { Dims d; Geo<R> g; Geo<double> gd; State<R> s; const R *x; R *y; R *cb; R *psi; double *partial; int P, mc; };
+struct SweepArgs { Dims d; Geo<R> g; Geo<double> gd; State<R> s; const R *x; R *y; R *cb; R *psi; double *partial; int P, mc, ld; };
 template <typename R, int L, int D, int MODE, int DIFF> struct KThomas {
     using Args = SweepArgs<R>;
     static constexpr int bounds = 256;
@@ -1720,7 +1720,7 @@ template <typename R, int L, int MODE, int DIFF, int M> struct KContig {
     const int n = d.np - k0;
     const int ni = d.nr - i0, nj = d.nt - j0;
     const int64_t nlines = (int64_t)ni * nj;
-    const int ld = P + 1;                      // padded row length of the transposed arrays
+    const int ld = a.ld;                       // row pitch of the transposed arrays (host-chosen)
     const int per = 4 * mc * ld;               // elements per line
     R *sl = reinterpret_cast<R *>(smem_raw) + (int64_t)w * per;
     R *tlo = sl, *tdi = sl + mc * ld, *tup = sl + 2 * mc * ld, *tx = sl + 3 * mc * ld;
@@ -1864,7 +1864,7 @@ template <typename R, int L, int MODE, int DIFF, int M> struct KContigMw {
     const int n = d.np - k0;
     const int ni = d.nr - i0, nj = d.nt - j0;
     const int64_t nlines = (int64_t)ni * nj;
-    const int ld = P + 1;                      // padded row length of the transposed arrays
+    const int ld = a.ld;                       // row pitch of the transposed arrays (host-chosen)
     R *tlo = reinterpret_cast<R *>(smem_raw);
     R *tdi = tlo + mc * ld, *tup = tlo + 2 * mc * ld, *tx = tlo + 3 * mc * ld;
     // reduced rows (after the chunks are eliminated): aliases of tlo/tdi/tup
@@ -2013,6 +2013,46 @@ template <typename R, int L, int MODE, int DIFF, int M> struct KContigMw {
     }
 };
 
+// Row pitch (>= P + 1) of the chunk-transposed staging arrays of the phi
+// solvers.  Row e of a line goes to (e mod mc) * ld + e / mc, so the lanes
+// of a wave, holding consecutive rows, write mc-strided runs: with ld = P + 1
+// most pitches put several lanes of a wave on one LDS bank (6-way for 6-row
+// chunks of 1152-point lines).  The pitch kept is the one among P+1 .. P+32
+// with the fewest lanes per bank over the waves' access groups (32 banks of
+// 4 bytes; 8-byte elements in half-waves).
+#if !defined(YY_ONLY_FLOAT)
+int contig_pitch(int n, int P, int mc, int elem_bytes)
+{
+    // a few (n, P, mc, size) keys recur every step: remember them
+    struct Key { int n, P, mc, eb, ld; };
+    thread_local Key memo[16] = {};
+    thread_local int nmemo = 0;
+    for (int q = 0; q < nmemo; q++)
+        if (memo[q].n == n && memo[q].P == P && memo[q].mc == mc && memo[q].eb == elem_bytes) return memo[q].ld;
+    const int group = elem_bytes == 8 ? 32 : 64, words = elem_bytes / 4;
+    int best_ld = P + 1, best = 1 << 30;
+    for (int ld = P + 1; ld <= P + 32; ld++) {
+        int worst = 0;
+        for (int e0 = 0; e0 < n && e0 < 64 * 8; e0 += group) {
+            int cnt[32] = {0};
+            for (int e = e0; e < e0 + group && e < n; e++) {
+                const int o = (e % mc) * ld + e / mc;
+                for (int w = 0; w < words; w++) {
+                    const int b = (o * words + w) & 31;
+                    if (++cnt[b] > worst) worst = cnt[b];
+                }
+            }
+        }
+        if (worst < best) {
+            best = worst;
+            best_ld = ld;
+        }
+    }
+    memo[nmemo < 16 ? nmemo++ : (n + P + mc) & 15] = Key{n, P, mc, elem_bytes, best_ld};
+    return best_ld;
+}
+#endif
+
 // Block shape of a strided partitioned solve of lines of n unknowns with
 // chunks of <= M rows: W lanes (consecutive k) x P chunks, W * P <= 512 and
 // a whole number of 64-lane waves, every chunk >= 2 rows.  False if the
@@ -2097,9 +2137,10 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
                 int64_t b = nlines;
                 if (b > SWEEP_BLOCKS) b = SWEEP_BLOCKS;
                 if (nblocks) *nblocks = (int)b;
-                const size_t lds = (size_t)4 * mcv * (Pv + 1) * sizeof(R);
+                const int ldv = contig_pitch(n, Pv, mcv, (int)sizeof(R));
+                const size_t lds = (size_t)4 * mcv * ldv * sizeof(R);
                 const dim3 grid((unsigned)b, d.npatch), block(64 * V);
-                const SweepArgs<R> sa{d, g, gd, s, x, y, s.cb, psi, partial, Pv, mcv};
+                const SweepArgs<R> sa{d, g, gd, s, x, y, s.cb, psi, partial, Pv, mcv, ldv};
 #define YY_MW(MM) launch<KContigMw<R, L, MODE, DIFF, MM>>(grid, block, lds, st, sa)
                 if (mcv <= 4) YY_MW(4);
                 else if (mcv <= 6) YY_MW(6);
@@ -2109,7 +2150,8 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
                 return true;
             }
         }
-        const size_t per_line = (size_t)4 * mc * (P + 1) * sizeof(R);
+        const int ld = contig_pitch(n, P, mc, (int)sizeof(R));
+        const size_t per_line = (size_t)4 * mc * ld * sizeof(R);
         int lpb = (int)(65536 / per_line);
         if (lpb > 4) lpb = 4;
         if (lpb < 1) return false;
@@ -2120,7 +2162,7 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
         if (nblocks) *nblocks = (int)b;
         const size_t lds = per_line * lpb;
         const dim3 grid((unsigned)b, d.npatch), block(64 * lpb);
-        const SweepArgs<R> sa{d, g, gd, s, x, y, s.cb, psi, partial, P, mc};
+        const SweepArgs<R> sa{d, g, gd, s, x, y, s.cb, psi, partial, P, mc, ld};
         if (mc <= 8) launch<KContig<R, L, MODE, DIFF, 8>>(grid, block, lds, st, sa);
         else if (mc <= 16) launch<KContig<R, L, MODE, DIFF, 16>>(grid, block, lds, st, sa);
         else if (mc <= 24) launch<KContig<R, L, MODE, DIFF, 24>>(grid, block, lds, st, sa);
@@ -2455,24 +2497,27 @@ void zero_doubles(double *p, int64_t n, hipStream_t st)
 // reaches on this part: every word read once and written once)
 // ---------------------------------------------------------------------------
 #if !defined(YY_ONLY_FLOAT)
+// block b copies the 16 KiB chunk [1024 b, 1024 b + 1024) of 16-byte words,
+// four coalesced words per thread, all loads in flight before the stores
 __global__ void __launch_bounds__(256) k_stream_copy(uint4 *__restrict__ dst, const uint4 *__restrict__ src,
                                                      int64_t n)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    for (; q + 3 * stride < n; q += 4 * stride) {
-        const uint4 a = src[q], b = src[q + stride], c = src[q + 2 * stride], e = src[q + 3 * stride];
+    const int64_t q = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    if (q + 768 < n) {
+        const uint4 a = src[q], b = src[q + 256], c = src[q + 512], e = src[q + 768];
         dst[q] = a;
-        dst[q + stride] = b;
-        dst[q + 2 * stride] = c;
-        dst[q + 3 * stride] = e;
+        dst[q + 256] = b;
+        dst[q + 512] = c;
+        dst[q + 768] = e;
+    } else {
+        for (int64_t r = q; r < n && r < q + 1024; r += 256) dst[r] = src[r];
     }
-    for (; q < n; q += stride) dst[q] = src[q];
 }
 
 void stream_copy(void *dst, const void *src, int64_t words16, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_stream_copy, dim3(256 * 16), dim3(256), 0, st, (uint4 *)dst, (const uint4 *)src,
+    const int64_t blocks = (words16 + 1023) / 1024;
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, st, (uint4 *)dst, (const uint4 *)src,
                        words16);
 }
 #endif

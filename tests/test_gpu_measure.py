@@ -16,7 +16,7 @@ def yy():
     return mod
 
 
-@pytest.mark.parametrize("n", [2, 1000, 3 * 256 * 16 * 256 + 6, (1 << 23) + (1 << 22) + 2])
+@pytest.mark.parametrize("n", [2, 1000, 2048 + 6, 3 * 256 * 16 * 256 + 6, (1 << 23) + (1 << 22) + 2])
 def test_stream_copy_exact(yy, n):
     print(f"case: stream copy of {n} doubles", flush=True)
     g = torch.Generator(device="cuda").manual_seed(n)
