@@ -467,16 +467,37 @@ template <typename R> struct KExtrapCopy {
         const PtrStep<R> &pa = a.p;
         const int64_t n = a.n;
 
-    for (int64_t q = blk.x * (int64_t)blockDim.x + threadIdx.x; q < n;
-         q += (int64_t)blk.nx * blockDim.x) {
+    // one 16-byte word of every compute-precision array per thread (VN
+    // elements; the FP64 pressures as VN doubles), all loads issued before
+    // the stores; n is a multiple of VN (rows are 128-byte aligned)
+    constexpr int VN = 16 / (int)sizeof(R);
+    const int64_t q = (blk.x * (int64_t)blockDim.x + threadIdx.x) * VN;
+    if (q >= n) return;
+    R vn[7][VN], vm[7][VN];
+    double pp[2][VN];
 #pragma unroll
-        for (int f = 0; f < 7; f++) {
-            const R v = pa.n[f][q];
-            pa.s[f][q] = R(1.5) * v - R(0.5) * pa.m[f][q];
-            pa.k[f][q] = v;
-        }
-        pa.p0k[q] = pa.p0[q];
-        pa.p1k[q] = pa.p1[q];
+    for (int f = 0; f < 7; f++) {
+        *(uint4 *)vn[f] = *(const uint4 *)(pa.n[f] + q);
+        *(uint4 *)vm[f] = *(const uint4 *)(pa.m[f] + q);
+    }
+#pragma unroll
+    for (int h = 0; h < VN; h += 2) {
+        *(double2 *)&pp[0][h] = *(const double2 *)(pa.p0 + q + h);
+        *(double2 *)&pp[1][h] = *(const double2 *)(pa.p1 + q + h);
+    }
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int f = 0; f < 7; f++) {
+        R vs[VN];
+#pragma unroll
+        for (int e = 0; e < VN; e++) vs[e] = R(1.5) * vn[f][e] - R(0.5) * vm[f][e];
+        *(uint4 *)(pa.s[f] + q) = *(const uint4 *)vs;
+        *(uint4 *)(pa.k[f] + q) = *(const uint4 *)vn[f];
+    }
+#pragma unroll
+    for (int h = 0; h < VN; h += 2) {
+        *(double2 *)(pa.p0k + q + h) = *(const double2 *)&pp[0][h];
+        *(double2 *)(pa.p1k + q + h) = *(const double2 *)&pp[1][h];
     }
     }
 };
@@ -521,7 +542,8 @@ template <typename R> void Ops<R>::extrap_copy(const Dims &d, const State<R> &s,
     a.p0 = s.p[0][0]; a.p0k = s.p[0][1];
     a.p1 = s.p[1][0]; a.p1k = s.p[1][1];
     const int64_t n = 2 * d.sP;
-    launch<KExtrapCopy<R>>(dim3(grid_for(n)), dim3(256), 0, st, ExtrapCopyArgs<R>{a, n});
+    const int64_t words = n / (16 / (int64_t)sizeof(R));
+    launch<KExtrapCopy<R>>(dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st, ExtrapCopyArgs<R>{a, n});
 }
 
 
