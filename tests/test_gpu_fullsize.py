@@ -66,16 +66,25 @@ BENCH_TILES = ('{"T.r":"m8w16b","T.t":"m6w32b","T.p":"v4","u_r.r":"m4w32b","u_r.
                '"u_p.t":"m6w32b","u_p.p":"v4","D.r":"m8w16b","D.t":"m6w16b","D.p":"v4"}')
 
 
-_ORACLE_64 = {}     # the oracle's two steps, shared by both tile sets
+# the tiles the autotuner chose for the same workload with the LDS-staged
+# residual tiles available (theta/phi neighbours staged in LDS planes)
+BENCH_TILES_LDS = ('{"T.r":"m8w16b","T.t":"m12w32","T.p":"v4","u_r.r":"m8w16b","u_r.t":"m12w16",'
+                   '"u_r.p":"v4","u_t.r":"m8w16","u_t.t":"m6w16","u_t.p":"v4","u_p.r":"m8w16b",'
+                   '"u_p.t":"m12w16b","u_p.p":"v4","D.r":"m16w32b","D.t":"m12w64b","D.p":"v2",'
+                   '"res.T":"lds64x8k","res.u_r":"lds64x4k","res.u_t":"lds64x4k","res.u_p":"lds64x4k"}')
+
+
+_ORACLE_64 = {}     # the oracle's two steps, shared by every tile set
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("tiles", ["bench", "auto"])
+@pytest.mark.parametrize("tiles", ["bench", "bench_lds", "auto"])
 def test_convection_steps_64x192x576(oracle_lib, yy, tiles):
     """The benchmark's workload (convection start: conductive T plus seeded
     noise, hydrostatic p, Ra = 1e5, tau = 2e-4, K = 3) on 2x64x192x576:
-    two whole steps against the oracle, with the benchmark's tile set and
-    with the tiles the autotuner picks at this size.  Every field within
+    two whole steps against the oracle, with two tile sets the autotuner
+    picked for the benchmark (memory-read and LDS-staged residuals) and with
+    the tiles it picks at this size.  Every field within
     1e-12 relative, the velocities plus the rounding floor of the cancelling
     buoyancy and hydrostatic pressure gradient (as in the small convection
     parity case)."""
@@ -91,6 +100,8 @@ def test_convection_steps_64x192x576(oracle_lib, yy, tiles):
             g.set_field(f, 1, st[f])
     if tiles == "bench":
         g.set_tuning(BENCH_TILES)
+    elif tiles == "bench_lds":
+        g.set_tuning(BENCH_TILES_LDS)
     else:
         g.autotune()
     for _ in range(nsteps):
