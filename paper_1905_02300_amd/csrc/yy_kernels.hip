@@ -1372,17 +1372,30 @@ template <typename R, int L, int D, int MODE, int DIFF> struct KThomas {
 // Forward elimination of row m of a chunk as it is assembled (row m:
 // lo x_{m-1} + di x_m + up x_{m+1} = rhs).  Rows 0 and 1 are normalised;
 // rows m >= 2 are rewritten through the chunk's first unknown x_0.
+// 1/x for the pivots of the line solvers: the hardware reciprocal refined
+// by two Newton steps r <- r (2 - x r) in FP64 (each squares the relative
+// error), the 1-ulp hardware reciprocal in FP32.  The pivots of these
+// diagonally dominant systems are O(1), far from zero and from overflow, so
+// the scaling an IEEE division performs is not needed.
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = r * (2.0 - x * r);
+    return r * (2.0 - x * r);
+}
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+
 template <typename R, int M>
 __device__ __forceinline__ void chunk_forward(R (&a)[M], R (&c)[M], R (&d)[M], int m, R lo, R di,
                                               R up, R rhs)
 {
     if (m < 2) {
-        const R r = R(1) / di;
+        const R r = recip(di);
         a[m] = lo * r;
         c[m] = up * r;
         d[m] = rhs * r;
     } else {
-        const R r = R(1) / (di - lo * c[m - 1]);
+        const R r = recip(di - lo * c[m - 1]);
         d[m] = r * (rhs - lo * d[m - 1]);
         c[m] = r * up;
         a[m] = -r * lo * a[m - 1];
@@ -1404,7 +1417,7 @@ __device__ __forceinline__ void chunk_backward(R (&a)[M], R (&c)[M], R (&d)[M], 
         }
     }
     if (mt >= 3) {
-        const R r = R(1) / (R(1) - c[0] * a[1]);
+        const R r = recip(R(1) - c[0] * a[1]);
         d[0] = r * (d[0] - c[0] * d[1]);
         a[0] = r * a[0];
         c[0] = -r * c[0] * c[1];
@@ -1435,7 +1448,7 @@ __device__ __forceinline__ Row4<R> erow(R al, R be, R de, R ga, R et, R ze, R al
 template <typename R>
 __device__ __forceinline__ Row4<R> pcr_level(const Row4<R> &t, const Row4<R> &m, const Row4<R> &p)
 {
-    const R k1 = t.a / m.b, k2 = t.c / p.b;
+    const R k1 = t.a * recip(m.b), k2 = t.c * recip(p.b);
     Row4<R> o;
     o.a = -k1 * m.a;
     o.c = -k2 * p.c;
@@ -1666,7 +1679,7 @@ template <typename R, int L, int D, int MODE, int DIFF, int M, bool BL> struct K
             }
             row = pcr_level<R>(row, rm, rp);
         }
-        const R xe = row.d / row.b;
+        const R xe = row.d * recip(row.b);
         __syncthreads();
         sA[t * W + lane] = xe;
         __syncthreads();
@@ -1805,7 +1818,7 @@ template <typename R, int L, int MODE, int DIFF, int M> struct KContig {
             if (lane + h >= P) { rp.a = R(0); rp.b = R(1); rp.c = R(0); rp.d = R(0); }
             row = pcr_level<R>(row, rm, rp);
         }
-        const R xe = row.d / row.b;
+        const R xe = row.d * recip(row.b);
         const R xem0 = shfl_r(xe, (lane - 1) & 63);
         const R xem = lane > 0 ? xem0 : R(0);
         const R xs = dd[0] - a[0] * xem - c[0] * xe;
@@ -1997,7 +2010,7 @@ template <typename R, int L, int MODE, int DIFF, int M> struct KContigMw {
                 row = pcr_level<R>(row, rm, rp);
             }
         }
-        const R xe = tid < P ? row.d / row.b : R(0);
+        const R xe = tid < P ? row.d * recip(row.b) : R(0);
         __syncthreads();
         if (tid < P) sA[tid] = xe;
         __syncthreads();
