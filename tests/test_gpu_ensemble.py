@@ -215,3 +215,28 @@ def test_ensemble_batched_falls_back_for_mass_fix_and_exchange(yy):
             x = a.shells[q].get_field(f).cpu().numpy()
             y = b.shells[q].get_field(f).cpu().numpy()
             assert np.array_equal(x, y), (q, I.FIELD_NAMES[f])
+
+
+def test_ensemble_batched_multiplicative_and_mixed_modes(yy):
+    """Shells in the multiplicative mode (Yin, then Yang from Yin's
+    iterate: one patch per launch) batch like additive ones and stay
+    bitwise equal to graph-free stepping; an ensemble mixing the two modes
+    has step sequences that do not line up, so it takes the per-shell
+    stream graph (info: not batched) with the same results."""
+    print("case: ensemble batched, multiplicative and mixed modes", flush=True)
+    states = _states()
+    for modes, want_batched in (([1, 1, 1], True), ([0, 1, 0], False)):
+        a = _load_ensemble(yy, yy.YY_FP64, states)
+        b = _load_ensemble(yy, yy.YY_FP64, states)
+        for e in (a, b):
+            for q, sh in enumerate(e.shells):
+                sh.set_params(pr=1.0, ra=RAS[q], dt=DT, t_inner=1.0, mode=modes[q])
+        for _ in range(7):
+            a.step(K, graph=1)
+            b.step(K, graph=0)
+        assert a.info()[0] is want_batched, modes
+        for q in range(len(GRIDS)):
+            for f in range(9):
+                x = a.shells[q].get_field(f).cpu().numpy()
+                y = b.shells[q].get_field(f).cpu().numpy()
+                assert np.array_equal(x, y), (modes, q, I.FIELD_NAMES[f])
