@@ -1084,6 +1084,9 @@ template <typename R, int L, int CJ> struct KResidualLds {
     static constexpr int wpe = (L == CC || sizeof(R) == 4) ? 4 : 3;
     static constexpr bool xcd = true;
     static constexpr int W = 66, PL = (CJ + 2) * W, NT = 64 * CJ;
+    // every halo cell of a group has its own thread (at most two rows of
+    // 66 and two columns of CJ)
+    static_assert(2 * W + 2 * CJ <= NT, "LDS residual tiles need at least 4 rows");
     static constexpr int NPL = res_nplanes<L>();
     static constexpr bool HASP = L == FT || L == FP;
     // halo groups: psibar and psi* (all four sides); CC/FR: j+1 and k+1
