@@ -346,20 +346,21 @@ yy_shell *yy_ensemble_shell(yy_ensemble *e, int32_t s);
  * shells' launches at one position of the step are grouped by kernel
  * instance (tile) and block shape, and each group is one launch over a
  * work list in which every shell owns a range of blocks (argument and
- * block tables in the ensemble's workspace).  Shells whose steps do not
- * line up (different Schwarz modes, the mass-flux correction or the
- * pressure exchange on some only), or n_schwarz > 8, fall back to
- * graph = 2.
+ * block tables in the ensemble's workspace); the shells are dealt to up
+ * to four branches of similar cell counts, which the graph runs side by
+ * side.  Shells whose steps do not line up (different Schwarz modes), with
+ * the mass-flux correction or the pressure exchange, n_schwarz > 8, or
+ * launch tables that exceed the ensemble's arena fall back to graph = 2.
  * graph = 2: one forked stream per shell inside the graph.
  * graph = 0 enqueues the shells one after another on the stream instead.
  * A single-shell step (yy_step, yy_step_tol, yy_step_static) on a member
  * between graph steps is allowed: the graphs are captured again.  Shells
  * with Dirichlet wall data (yy_set_wall) need new values every step, so
- * graph = 1 refuses them (YY_ERR_STATE, nothing advanced); graph = 0
+ * graph = 1 and 2 refuse them (YY_ERR_STATE, nothing advanced); graph = 0
  * steps them.  A failed capture leaves every shell's time levels as they
  * were.
  * Errors: YY_ERR_ARG, YY_ERR_STATE (a shell without params, or with wall
- * data under graph = 1), YY_ERR_HIP. */
+ * data under graph = 1 or 2), YY_ERR_HIP. */
 int yy_ensemble_step(yy_ensemble *e, int32_t n_schwarz, int32_t graph, hipStream_t stream);
 
 /* Tile autotuning of an ensemble: every shell is tuned (yy_autotune), then
