@@ -740,8 +740,15 @@ def test_autotune_round_trip(yy):
     js = g.autotune()
     assert js.startswith("{") and '"u_t.t"' in js and '"T.p"' in js
     g.set_tuning(js)
+    # the current tiles read back as the autotuner wrote them
+    import json
+    assert json.loads(g.tuning_json()) == json.loads(js)
     with pytest.raises(yy.YYError):
         g.set_tuning('{"T.r":"m7w64"}')
-    g.set_tuning('{"T.r":"m8w32b","u_t.t":"m6w16"}')
+    g.set_tuning('{"T.r":"m8w32b","u_t.t":"m6w16","res.u_p":"lds64x8j"}')
+    cur = json.loads(g.tuning_json())
+    assert cur["T.r"] == "m8w32b" and cur["u_t.t"] == "m6w16" and cur["res.u_p"] == "lds64x8j"
     with pytest.raises(yy.YYError):
         g.set_tuning('{"T.r":"m8w32x"}')
+    with pytest.raises(yy.YYError):
+        g.set_tuning('{"res.T":"lds64x2k"}')
