@@ -63,8 +63,11 @@ def test_step_static_matches_step(yy, prec):
         a.step(3)
         b.step_static(3)
     _same(a, b, 3, prec)
-    # second call, a smaller grid on the same static array
+    # second call, a smaller grid on the same static array, with the
+    # LDS-staged residual tiles
     a, b = _convection_pair(yy, 6, 12, 36, prec, 1e4, 4)
+    for sh in (a, b):
+        sh.set_tuning('{"res.T":"lds64x4k","res.u_r":"lds64x8k","res.u_t":"lds64x4k","res.u_p":"lds64x8j"}')
     for _ in range(3):
         a.step(2)
         b.step_static(2)
