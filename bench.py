@@ -757,27 +757,43 @@ def parity_oracle(args):
             json.dump(out, fh, indent=1)
 
 
-def cpu_baseline(grid_s, pr, ra, dt, K):
-    """The oracle as it stands, on the host cores: one step of the same
-    workload (same physics and schedule) on a bounded grid."""
+def cpu_baseline(grid_s, pr, ra, dt, K, nsteps=2, single_grid="20,60,180"):
+    """The oracle as it stands, on the host cores: the first nsteps steps of
+    the same workload (same physics, schedule and start) on a bounded grid,
+    all host threads; and one step on a smaller grid on one thread."""
     from oracle import yyo
     from paper_1905_02300_amd import inputs as I
-    nr, nt, np_ = (int(x) for x in grid_s.split(","))
-    grid = I.Grid(nr, nt, np_)
-    o = yyo.Shell(nr, nt, np_)
-    o.set_params(pr=pr, ra=ra, tau=dt, chi=1.0, t_inner=1.0, t_outer=0.0)
-    st = I.convection_state(grid, pr, ra, seed=3)
-    for f in range(9):
-        o.set_field(f, 0, st[f])
-        o.set_field(f, 1, st[f])
-    del st
-    t0 = time.perf_counter()
-    o.step(K)
-    el = time.perf_counter() - t0
-    return {"value": grid.cells / el / 1e6, "unit": "Mcell-steps/s", "cores": yyo.omp_threads(),
-            "kind": "oracle",
-            "sample": f"one step (K={K}) of the same convecting-shell workload on a 2x{nr}x{nt}x{np_} "
-                      f"grid ({grid.cells} cells), {el:.1f} s wall"}
+
+    def run(gs, steps):
+        nr, nt, np_ = (int(x) for x in gs.split(","))
+        grid = I.Grid(nr, nt, np_)
+        o = yyo.Shell(nr, nt, np_)
+        o.set_params(pr=pr, ra=ra, tau=dt, chi=1.0, t_inner=1.0, t_outer=0.0)
+        st = I.convection_state(grid, pr, ra, seed=3)
+        for f in range(9):
+            o.set_field(f, 0, st[f])
+            o.set_field(f, 1, st[f])
+        del st
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            o.step(K)
+        el = time.perf_counter() - t0
+        o.close()
+        return grid, el
+
+    yyo.set_threads(0)
+    grid, el = run(grid_s, nsteps)
+    out = {"value": grid.cells * nsteps / el / 1e6, "unit": "Mcell-steps/s", "cores": yyo.omp_threads(),
+           "kind": "oracle",
+           "sample": f"the first {nsteps} steps (K={K}) of the same convecting-shell workload on a "
+                     f"2x{grid.nr}x{grid.nt}x{grid.np} grid ({grid.cells} cells), {el:.1f} s wall"}
+    yyo.set_threads(1)
+    g1, e1 = run(single_grid, 1)
+    yyo.set_threads(0)
+    out["single_thread"] = {"value": g1.cells / e1 / 1e6, "unit": "Mcell-steps/s", "cores": 1,
+                            "sample": f"one step (K={K}) on a 2x{g1.nr}x{g1.nt}x{g1.np} grid "
+                                      f"({g1.cells} cells), {e1:.1f} s wall"}
+    return out
 
 
 if __name__ == "__main__":

@@ -1424,6 +1424,15 @@ int yyo_get_norms(const yyo *h, double *out, int cap)
     return n;
 }
 
+void yyo_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+    (void)n;
+#endif
+}
+
 int yyo_omp_threads(void)
 {
 #ifdef _OPENMP

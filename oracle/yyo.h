@@ -123,6 +123,8 @@ void yyo_involution(double th, double ph, double *th2, double *ph2);
  * this patch's components at (th, ph) */
 void yyo_rotation(double th, double ph, double m[4]);
 int yyo_omp_threads(void);
+/* threads of the following calls (n <= 0: one per host core) */
+void yyo_set_threads(int n);
 
 #ifdef __cplusplus
 }

@@ -98,6 +98,11 @@ def omp_threads():
     return lib().yyo_omp_threads()
 
 
+def set_threads(n):
+    """threads of the following oracle calls (n <= 0: one per host core)"""
+    lib().yyo_set_threads(int(n))
+
+
 class Shell:
     """One Yin-Yang shell held by the oracle."""
 
