@@ -147,11 +147,20 @@ int yy_set_wall(yy_shell *s, int32_t field, int32_t level, int32_t wall, const d
  * normal velocities of each patch (u_theta on its theta-boundary faces,
  * u_phi on its phi-boundary faces) so that, with the wall data, the
  * patch's boundary carries no net mass flux.  The correction is the
- * minimiser of the paper's functional J in the limit of a vanishing
- * penalty parameter: v = u_bd - (F / a.a) a, with a the faces' outward
- * flux weights (the face areas of Div_h) and F the net flux.  on = 0
- * (default) turns it off.  Errors: YY_ERR_ARG. */
+ * minimiser of the paper's functional J (the point its conjugate-gradient
+ * iteration converges to): v = u_bd - (F / (eps |dOmega|^2 + a.a)) a, with
+ * a the faces' outward flux weights (the face areas of Div_h), F the net
+ * flux of u_bd and the wall data, |dOmega| the area of the patch's
+ * boundary; by default eps = 0 (the limit: no net flux left) and it is
+ * applied whatever F (see yy_set_mass_fix_params).  on = 0 (default) turns
+ * it off.  Errors: YY_ERR_ARG. */
 int yy_set_mass_fix(yy_shell *s, int32_t on);
+
+/* The parameters of step 4: eps >= 0, the penalty parameter of J (the
+ * paper's epsilon; 0: the limit), and tol >= 0, the net flux below which a
+ * patch's data are left uncorrected (the paper's test |F| >= tol; 0:
+ * always corrected).  Errors: YY_ERR_ARG (negative or NaN). */
+int yy_set_mass_fix_params(yy_shell *s, double eps, double tol);
 
 /* Algorithm step 7 (Sec. 4: after the pressure update of a patch,
  * interpolate the pressure near its boundary from the other patch; the

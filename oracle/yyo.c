@@ -46,6 +46,7 @@ struct yyo {
     double pr, ra, tau, chi, t_in, t_out;
     int mode;
     int mass_fix;                /* Algorithm step 4 on every velocity fill */
+    double mf_eps, mf_tol;       /* its epsilon (0: the limit) and flux trigger */
     int nring;                   /* Algorithm step 7: rings of pressure cells taken
                                     from the other patch (0: off) */
     double *ptmp;                /* gathered ring pressures (both patches) */
@@ -398,6 +399,15 @@ int yyo_set_mass_fix(yyo *h, int on)
     return 0;
 }
 
+int yyo_set_mass_fix_params(yyo *h, double eps, double tol)
+{
+    if (!h || !(eps >= 0.0) || !(tol >= 0.0)) return -1;
+    h->mf_eps = eps;
+    h->mf_tol = tol;
+    h->filled = 0;
+    return 0;
+}
+
 /* Algorithm step 7 (Sec. 4): after each pressure update the pressure of
  * the outermost nring cells of a patch (cells with j < nring,
  * j >= nt - nring, k < nring or k >= np - nring, every radial index) is
@@ -600,8 +610,11 @@ static void wall_rules(const yyo *h, int level, int p)
  * is quadratic with the Hessian I + c a a^T (a = the faces' flux weights
  * with their outward signs).  Its minimiser, the limit of the conjugate
  * gradient iteration, is v = u_bd - kappa a with
- *   kappa = (F(u_bd) + F_r) / (eps |dOmega|^2 + a.a);
- * here eps -> 0, so the corrected data carry no net flux.  The flux weights
+ *   kappa = (F(u_bd) + F_r) / (eps |dOmega|^2 + a.a),
+ * |dOmega| the area of the patch's boundary (all its faces).  eps = 0 (the
+ * default) is the limit in which the corrected data carry no net flux.  The
+ * correction is made when |F(u_bd) + F_r| >= tol (default 0: always).  The
+ * flux weights
  * are the face areas of the discrete divergence: r-face r_f^2 sin(theta_j)
  * dtheta dphi, theta-face r_i sin(theta_f) dr dphi, phi-face r_i dr dtheta,
  * so that the volume-weighted sum of Div_h over the patch telescopes to
@@ -613,12 +626,13 @@ static void mass_fix(yyo *h, int level, int p)
         double *ur = h->lev[s == 0 ? YYO_U1R : YYO_U2R][level];
         double *ut = h->lev[s == 0 ? YYO_U1T : YYO_U2T][level];
         double *up = h->lev[s == 0 ? YYO_U1P : YYO_U2P][level];
-        double F = 0.0, S = 0.0;
+        double F = 0.0, S = 0.0, A = 0.0;
         for (int j = 0; j < nt; j++)
             for (int k = 0; k < np; k++) {
                 const double a0 = rf(h, 0) * rf(h, 0) * sin(tc(h, j)) * h->dth * h->dph;
                 const double a1 = rf(h, nr) * rf(h, nr) * sin(tc(h, j)) * h->dth * h->dph;
                 F += a1 * ur[ix(h, p, nr, j, k)] - a0 * ur[ix(h, p, 0, j, k)];
+                A += a0 + a1;
             }
         for (int i = 0; i < nr; i++) {
             for (int k = 0; k < np; k++) {
@@ -626,14 +640,17 @@ static void mass_fix(yyo *h, int level, int p)
                 const double a1 = rc(h, i) * sin(tf(h, nt)) * h->dr * h->dph;
                 F += a1 * ut[ix(h, p, i, nt, k)] - a0 * ut[ix(h, p, i, 0, k)];
                 S += a0 * a0 + a1 * a1;
+                A += a0 + a1;
             }
             for (int j = 0; j < nt; j++) {
                 const double a = rc(h, i) * h->dr * h->dth;
                 F += a * (up[ix(h, p, i, j, np)] - up[ix(h, p, i, j, 0)]);
                 S += 2.0 * a * a;
+                A += 2.0 * a;
             }
         }
-        const double kappa = F / S;
+        if (fabs(F) < h->mf_tol) continue;
+        const double kappa = F / (h->mf_eps * A * A + S);
         for (int i = 0; i < nr; i++) {
             for (int k = 0; k < np; k++) {
                 ut[ix(h, p, i, 0, k)] += kappa * rc(h, i) * sin(tf(h, 0)) * h->dr * h->dph;

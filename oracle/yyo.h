@@ -52,6 +52,9 @@ int yyo_set_mode(yyo *h, int mode);
  * fill so that each patch's boundary carries no net mass flux (Algorithm
  * step 4, optional in the paper); 0 (default): off */
 int yyo_set_mass_fix(yyo *h, int on);
+/* epsilon of step 4's functional (0: the limit, no net flux left) and the
+ * flux below which the correction is skipped (0: always applied) */
+int yyo_set_mass_fix_params(yyo *h, double eps, double tol);
 /* Algorithm step 7 (pressure exchange): nring > 0 makes the outermost
  * nring cells of each patch (in theta and phi, every radial index) take,
  * after every pressure update of p1 and p2, the other patch's pressure

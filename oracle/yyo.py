@@ -33,6 +33,7 @@ def load_library(path):
     L.yyo_set_mode.argtypes = [vp, i]
     L.yyo_set_verbose.argtypes = [vp, i]
     L.yyo_set_mass_fix.argtypes = [vp, i]
+    L.yyo_set_mass_fix_params.argtypes = [vp, d, d]
     L.yyo_set_pressure_exchange.argtypes = [vp, i]
     L.yyo_set_t_bc.argtypes = [vp, i, d, d]
     L.yyo_set_u_bc.argtypes = [vp, i, d, d]
@@ -179,6 +180,11 @@ class Shell:
     def set_mass_fix(self, on):
         if self._L.yyo_set_mass_fix(self.h, 1 if on else 0) != 0:
             raise RuntimeError("set_mass_fix failed")
+
+    def set_mass_fix_params(self, eps, tol):
+        """epsilon of step 4's functional (0: the limit) and its flux trigger"""
+        if self._L.yyo_set_mass_fix_params(self.h, float(eps), float(tol)) != 0:
+            raise ValueError("yyo_set_mass_fix_params: eps and tol must be >= 0")
 
     def set_pressure_exchange(self, nring):
         """Algorithm step 7: the outermost nring cells take the other

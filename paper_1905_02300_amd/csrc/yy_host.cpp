@@ -468,6 +468,8 @@ struct yy_shell {
     // Algorithm step 4 on every velocity fill
     bool mass_fix = false;
     double mf_S = 0.0;           // sum of the squared boundary flux weights
+    double mf_A = 0.0;           // area of a patch's boundary
+    double mf_eps = 0.0, mf_tol = 0.0;   // step 4's epsilon (0: the limit) and flux trigger
     double *mfp = nullptr;       // partial net fluxes
 };
 
@@ -559,7 +561,9 @@ template <typename R> void do_fill(yy_shell *s, int lev, int pmask, hipStream_t 
     Timed tm(s, PC_FILL, st);
     Ops<R>::fill(s->L.d, state_of<R>(s), lev, s->fcc, (int)s->L.ncc, s->fvt, (int)s->L.nvt, s->fvp,
                  (int)s->L.nvp, s->prm.t_inner, s->prm.t_outer, s->tb, s->ub, walls_of(s, lev), pmask, st);
-    if (s->mass_fix) Ops<R>::mass_fix(s->L.d, s->gd, state_of<R>(s), lev, s->mf_S, s->mfp, pmask, st);
+    if (s->mass_fix)
+        Ops<R>::mass_fix(s->L.d, s->gd, state_of<R>(s), lev, s->mf_S + s->mf_eps * s->mf_A * s->mf_A, s->mf_tol,
+                         s->mfp, pmask, st);
 }
 
 template <typename R> void solve_field(yy_shell *s, const Dims &d, int f, hipStream_t st)
@@ -865,14 +869,20 @@ int yy_create(const yy_grid *g, int32_t prec, void *dev_ws, uint64_t ws_bytes, y
     {
         // squared flux weights of the interpolated boundary faces (theta- and
         // phi-boundary), the same for both patches
-        double S = 0.0;
+        double S = 0.0, A = 0.0;
         const double s0 = std::sin(F.th0), s1 = std::sin(F.th0 + L.d.nt * F.dth);
         for (int i = 0; i < L.d.nr; i++) {
             const double rc = F.r1 + (i + 0.5) * F.dr;
             const double a0 = rc * s0 * F.dr * F.dph, a1 = rc * s1 * F.dr * F.dph, a2 = rc * F.dr * F.dth;
             S += L.d.np * (a0 * a0 + a1 * a1) + 2.0 * L.d.nt * a2 * a2;
+            A += L.d.np * (a0 + a1) + 2.0 * L.d.nt * a2;
         }
+        // the r walls (their data enter the flux, they are not corrected)
+        const double r2 = F.r1 + L.d.nr * F.dr;
+        for (int j = 0; j < L.d.nt; j++)
+            A += (F.r1 * F.r1 + r2 * r2) * L.d.np * std::sin(F.th0 + (j + 0.5) * F.dth) * F.dth * F.dph;
         s->mf_S = S;
+        s->mf_A = A;
     }
     for (int q = 0; q < NSLOT; q++) s->nblocks[q] = 0;
     *out = s;
@@ -1015,6 +1025,16 @@ int yy_set_mass_fix(yy_shell *s, int32_t on)
     if (!s || (on != 0 && on != 1)) return YY_ERR_ARG;
     if ((on != 0) != s->mass_fix) s->version++;
     s->mass_fix = on != 0;
+    s->need_fill = true;
+    return YY_OK;
+}
+
+int yy_set_mass_fix_params(yy_shell *s, double eps, double tol)
+{
+    if (!s || !(eps >= 0.0) || !(tol >= 0.0)) return YY_ERR_ARG;
+    if (eps != s->mf_eps || tol != s->mf_tol) s->version++;
+    s->mf_eps = eps;
+    s->mf_tol = tol;
     s->need_fill = true;
     return YY_OK;
 }

@@ -253,9 +253,10 @@ template <typename R> struct Ops {
     static void add_profile(const Dims &d, R *a, const double *prof, hipStream_t st);
     // Algorithm step 4 on a filled velocity level: make each patch's boundary
     // normal data carry no net mass flux (both systems); partial: 4 * MF_BLOCKS
-    // doubles of scratch; S = sum of the squared boundary flux weights
+    // doubles of scratch; S = sum of the squared boundary flux weights plus
+    // eps |dOmega|^2; patches whose |net flux| is below tol are left alone
     static void mass_fix(const Dims &d, const Geo<double> &gd, const State<R> &s, int level,
-                         double S, double *partial, int patch_mask, hipStream_t st);
+                         double S, double tol, double *partial, int patch_mask, hipStream_t st);
 };
 void io_double(const Dims &d, double *internal, const double *ext, double *ext_out, int field_loc,
                int layout, hipStream_t st);

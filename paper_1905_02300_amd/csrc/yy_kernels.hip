@@ -2689,7 +2689,7 @@ __global__ void __launch_bounds__(256) k_mflux(Dims d, Geo<double> g, State<R> s
 // every block sums the partials (fixed order), then corrects its faces
 template <typename R>
 __global__ void __launch_bounds__(256) k_mfix(Dims d, Geo<double> g, State<R> s, int lev, double S,
-                                              const double *partial, int pmask)
+                                              double tol, const double *partial, int pmask)
 {
     const int p = blockIdx.y, y = blockIdx.z;
     if (!((pmask >> p) & 1)) return;
@@ -2698,7 +2698,7 @@ __global__ void __launch_bounds__(256) k_mfix(Dims d, Geo<double> g, State<R> s,
         double v = 0.0;
         for (int b = threadIdx.x; b < MF_BLOCKS; b += 64) v += partial[(y * 2 + p) * MF_BLOCKS + b];
         for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-        if (threadIdx.x == 0) kap = v / S;
+        if (threadIdx.x == 0) kap = fabs(v) < tol ? 0.0 : v / S;
     }
     __syncthreads();
     R *ut = s.u[y][1][lev], *up = s.u[y][2][lev];
@@ -2712,7 +2712,7 @@ __global__ void __launch_bounds__(256) k_mfix(Dims d, Geo<double> g, State<R> s,
 }
 
 template <typename R>
-void Ops<R>::mass_fix(const Dims &d, const Geo<double> &gd, const State<R> &s, int lev, double S,
+void Ops<R>::mass_fix(const Dims &d, const Geo<double> &gd, const State<R> &s, int lev, double S, double tol,
                       double *partial, int pmask, hipStream_t st)
 {
     if (LaunchRecorder *r = launch_recorder()) {
@@ -2721,8 +2721,8 @@ void Ops<R>::mass_fix(const Dims &d, const Geo<double> &gd, const State<R> &s, i
     }
     const dim3 g(MF_BLOCKS, 2, 2);
     hipLaunchKernelGGL(k_mflux<R>, g, dim3(256), 0, st, d, gd, s, lev, partial, pmask);
-    hipLaunchKernelGGL(k_mfix<R>, dim3(64, 2, 2), dim3(256), 0, st, d, gd, s, lev, S, (const double *)partial,
-                       pmask);
+    hipLaunchKernelGGL(k_mfix<R>, dim3(64, 2, 2), dim3(256), 0, st, d, gd, s, lev, S, tol,
+                       (const double *)partial, pmask);
 }
 
 #if !defined(YY_ONLY_FLOAT)

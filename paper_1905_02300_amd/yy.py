@@ -28,7 +28,7 @@ EXPORTS = ["yy_workspace_bytes", "yy_create", "yy_set_params", "yy_set_field", "
            "yy_ensemble_step", "yy_ensemble_destroy", "yy_autotune", "yy_set_tuning", "yy_step_tol",
            "yy_set_wall", "yy_set_mass_fix", "yy_set_t_bc",
            "yy_set_pressure_exchange", "yy_step_static", "yy_set_u_bc", "yy_ensemble_autotune",
-           "yy_ensemble_info", "yy_get_tuning", "yy_stream_copy"]
+           "yy_ensemble_info", "yy_get_tuning", "yy_stream_copy", "yy_set_mass_fix_params"]
 NPROF = 17
 
 
@@ -70,6 +70,7 @@ def load():
     L.yy_set_forcing.argtypes = [vp, i32, vp, vp]
     L.yy_set_wall.argtypes = [vp, i32, i32, i32, vp, vp]
     L.yy_set_mass_fix.argtypes = [vp, i32]
+    L.yy_set_mass_fix_params.argtypes = [vp, ctypes.c_double, ctypes.c_double]
     L.yy_set_pressure_exchange.argtypes = [vp, i32]
     L.yy_set_t_bc.argtypes = [vp, i32, ctypes.c_double, ctypes.c_double]
     L.yy_set_u_bc.argtypes = [vp, i32, ctypes.c_double, ctypes.c_double]
@@ -249,6 +250,10 @@ class Shell:
     def set_mass_fix(self, on):
         """Algorithm step 4 (boundary mass-flux correction) on every velocity fill"""
         _check(load().yy_set_mass_fix(self.h, 1 if on else 0), "yy_set_mass_fix")
+
+    def set_mass_fix_params(self, eps, tol):
+        """epsilon of step 4's functional (0: the limit) and its flux trigger"""
+        _check(load().yy_set_mass_fix_params(self.h, float(eps), float(tol)), "yy_set_mass_fix_params")
 
     def set_pressure_exchange(self, nring):
         """Algorithm step 7: the outermost nring cells take the other

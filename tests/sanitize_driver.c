@@ -41,6 +41,7 @@ static int run(int nr, int nt, int np, double delta, int mode, int extras)
     }
     if (extras) {
         yyo_set_mass_fix(h, 1);
+        yyo_set_mass_fix_params(h, 1e-3, 0.0);
         yyo_set_pressure_exchange(h, 1);
         yyo_set_t_bc(h, 1, 1.0, 0.5);
         const int64_t nw = 2 * (int64_t)(nt + 2) * (np + 2);

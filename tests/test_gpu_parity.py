@@ -175,6 +175,28 @@ def test_mass_fix_parity(oracle_lib, yy):
         assert _rel(a, b) <= TOL, (I.FIELD_NAMES[f], _rel(a, b))
 
 
+@pytest.mark.parametrize("eps,tol", [(1e-3, 0.0), (1e-2, 0.0), (0.0, 1e3)])
+def test_mass_fix_finite_eps_and_trigger_parity(oracle_lib, yy, eps, tol):
+    """Algorithm step 4 with the paper's finite epsilon (the correction
+    shrinks to F / (eps |dOmega|^2 + a.a)) and with a flux trigger above the
+    imbalance (nothing corrected): one fill of random data in both stacks."""
+    print(f"case: mass fix eps {eps} tol {tol} 6x16x48", flush=True)
+    o, g = _pair(oracle_lib, yy, 6, 16, 48, t_inner=1.0, t_outer=0.3)
+    for sh in (o, g):
+        sh.set_mass_fix(True)
+        sh.set_mass_fix_params(eps, tol)
+    rng = np.random.default_rng(29)
+    _set_random(o, g, rng, [0])
+    o.fill(0)
+    g.fill(0)
+    for f in range(9):
+        a = g.get_field(f, 0, layout=1).cpu().numpy()
+        b = o.get_field(f, 0, layout=1)
+        assert _rel(a, b) <= 1e-13, I.FIELD_NAMES[f]
+    with pytest.raises(yy.YYError):
+        g.set_mass_fix_params(-1.0, 0.0)
+
+
 @pytest.mark.parametrize("field", [I.T, I.U1R, I.U1T, I.U1P, I.U2R, I.U2T, I.U2P])
 @pytest.mark.parametrize("d", [0, 1, 2])
 def test_sweep_parity(oracle_lib, yy, field, d):

@@ -342,6 +342,66 @@ def test_mass_flux_correction(oracle_lib):
             assert np.allclose(-dt_[1:-1, -1, 1:-1] / wu, kap.flat[0], rtol=1e-9, atol=0)
 
 
+def _boundary_area(g):
+    """|dOmega| of one patch: the r walls, the theta- and phi-boundary faces
+    (the face areas of the discrete divergence)"""
+    rc = g.r1 + (np.arange(g.nr) + 0.5) * g.dr
+    tc = g.th0 + (np.arange(g.nt) + 0.5) * g.dth
+    walls = (g.r1 ** 2 + g.r2 ** 2) * g.np * np.sum(np.sin(tc)) * g.dth * g.dph
+    sides = g.np * np.sum(rc) * g.dr * g.dph * (math.sin(g.th0) + math.sin(g.th0 + g.nt * g.dth))
+    ends = 2 * g.nt * np.sum(rc) * g.dr * g.dth
+    return walls + sides + ends
+
+
+def test_mass_flux_correction_finite_eps_and_trigger(oracle_lib):
+    """Algorithm step 4 with the paper's finite epsilon: the corrected data
+    v make the gradient of J(v) = |v - u_bd|^2/2 + (F(v) + F_r)^2 /
+    (2 eps |dOmega|^2) vanish, i.e. v - u_bd = -(F(v) + F_r)/(eps |dOmega|^2)
+    times the outward flux weights, checked from the net flux left after
+    the correction (so not from the oracle's own formula); the flux left
+    falls as eps does.  With a trigger above the imbalance nothing moves."""
+    y = oracle_lib
+    g = I.Grid(8, 24, 72, 1.0, 2.0)
+    area = _boundary_area(g)
+    rng = np.random.default_rng(12)
+    data = {f: rng.uniform(-1, 1, g.mac_shape(f)) for f in range(9)}
+
+    def filled(eps, tol, on=True):
+        sh = y.Shell(g.nr, g.nt, g.np, g.r1, g.r2)
+        sh.set_params(pr=1.0, ra=1.0, tau=1e-3, chi=1.0)
+        for f in range(9):
+            sh.set_field(f, y.LEV_N, data[f])
+        _paper_walls(y, sh, g, y.LEV_N, 0.3)
+        sh.set_mass_fix(on)
+        sh.set_mass_fix_params(eps, tol)
+        sh.fill(y.LEV_N)
+        return {f: sh.get_field(f, y.LEV_N, y.PADDED) for f in (I.U1R, I.U1T, I.U1P)}
+
+    before = filled(0.0, 0.0, on=False)
+    f0 = _net_flux(g, before[I.U1R], before[I.U1T], before[I.U1P])
+    assert max(abs(v) for v in f0) > 1e-6
+    rc = g.r1 + (np.arange(g.nr) + 0.5) * g.dr
+    wl = rc[:, None] * math.sin(g.th0) * g.dr * g.dph
+    left = []
+    for eps in (1e-2, 1e-3):
+        after = filled(eps, 0.0)
+        f1 = _net_flux(g, after[I.U1R], after[I.U1T], after[I.U1P])
+        left.append(max(abs(v) for v in f1))
+        for p in range(2):
+            kap = (after[I.U1T][p] - before[I.U1T][p])[1:-1, 1, 1:-1] / wl
+            assert np.allclose(kap, kap.flat[0], rtol=1e-9, atol=0)
+            # stationarity: kappa = (F(v) + F_r) / (eps |dOmega|^2)
+            assert abs(kap.flat[0] - f1[p] / (eps * area ** 2)) <= 1e-9 * abs(kap.flat[0]), (p, eps)
+            assert 0 < abs(f1[p]) < abs(f0[p])
+    assert left[1] < left[0]
+    # the trigger: |F| below tol leaves the interpolated data as they are
+    quiet = filled(1e-3, 10 * max(abs(v) for v in f0))
+    for f in quiet:
+        assert np.array_equal(quiet[f], before[f])
+    with pytest.raises(ValueError):
+        y.Shell(4, 12, 36).set_mass_fix_params(-1.0, 0.0)
+
+
 def test_residual_graddiv_terms(oracle_lib):
     """With a non-solenoidal velocity the grad-div blocks D_ij/(2 chi), the
     Gauss-Seidel splitting and the div-dependent viscous terms are O(1);
