@@ -314,7 +314,9 @@ int yy_residual(yy_shell *s, int32_t field, void *dev_out, hipStream_t stream);
  * (unknown or "D", direction); then the column tile of each residual
  * (keys "res.T", "res.u_r", "res.u_t", "res.u_p": a 256-thread block of
  * k x j columns, "64x4", "128x2", "256x1", "32x8" or "16x16", taken by
- * consecutive blocks k-tile first, "k", or j-tile first, "j"), and
+ * consecutive blocks k-tile first, "k", or j-tile first, "j"; or 64 x 4,
+ * 8 or 16 columns with the theta/phi neighbours staged in LDS, "lds64x4k",
+ * "lds64x8k", "lds64x8j", "lds64x16k"), and
  * write the choices as a JSON object (a NUL-terminated string of at most
  * cap bytes) to json_out if not NULL.
  * Synchronises the stream.  Needs params.  Errors: YY_ERR_ARG,
@@ -326,7 +328,12 @@ int yy_autotune(yy_shell *s, char *json_out, int32_t cap, hipStream_t stream);
 int yy_get_tuning(yy_shell *s, char *json_out, int32_t cap);
 
 /* Apply choices written by yy_autotune (a tuning cache).  Unknown keys are
- * ignored.  Errors: YY_ERR_ARG (NULL or malformed). */
+ * ignored.  Optional keys "res.<unknown>.seg":"<n>" (n = 0..64) split each
+ * residual column's radial points into n segments run by separate blocks
+ * (0, the default: the count that best fills the device's last round of
+ * resident blocks, at most 4); every count gives bitwise the same residual.
+ * yy_get_tuning writes them only where n > 0.  Errors: YY_ERR_ARG (NULL or
+ * malformed). */
 int yy_set_tuning(yy_shell *s, const char *json);
 
 /* ---- ensembles: many independent shells advanced by one graph ---- */

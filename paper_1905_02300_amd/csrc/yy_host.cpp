@@ -820,6 +820,9 @@ int yy_create(const yy_grid *g, int32_t prec, void *dev_ws, uint64_t ws_bytes, y
     s->L = L;
     s->F = F;
     s->ws = (char *)dev_ws;
+    // occupancy queries of the launchers, here rather than under a capture
+    if (prec == YY_FP64) Ops<double>::prepare();
+    else Ops<float>::prepare();
     // zero the whole workspace (fields start at zero)
     zero_doubles((double *)s->ws, L.total / 8, nullptr);
     // tables
@@ -1485,6 +1488,11 @@ static std::string tuning_json(yy_shell *s)
         js += "\":\"";
         js += RES_TILES[T.rt[L] >= 0 && T.rt[L] < N_RES_TILES ? T.rt[L] : 0].name;
         js += "\"";
+        if (T.rseg[L] > 0) {
+            char val[48];
+            std::snprintf(val, sizeof val, ",\"res.%s.seg\":\"%d\"", tune_field_name[L], (int)T.rseg[L]);
+            js += val;
+        }
     }
     return js + "}";
 }
@@ -1549,6 +1557,17 @@ extern "C" int yy_set_tuning(yy_shell *s, const char *json)
             if (v == RES_TILES[t].name) found = t;
         if (found < 0) return YY_ERR_ARG;
         T.rt[L] = (int8_t)found;
+    }
+    // radial segments of the residual columns: "0" = from the occupancy
+    for (int L = 0; L < 4; L++) {
+        const std::string key = std::string("\"res.") + tune_field_name[L] + ".seg\":\"";
+        const size_t at = js.find(key);
+        if (at == std::string::npos) continue;
+        int n = -1, used = 0;
+        if (std::sscanf(js.c_str() + at + key.size(), "%d%n", &n, &used) != 1 || n < 0 || n > 64 ||
+            js[at + key.size() + used] != '"')
+            return YY_ERR_ARG;
+        T.rseg[L] = (int8_t)n;
     }
     s->version++;
     return YY_OK;

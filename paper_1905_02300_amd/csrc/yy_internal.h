@@ -142,6 +142,7 @@ struct FillVector {
 struct Tune {
     int8_t m[5][2], w[5][2], bl[5][2], lpb[5], wpl[5];   // [4]: the diffusion-only line solves
     int8_t rt[4];            // residual column tile per location (index into RES_TILES)
+    int8_t rseg[4];          // radial segments per residual column (0: chosen from the occupancy)
 };
 
 // Column tiles of the residual kernels: (k extent, j extent) of a block
@@ -228,6 +229,9 @@ LaunchRecorder *launch_recorder();
 
 // ---- launchers (yy_kernels.hip) ----
 template <typename R> struct Ops {
+    // host queries the launchers use (the residuals' resident blocks per
+    // device); once per process, outside any stream capture
+    static void prepare();
     static void extrap(const Dims &d, const State<R> &s, hipStream_t st);
     // extrap, and the working level k = level n (fields and pressures)
     static void extrap_copy(const Dims &d, const State<R> &s, hipStream_t st);

@@ -892,8 +892,20 @@ __device__ __forceinline__ R res_point(const Geo<R> &g, int i, int j, const ResN
     return g.tau * Rv;
 }
 
+// nseg: each column's radial points are split into nseg segments of
+// ceil((nr - i0) / nseg) points, one block per (segment, column tile), so
+// that the block count fills the last round of resident blocks; ntile:
+// column tiles per patch.  Virtual block x = segment * ntile + tile.
 template <typename R>
-struct ResArgs { Dims d; Geo<R> g; State<R> s; RhsIn<R> in; R *out; int jfast; };
+struct ResArgs { Dims d; Geo<R> g; State<R> s; RhsIn<R> in; R *out; int jfast, nseg, ntile; };
+
+// radial range [is, ie) of segment seg of a column starting at i0
+__device__ __forceinline__ void res_segment(int i0, int nr, int nseg, int seg, int &is, int &ie)
+{
+    const int len = (nr - i0 + nseg - 1) / nseg;
+    is = i0 + seg * len;
+    ie = min(nr, is + len);
+}
 
 // the arrays a residual reads, as 32-bit-indexed views
 template <typename R> struct ResSrc {
@@ -995,15 +1007,18 @@ template <typename R, int L> struct KResidual {
         const int p = d.p0 + (int)blk.y;
         const int j0 = ulo<L>(1), k0 = ulo<L>(2), i0 = ulo<L>(0);
         const int nj = d.nt - j0;
-        int j, k;
-        if (!col_of_t(blk.x, nj, d.np, j0, k0, a.jfast, j, k)) return;
+        int j, k, is, ie;
+        const unsigned seg = blk.x / (unsigned)a.ntile;
+        res_segment(i0, d.nr, a.nseg, (int)seg, is, ie);
+        if (is >= ie) return;
+        if (!col_of_t(blk.x - seg * (unsigned)a.ntile, nj, d.np, j0, k0, a.jfast, j, k)) return;
         // 32-bit element indices (each field is below 4 GiB: checked on the host)
         const uint32_t sI = (uint32_t)d.sI, sJ = (uint32_t)d.sJ;
         const ResSrc<R> src(a);
-        uint32_t q = (uint32_t)ix(d, p, i0, j, k);
+        uint32_t q = (uint32_t)ix(d, p, is, j, k);
         Col<R> w;
-        src.template prime<L>(g, i0, q, sI, sJ, w);
-        for (int i = i0; i < d.nr; i++, q += sI) {
+        src.template prime<L>(g, is, q, sI, sJ, w);
+        for (int i = is; i < ie; i++, q += sI) {
             ResNb<R> n;
             src.template own<L>(q, sI, n);
             src.template nbrs<L>(q, sI, sJ, n);
@@ -1109,8 +1124,13 @@ template <typename R, int L, int CJ> struct KResidualLds {
         const int j0 = ulo<L>(1), k0 = ulo<L>(2), i0 = ulo<L>(0);
         const int nj = d.nt - j0;
         const unsigned ntk = (unsigned)((d.np + 63) / 64), ntj = (unsigned)((nj + CJ - 1) / CJ);
-        const int tk = (int)(a.jfast ? blk.x / ntj : blk.x % ntk);
-        const int tj = (int)(a.jfast ? blk.x % ntj : blk.x / ntk);
+        // segment (block-uniform, so the early exit keeps every barrier whole)
+        const unsigned seg = blk.x / (ntk * ntj), bt = blk.x - seg * (ntk * ntj);
+        int is, ie;
+        res_segment(i0, d.nr, a.nseg, (int)seg, is, ie);
+        if (is >= ie) return;
+        const int tk = (int)(a.jfast ? bt / ntj : bt % ntk);
+        const int tj = (int)(a.jfast ? bt % ntj : bt / ntk);
         const int kt0 = tk * 64, jt0 = j0 + tj * CJ;
         const int x = (int)threadIdx.x, y = (int)threadIdx.y, t = x + 64 * y;
         const int j = jt0 + y, k = kt0 + x;
@@ -1176,13 +1196,13 @@ template <typename R, int L, int CJ> struct KResidualLds {
             if (L == FP) owa = src.wp[ql + lev];
         };
         Col<R> w;
-        uint32_t q = ql;
-        if (active) src.template prime<L>(g, i0, q, sI, sJ, w);
-        uint32_t lev = 0;                    // (i - i0) sI
+        uint32_t lev = (uint32_t)(is - i0) * sI;   // (i - i0) sI
+        uint32_t q = ql + lev;
+        if (active) src.template prime<L>(g, is, q, sI, sJ, w);
         fetch(lev, true);
         const int me = (y + 1) * W + (x + 1);
-        for (int i = i0; i < d.nr; i++, q += sI) {
-            if (i > i0) __syncthreads();
+        for (int i = is; i < ie; i++, q += sI) {
+            if (i > is) __syncthreads();
 #pragma unroll
             for (int c = 0; c < NPL; c++) {
                 pl[c][me] = ov[c];
@@ -1205,7 +1225,7 @@ template <typename R, int L, int CJ> struct KResidualLds {
             if (L == FT) n.t0 = owa;
             if (L == FP) n.p0 = owa;
             lev += sI;
-            fetch(lev, i + 1 < d.nr);
+            fetch(lev, i + 1 < ie);
             n.bp = ov[0];
             __syncthreads();
             if (active) {
@@ -2289,6 +2309,71 @@ void Ops<R>::sweep(const Dims &d, const Geo<R> &g, const Geo<double> &gd, const 
 #undef YY_SW
 }
 
+// Resident blocks of a residual kernel on the whole device (blocks per CU
+// from its registers and LDS, times the CU count), per location and tile
+// kind (0..2: LDS tiles of 4, 8, 16 rows; 3: memory-read, 256 threads);
+// 0 until prepare() has run, which then leaves every column whole.
+template <typename R> struct ResSlots { static int v[4][4]; };
+template <typename R> int ResSlots<R>::v[4][4] = {};
+
+template <class K> static int device_slots(int threads, int cus)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_single<K>, threads, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return nb * cus;
+}
+
+template <typename R, int L> static void res_slots_of(int cus)
+{
+    ResSlots<R>::v[L][0] = device_slots<KResidualLds<R, L, 4>>(256, cus);
+    ResSlots<R>::v[L][1] = device_slots<KResidualLds<R, L, 8>>(512, cus);
+    ResSlots<R>::v[L][2] = device_slots<KResidualLds<R, L, 16>>(1024, cus);
+    ResSlots<R>::v[L][3] = device_slots<KResidual<R, L>>(256, cus);
+}
+
+template <typename R> void Ops<R>::prepare()
+{
+    static const bool once = [] {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        res_slots_of<R, CC>(cus);
+        res_slots_of<R, FR>(cus);
+        res_slots_of<R, FT>(cus);
+        res_slots_of<R, FP>(cus);
+        return true;
+    }();
+    (void)once;
+}
+
+// Radial segments per column: blocks run in rounds of `slots`, and a last
+// round that is partly empty leaves CUs idle for a whole block time.  Cost
+// model: rounds x (points per segment + 2, the priming and pipeline fill of
+// a segment); the fewest segments of least cost, at most 4.  forced > 0
+// (tuning) overrides.
+static int res_segments(int forced, int64_t blocks, int ni, int slots)
+{
+    if (forced > 0) return forced < ni ? forced : (ni > 0 ? ni : 1);
+    if (slots <= 0 || ni < 8) return 1;
+    int best = 1;
+    double bc = 0.0;
+    for (int ns = 1; ns <= 4 && ns <= ni / 4; ns++) {
+        const int64_t rounds = (blocks * ns + slots - 1) / slots;
+        const double c = (double)rounds * ((ni + ns - 1) / ns + 2);
+        if (ns == 1 || c < bc) {
+            bc = c;
+            best = ns;
+        }
+    }
+    return best;
+}
+
 template <typename R, int L>
 void launch_res_lds(int cj, dim3 gr, dim3 bl, hipStream_t st, const ResArgs<R> &ra)
 {
@@ -2324,9 +2409,13 @@ void Ops<R>::residual(const Dims &d, const Geo<R> &g, const State<R> &s, int fie
     int ti = s.tune.rt[L];
     if (ti < 0 || ti >= N_RES_TILES) ti = 0;
     const ResTile &t = RES_TILES[ti];
-    const dim3 gr((unsigned)col_blocks_t(d.nt - j0, d.np, t), d.npatch), bl(t.ck, t.cj);
+    const int64_t ntile = col_blocks_t(d.nt - j0, d.np, t);
+    const int kind = t.lds ? (t.cj == 4 ? 0 : t.cj == 8 ? 1 : 2) : 3;
+    const int nseg = res_segments(s.tune.rseg[L], ntile * d.npatch, d.nr - (L == FR ? 1 : 0),
+                                  ResSlots<R>::v[L][kind]);
+    const dim3 gr((unsigned)(ntile * nseg), d.npatch), bl(t.ck, t.cj);
     const int jf = t.jfast;
-    const ResArgs<R> ra{d, g, s, in, out, jf};
+    const ResArgs<R> ra{d, g, s, in, out, jf, nseg, (int)ntile};
     if (t.lds) {
         if (L == CC) launch_res_lds<R, CC>(t.cj, gr, bl, st, ra);
         else if (L == FR) launch_res_lds<R, FR>(t.cj, gr, bl, st, ra);

@@ -5,6 +5,8 @@ Bar: FP64 relative error <= 1e-12 (max abs difference over max abs value of
 the oracle's field); the FP32-mixed step is compared with the FP64 step at
 its stated error.
 """
+import json
+
 import numpy as np
 import pytest
 
@@ -330,6 +332,51 @@ def test_residual_lds_tiles_bitwise(yy, prec):
     for tile in ["lds64x4k", "lds64x8k", "lds64x8j", "lds64x16k"]:
         for field in (I.T, I.U1R, I.U1T, I.U1P, I.U2R, I.U2T, I.U2P):
             assert torch.equal(outs[(tile, field)], outs[("64x4k", field)]), (tile, I.FIELD_NAMES[field])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_residual_radial_segments_bitwise(oracle_lib, yy, prec):
+    """Splitting each residual column's radial points over several blocks
+    (the segment's first block primes its radial windows from memory) gives
+    bitwise the residual of whole columns, for memory-read and LDS tiles,
+    with ragged segments (13 points, 12 for u_r, in 2 to 13 segments, with
+    empty trailing segments where ceil(n / segments) overshoots, and a count
+    above the points, which is clamped); the FP64 3-segment case also
+    matches the oracle."""
+    print(f"case: residual radial segments, prec {prec}", flush=True)
+    nr, nt, np_ = 13, 44, 170
+    o, g = _pair(oracle_lib, yy, nr, nt, np_, prec=prec, pr=0.8, ra=50.0, dt=0.02, chi=0.9)
+    rng = np.random.default_rng(302)
+    _set_random(o, g, rng, [0, 1, 2])
+    o.extrapolate()
+    g.extrapolate()
+    fields = (I.T, I.U1R, I.U1T, I.U1P, I.U2R, I.U2T, I.U2P)
+    for tile in ["64x4k", "lds64x4k", "lds64x8k"]:
+        outs = {}
+        for seg in (1, 2, 3, 5, 6, 13, 20):
+            js = ",".join('"res.%s":"%s","res.%s.seg":"%d"' % (u, tile, u, seg)
+                          for u in ("T", "u_r", "u_t", "u_p"))
+            g.set_tuning("{" + js + "}")
+            cur = json.loads(g.tuning_json())
+            assert cur["res.u_t.seg"] == str(seg)
+            for field in fields:
+                out = g.internal_tensor()
+                out.zero_()
+                g.residual(field, out)
+                outs[(seg, field)] = out.cpu()
+        for seg in (2, 3, 5, 6, 13, 20):
+            for field in fields:
+                assert torch.equal(outs[(seg, field)], outs[(1, field)]), (tile, seg, I.FIELD_NAMES[field])
+        if prec == 0:
+            for field in fields:
+                ref = 0.02 * o.residual(field)
+                got = g.from_internal(outs[(3, field)].to(out.device)).cpu().numpy()
+                m = _unknown_mask(o.padded_shape(), field)
+                assert _rel(got[m], ref[m]) <= TOL, (tile, I.FIELD_NAMES[field])
+    g.set_tuning('{"res.T.seg":"0","res.u_r.seg":"0","res.u_t.seg":"0","res.u_p.seg":"0"}')
+    assert "seg" not in g.tuning_json()
+    with pytest.raises(Exception):
+        g.set_tuning('{"res.T.seg":"x"}')
 
 
 def _mms_pair(oracle_lib, yy, nr, nt, np_, dt, prec=0, pr=1.0, ra=1e3, mode=0):
