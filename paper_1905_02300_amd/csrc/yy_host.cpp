@@ -2,6 +2,7 @@
 // metric and overlap-interpolation tables, workspace layout, and the
 // schedule of one time step (Sec. 4 Algorithm, additive Schwarz).
 #include <algorithm>
+#include <cctype>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1510,7 +1511,11 @@ extern "C" int yy_set_tuning(yy_shell *s, const char *json)
 {
     if (!s || !json) return YY_ERR_ARG;
     Tune &T = tune_of(s);
-    const std::string js(json);
+    // keys and values hold no blanks: drop every blank, so that JSON written
+    // with separators ", " and ": " matches like the compact form
+    std::string js;
+    for (const char *c = json; *c; c++)
+        if (!std::isspace((unsigned char)*c)) js += *c;
     for (int L = 0; L < 5; L++)
         for (int dir = 0; dir < 3; dir++) {
             char key[24];

@@ -810,7 +810,6 @@ def test_autotune_round_trip(yy):
     assert js.startswith("{") and '"u_t.t"' in js and '"T.p"' in js
     g.set_tuning(js)
     # the current tiles read back as the autotuner wrote them
-    import json
     assert json.loads(g.tuning_json()) == json.loads(js)
     with pytest.raises(yy.YYError):
         g.set_tuning('{"T.r":"m7w64"}')
@@ -821,3 +820,7 @@ def test_autotune_round_trip(yy):
         g.set_tuning('{"T.r":"m8w32x"}')
     with pytest.raises(yy.YYError):
         g.set_tuning('{"res.T":"lds64x2k"}')
+    # JSON with blanks (Python's default separators, newlines) reads alike
+    g.set_tuning(json.dumps({"T.r": "m6w16", "u_r.p": "v4", "res.u_r": "lds64x16k"}, indent=1))
+    cur = json.loads(g.tuning_json())
+    assert cur["T.r"] == "m6w16" and cur["u_r.p"] == "v4" and cur["res.u_r"] == "lds64x16k"
