@@ -2017,21 +2017,31 @@ template <typename R, int L, int MODE, int DIFF, int M> struct KContigMw {
             row = erow<R>(a[0], c[0], dd[0], ga, gc, gdv, nx ? sA[tid + 1] : R(0), nx ? sB[tid + 1] : R(0),
                           nx ? sC[tid + 1] : R(0));
         }
-        for (int h = 1; h < P; h <<= 1) {
-            __syncthreads();
+        // The levels alternate between two sets of row arrays, so a level
+        // needs one barrier: the odd levels (h = 1, 4, 16, ...) use the second
+        // rows of tdi and tup and the first two rows of tx, which the reads
+        // above do not touch, the even ones sA..sD; a thread writes a set
+        // again only after the next level's barrier, which every thread
+        // reaches after its reads of the level before.  (Each call site names
+        // its arrays, so they stay LDS addresses.)
+        auto level = [&](R *bA, R *bB, R *bC, R *bD, int h) {
             if (tid < P) {
-                sA[tid] = row.a;
-                sB[tid] = row.b;
-                sC[tid] = row.c;
-                sD[tid] = row.d;
+                bA[tid] = row.a;
+                bB[tid] = row.b;
+                bC[tid] = row.c;
+                bD[tid] = row.d;
             }
             __syncthreads();
             if (tid < P) {
                 Row4<R> rm = {R(0), R(1), R(0), R(0)}, rp = {R(0), R(1), R(0), R(0)};
-                if (tid - h >= 0) { rm.a = sA[tid - h]; rm.b = sB[tid - h]; rm.c = sC[tid - h]; rm.d = sD[tid - h]; }
-                if (tid + h < P) { rp.a = sA[tid + h]; rp.b = sB[tid + h]; rp.c = sC[tid + h]; rp.d = sD[tid + h]; }
+                if (tid - h >= 0) { rm.a = bA[tid - h]; rm.b = bB[tid - h]; rm.c = bC[tid - h]; rm.d = bD[tid - h]; }
+                if (tid + h < P) { rp.a = bA[tid + h]; rp.b = bB[tid + h]; rp.c = bC[tid + h]; rp.d = bD[tid + h]; }
                 row = pcr_level<R>(row, rm, rp);
             }
+        };
+        for (int h = 1; h < P; h <<= 2) {
+            level(tdi + ld, tup + ld, tx, tx + ld, h);
+            if (2 * h < P) level(sA, sB, sC, sD, 2 * h);
         }
         const R xe = tid < P ? row.d * recip(row.b) : R(0);
         __syncthreads();
