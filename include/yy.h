@@ -316,7 +316,10 @@ int yy_residual(yy_shell *s, int32_t field, void *dev_out, hipStream_t stream);
  * k x j columns, "64x4", "128x2", "256x1", "32x8" or "16x16", taken by
  * consecutive blocks k-tile first, "k", or j-tile first, "j"; or 64 x 4,
  * 8 or 16 columns with the theta/phi neighbours staged in LDS, "lds64x4k",
- * "lds64x8k", "lds64x8j", "lds64x16k"), and
+ * "lds64x8k", "lds64x8j", "lds64x16k"); each partitioned line solve
+ * is also timed with 1536 blocks per patch in place of the default 1024,
+ * each block looping over its lines or line tiles, and where that is
+ * faster the choice is written as "<unknown>.<dir>.blocks":"1536"), and
  * write the choices as a JSON object (a NUL-terminated string of at most
  * cap bytes) to json_out if not NULL.
  * Synchronises the stream.  Needs params.  Errors: YY_ERR_ARG,
@@ -332,8 +335,10 @@ int yy_get_tuning(yy_shell *s, char *json_out, int32_t cap);
  * residual column's radial points into n segments run by separate blocks
  * (0, the default: the count that best fills the device's last round of
  * resident blocks, at most 4); every count gives bitwise the same residual.
- * yy_get_tuning writes them only where n > 0.  Errors: YY_ERR_ARG (NULL or
- * malformed). */
+ * yy_get_tuning writes them only where n > 0.  Likewise optional keys
+ * "<unknown>.<dir>.blocks":"<n>" (n = 0 or 8..16384): blocks per patch of
+ * that partitioned line solve (0: the default, 1024).  Errors: YY_ERR_ARG
+ * (NULL or malformed). */
 int yy_set_tuning(yy_shell *s, const char *json);
 
 /* ---- ensembles: many independent shells advanced by one graph ---- */

@@ -1379,6 +1379,7 @@ extern "C" int yy_autotune(yy_shell *s, char *json_out, int32_t cap, hipStream_t
             char key[16];
             std::snprintf(key, sizeof key, "%s.%c", tune_field_name[L], dir_name[dir]);
             char val[32];
+            T.sb[L][dir] = 0;
             if (dir < 2) {
                 // the per-line Thomas kernel, then every partitioned tile
                 // that fits the lines
@@ -1428,6 +1429,21 @@ extern "C" int yy_autotune(yy_shell *s, char *json_out, int32_t cap, hipStream_t
             js += "\":\"";
             js += val;
             js += "\"";
+            // blocks per patch of the chosen partitioned solve: the default
+            // or 1.5 times it, whichever runs faster (both timed afresh)
+            T.sb[L][dir] = 0;
+            if (dir == 2 || T.m[L][dir] != 1) {
+                const double t0 = time_sweep(s, tune_field_id[L], dir, st, a, b);
+                T.sb[L][dir] = (int16_t)(SWEEP_BLOCKS * 3 / 2);
+                const double t1 = time_sweep(s, tune_field_id[L], dir, st, a, b);
+                if (t1 < t0) {
+                    char bv[64];
+                    std::snprintf(bv, sizeof bv, ",\"%s.blocks\":\"%d\"", key, (int)T.sb[L][dir]);
+                    js += bv;
+                } else {
+                    T.sb[L][dir] = 0;
+                }
+            }
         }
     }
     // column tiles of the residuals (one per unknown location)
@@ -1482,6 +1498,11 @@ static std::string tuning_json(yy_shell *s)
             js += "\":\"";
             js += val;
             js += "\"";
+            if (T.sb[L][dir] > 0) {
+                char bv[64];
+                std::snprintf(bv, sizeof bv, ",\"%s.blocks\":\"%d\"", key, (int)T.sb[L][dir]);
+                js += bv;
+            }
         }
     for (int L = 0; L < 4; L++) {
         js += ",\"res.";
@@ -1574,6 +1595,20 @@ extern "C" int yy_set_tuning(yy_shell *s, const char *json)
             return YY_ERR_ARG;
         T.rseg[L] = (int8_t)n;
     }
+    // blocks per patch of a partitioned line solve: "0" = the default
+    for (int L = 0; L < 5; L++)
+        for (int dir = 0; dir < 3; dir++) {
+            char key[32];
+            std::snprintf(key, sizeof key, "\"%s.%c.blocks\":\"", tune_field_name[L], dir_name[dir]);
+            const size_t at = js.find(key);
+            if (at == std::string::npos) continue;
+            const size_t v0 = at + std::strlen(key);
+            int n = -1, used = 0;
+            if (std::sscanf(js.c_str() + v0, "%d%n", &n, &used) != 1 || n < 0 || n > NBMAX ||
+                (n > 0 && n < 8) || js[v0 + used] != '"')
+                return YY_ERR_ARG;
+            T.sb[L][dir] = (int16_t)n;
+        }
     s->version++;
     return YY_OK;
 }
@@ -2079,6 +2114,7 @@ int yy_ensemble_autotune(yy_ensemble *e, char *json_out, int32_t cap, hipStream_
             for (size_t q = 0; q < n; q++) {
                 const Tune &src = tune_of(e->sh[rep[bk[q]]]);
                 Tune &dst = tune_of(e->sh[q]);
+                dst.sb[L][dir] = 0;      // ensembles keep the default block counts
                 if (dir < 2) {
                     dst.m[L][dir] = src.m[L][dir];
                     dst.w[L][dir] = src.w[L][dir];

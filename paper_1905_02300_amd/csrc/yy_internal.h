@@ -143,6 +143,7 @@ struct Tune {
     int8_t m[5][2], w[5][2], bl[5][2], lpb[5], wpl[5];   // [4]: the diffusion-only line solves
     int8_t rt[4];            // residual column tile per location (index into RES_TILES)
     int8_t rseg[4];          // radial segments per residual column (0: chosen from the occupancy)
+    int16_t sb[5][3];        // blocks per patch of each partitioned line solve (0: SWEEP_BLOCKS)
 };
 
 // Column tiles of the residual kernels: (k extent, j extent) of a block

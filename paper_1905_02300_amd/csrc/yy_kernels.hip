@@ -2162,7 +2162,8 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
         const int nother = D == 0 ? d.nt - j0 : d.nr - i0;
         int64_t tasks = (int64_t)sweep_ktiles(d.np, W) * nother;
         int64_t b = tasks;
-        if (b > SWEEP_BLOCKS) b = SWEEP_BLOCKS;
+        const int64_t cap = s.tune.sb[TL][D] > 0 ? s.tune.sb[TL][D] : SWEEP_BLOCKS;
+        if (b > cap) b = cap;
         if (nblocks) *nblocks = (int)b;
         const size_t lds = ((size_t)4 * P * W + (size_t)ntabs<L, D>() * n) * sizeof(R);
         const bool bl = s.tune.bl[TL][D] != 0;
@@ -2203,7 +2204,8 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
             }
             if (mcv <= 12 && Pv <= 64 * V) {
                 int64_t b = nlines;
-                if (b > SWEEP_BLOCKS) b = SWEEP_BLOCKS;
+                const int64_t cap = s.tune.sb[DIFF ? 4 : L][2] > 0 ? s.tune.sb[DIFF ? 4 : L][2] : SWEEP_BLOCKS;
+                if (b > cap) b = cap;
                 if (nblocks) *nblocks = (int)b;
                 const int ldv = contig_pitch(n, Pv, mcv, (int)sizeof(R));
                 const size_t lds = (size_t)4 * mcv * ldv * sizeof(R);
@@ -2226,7 +2228,8 @@ static bool launch_partitioned(const Dims &d, const Geo<R> &g, const Geo<double>
         const int want = s.tune.lpb[DIFF ? 4 : L];
         if ((want == 1 || want == 2 || want == 4) && want < lpb) lpb = want;
         int64_t b = (nlines + lpb - 1) / lpb;
-        if (b > SWEEP_BLOCKS) b = SWEEP_BLOCKS;
+        const int64_t cap = s.tune.sb[DIFF ? 4 : L][2] > 0 ? s.tune.sb[DIFF ? 4 : L][2] : SWEEP_BLOCKS;
+        if (b > cap) b = cap;
         if (nblocks) *nblocks = (int)b;
         const size_t lds = per_line * lpb;
         const dim3 grid((unsigned)b, d.npatch), block(64 * lpb);

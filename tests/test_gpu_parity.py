@@ -820,7 +820,45 @@ def test_autotune_round_trip(yy):
         g.set_tuning('{"T.r":"m8w32x"}')
     with pytest.raises(yy.YYError):
         g.set_tuning('{"res.T":"lds64x2k"}')
+    # blocks per patch of a partitioned line solve
+    g.set_tuning('{"u_r.r.blocks":"1536","T.p.blocks":"8"}')
+    cur = json.loads(g.tuning_json())
+    assert cur["u_r.r.blocks"] == "1536" and cur["T.p.blocks"] == "8"
+    g.set_tuning('{"u_r.r.blocks":"0","T.p.blocks":"0"}')
+    cur = json.loads(g.tuning_json())
+    assert "u_r.r.blocks" not in cur and "T.p.blocks" not in cur
+    for bad in ('{"u_r.r.blocks":"4"}', '{"u_r.r.blocks":"99999"}', '{"u_r.r.blocks":"x"}'):
+        with pytest.raises(yy.YYError):
+            g.set_tuning(bad)
     # JSON with blanks (Python's default separators, newlines) reads alike
     g.set_tuning(json.dumps({"T.r": "m6w16", "u_r.p": "v4", "res.u_r": "lds64x16k"}, indent=1))
     cur = json.loads(g.tuning_json())
     assert cur["T.r"] == "m6w16" and cur["u_r.p"] == "v4" and cur["res.u_r"] == "lds64x16k"
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_line_solve_block_counts_bitwise(yy, prec):
+    """Every line is solved by one block whatever the number of blocks per
+    patch, so the fields after whole steps are bitwise the same with 8
+    blocks per patch (each looping over many lines or line tiles), the
+    default, and 1536, in every direction of every unknown."""
+    print(f"case: line-solve block counts, prec {prec}", flush=True)
+    nr, nt, np_ = 12, 30, 90
+    grid = I.Grid(nr, nt, np_)
+    st = I.convection_state(grid, 1.0, 1e4, seed=7)
+    out = {}
+    for nb in (0, 8, 1536):
+        g = yy.Shell(nr, nt, np_, prec=prec)
+        g.set_params(pr=1.0, ra=1e4, dt=2e-4, chi=1.0, t_inner=1.0, t_outer=0.0)
+        for f in range(9):
+            g.set_field(f, 0, st[f])
+            if f not in (I.P1, I.P2):
+                g.set_field(f, 1, st[f])
+        keys = ",".join('"%s.%s.blocks":"%d"' % (u, d, nb) for u in ("T", "u_r", "u_t", "u_p") for d in "rtp")
+        g.set_tuning("{" + keys + "}")
+        for _ in range(2):
+            g.step(3)
+        out[nb] = [g.get_field(f).cpu() for f in range(9)]
+    for nb in (8, 1536):
+        for f in range(9):
+            assert torch.equal(out[nb][f], out[0][f]), (nb, I.FIELD_NAMES[f])
