@@ -317,9 +317,10 @@ int yy_residual(yy_shell *s, int32_t field, void *dev_out, hipStream_t stream);
  * consecutive blocks k-tile first, "k", or j-tile first, "j"; or 64 x 4,
  * 8 or 16 columns with the theta/phi neighbours staged in LDS, "lds64x4k",
  * "lds64x8k", "lds64x8j", "lds64x16k"); each partitioned line solve
- * is also timed with 1536 blocks per patch in place of the default 1024,
- * each block looping over its lines or line tiles, and where that is
- * faster the choice is written as "<unknown>.<dir>.blocks":"1536"), and
+ * is also timed with 1536 and 2048 blocks per patch in place of the
+ * default 1024, each block looping over its lines or line tiles, and where
+ * one is faster the choice is written as "<unknown>.<dir>.blocks":"<n>"),
+ * and
  * write the choices as a JSON object (a NUL-terminated string of at most
  * cap bytes) to json_out if not NULL.
  * Synchronises the stream.  Needs params.  Errors: YY_ERR_ARG,

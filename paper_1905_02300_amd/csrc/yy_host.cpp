@@ -1429,19 +1429,22 @@ extern "C" int yy_autotune(yy_shell *s, char *json_out, int32_t cap, hipStream_t
             js += "\":\"";
             js += val;
             js += "\"";
-            // blocks per patch of the chosen partitioned solve: the default
-            // or 1.5 times it, whichever runs faster (both timed afresh)
+            // blocks per patch of the chosen partitioned solve: the default,
+            // 1.5 or 2 times it, whichever runs fastest (all timed afresh)
             T.sb[L][dir] = 0;
             if (dir == 2 || T.m[L][dir] != 1) {
-                const double t0 = time_sweep(s, tune_field_id[L], dir, st, a, b);
-                T.sb[L][dir] = (int16_t)(SWEEP_BLOCKS * 3 / 2);
-                const double t1 = time_sweep(s, tune_field_id[L], dir, st, a, b);
-                if (t1 < t0) {
+                double tb = time_sweep(s, tune_field_id[L], dir, st, a, b);
+                int best_sb = 0;
+                for (const int nb : {SWEEP_BLOCKS * 3 / 2, SWEEP_BLOCKS * 2}) {
+                    T.sb[L][dir] = (int16_t)nb;
+                    const double t1 = time_sweep(s, tune_field_id[L], dir, st, a, b);
+                    if (t1 < tb) { tb = t1; best_sb = nb; }
+                }
+                T.sb[L][dir] = (int16_t)best_sb;
+                if (best_sb > 0) {
                     char bv[64];
-                    std::snprintf(bv, sizeof bv, ",\"%s.blocks\":\"%d\"", key, (int)T.sb[L][dir]);
+                    std::snprintf(bv, sizeof bv, ",\"%s.blocks\":\"%d\"", key, best_sb);
                     js += bv;
-                } else {
-                    T.sb[L][dir] = 0;
                 }
             }
         }
